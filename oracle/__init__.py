@@ -1,0 +1,175 @@
+"""CPU oracle for the leaf-first oct-tree build -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path
+(``paper_2312_06102_amd``) never imports it, and this package imports nothing
+from the product path.
+
+The C source ``tb_oracle.c`` is a sequential top-down Barnes-Hut insertion
+build (Sec. 2.1) over hashed Morton keys (Sec. 2.2) with direct FP64 moment
+sums per cell; see the header comment there for each step and its source.
+``build_library()`` compiles it with gcc into ``liboracle.so`` next to it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "tb_oracle.c")
+LIB = os.path.join(_HERE, "liboracle.so")
+
+# Strict IEEE FP64: no contraction into FMA, no fast-math reassociation.
+CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+MAX_DEPTH = 21
+
+_lib = None
+
+
+def build_library(src: str = SRC, out: str = LIB, extra_flags=()) -> str:
+    """Compile the oracle C source into a shared library (gcc)."""
+    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", out + ".tmp", src, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.tbo_keys.argtypes = [P, i64, P, ctypes.c_double, P, P]
+    lib.tbo_keys.restype = ctypes.c_int
+    lib.tbo_max_cells.argtypes = [i64, ctypes.c_int32]
+    lib.tbo_max_cells.restype = i64
+    lib.tbo_build.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double] + [P] * 11
+    lib.tbo_build.restype = ctypes.c_int
+    lib.tbo_cell_moments.argtypes = [P, P, P, ctypes.c_double, P, i64, i64,
+                                     ctypes.c_uint64, ctypes.c_int, P, P]
+    lib.tbo_cell_moments.restype = ctypes.c_int
+    lib.tbo_auto_box.argtypes = [P, i64, P, P]
+    lib.tbo_auto_box.restype = ctypes.c_int
+    return lib
+
+
+def load(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load the oracle library, compiling it first if it is not built yet."""
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build_library()
+        _lib = _bind(ctypes.CDLL(LIB))
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle returned error code {code}")
+        self.code = code
+
+
+def _box(lo, side):
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).reshape(3))
+    return lo, float(side)
+
+
+def keys(pos: np.ndarray, lo=(0.0, 0.0, 0.0), side: float = 1.0, lib=None):
+    """Quantised coordinates [N,3] (uint32) and 64-bit Morton keys [N] (uint64)."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    n = pos.shape[0]
+    lo, side = _box(lo, side)
+    q = np.empty((n, 3), dtype=np.uint32)
+    k = np.empty(n, dtype=np.uint64)
+    rc = lib.tbo_keys(_ptr(pos), n, _ptr(lo), side, _ptr(q), _ptr(k))
+    if rc:
+        raise OracleError(rc)
+    return q, k
+
+
+def max_cells(n: int, n_leaf: int, lib=None) -> int:
+    lib = lib or load()
+    return int(lib.tbo_max_cells(n, n_leaf))
+
+
+def build(pos: np.ndarray, mass: np.ndarray, n_leaf: int, lo=(0.0, 0.0, 0.0), side: float = 1.0,
+          moments: bool = True, lib=None) -> dict:
+    """Reference tree.  Returns a dict of numpy arrays trimmed to n_cells:
+    perm, dfs_perm, cell_key, cell_level, cell_first, cell_count, child_ptr [C,2],
+    com [C,4] (dx, dy, dz relative to the cell centre, M), quad [C,6]
+    (xx, xy, xz, yy, yz, zz), level_offset [23], n_cells."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+    n = pos.shape[0]
+    if mass.shape[0] != n:
+        raise ValueError("pos and mass lengths differ")
+    lo, side = _box(lo, side)
+    cmax = max(max_cells(n, n_leaf, lib), 1)
+    perm = np.empty(max(n, 1), dtype=np.int32)
+    dfs = np.empty(max(n, 1), dtype=np.int32)
+    key = np.empty(cmax, dtype=np.uint64)
+    level = np.empty(cmax, dtype=np.uint8)
+    first = np.empty(cmax, dtype=np.int32)
+    count = np.empty(cmax, dtype=np.int32)
+    child = np.empty((cmax, 2), dtype=np.int32)
+    com = np.empty((cmax, 4), dtype=np.float64) if moments else None
+    quad = np.empty((cmax, 6), dtype=np.float64) if moments else None
+    loff = np.zeros(23, dtype=np.int64)
+    nc = np.zeros(1, dtype=np.int64)
+    null = ctypes.c_void_p(0)
+    rc = lib.tbo_build(_ptr(pos), _ptr(mass), n, n_leaf, _ptr(lo), side, _ptr(perm), _ptr(dfs),
+                       _ptr(key), _ptr(level), _ptr(first), _ptr(count), _ptr(child),
+                       _ptr(com) if moments else null, _ptr(quad) if moments else null,
+                       _ptr(loff), _ptr(nc))
+    if rc:
+        raise OracleError(rc)
+    c = int(nc[0])
+    out = dict(perm=perm[:n], dfs_perm=dfs[:n], cell_key=key[:c], cell_level=level[:c],
+               cell_first=first[:c], cell_count=count[:c], child_ptr=child[:c],
+               level_offset=loff, n_cells=c)
+    if moments:
+        out["com"] = com[:c]
+        out["quad"] = quad[:c]
+    return out
+
+
+def cell_moments(pos, mass, perm, first: int, count: int, key: int, level: int,
+                 lo=(0.0, 0.0, 0.0), side: float = 1.0, lib=None):
+    """Moments of one cell from its particle range of ``perm`` (FP64, compensated)."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    lo, side = _box(lo, side)
+    com = np.empty(4, dtype=np.float64)
+    quad = np.empty(6, dtype=np.float64)
+    rc = lib.tbo_cell_moments(_ptr(pos), _ptr(mass), _ptr(lo), side, _ptr(perm), int(first),
+                              int(count), ctypes.c_uint64(int(key)), int(level), _ptr(com),
+                              _ptr(quad))
+    if rc:
+        raise OracleError(rc)
+    return com, quad
+
+
+def auto_box(pos, lib=None):
+    """Root box chosen from the data: (lo[3], side)."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    lo = np.empty(3, dtype=np.float64)
+    side = np.empty(1, dtype=np.float64)
+    rc = lib.tbo_auto_box(_ptr(pos), pos.shape[0], _ptr(lo), _ptr(side))
+    if rc:
+        raise OracleError(rc)
+    return lo, float(side[0])

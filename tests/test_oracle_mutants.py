@@ -1,0 +1,120 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case copies ``oracle/tb_oracle.c``, plants one mistake by text substitution
+(a swapped axis, an off-by-one split threshold, a wrong sign, a dropped term, a
+wrong bit index, a wrong tie order, a rounding instead of a floor), compiles the
+copy with gcc and runs the pin checks against it: at least one must fail, and
+all of them must pass on the unmodified source.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import treecheck as tc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+MUTANTS = {
+    "axis_order": ("k = (k << 1) | ((qx >> b) & 1u);\n    k = (k << 1) | ((qy >> b) & 1u);",
+                   "k = (k << 1) | ((qy >> b) & 1u);\n    k = (k << 1) | ((qx >> b) & 1u);"),
+    "split_threshold": ("if (t->v[node].cnt <= t->n_leaf ||", "if (t->v[node].cnt < t->n_leaf ||"),
+    "octant_bit": ("int b = TBO_MAX_DEPTH - 1 - level;", "int b = TBO_MAX_DEPTH - 2 - level;"),
+    "quad_sign": ("nsum_add(&s2[0], m * (3.0 * r[0] * r[0] - r2));",
+                  "nsum_add(&s2[0], m * (3.0 * r[0] * r[0] + r2));"),
+    "quad_offdiag": ("nsum_add(&s2[4], m * (3.0 * r[1] * r[2]));",
+                     "nsum_add(&s2[4], m * (3.0 * r[1] * r[0]));"),
+    "drop_centre": ("double r = ((double)pos[3 * (int64_t)p + a] - lo[a]) - off[a];",
+                    "double r = ((double)pos[3 * (int64_t)p + a] - lo[a]);"),
+    "quad_about_centre": ("- off[a]) - c[a];", "- off[a]);"),
+    "tie_order": ("return (x->idx > y->idx) - (x->idx < y->idx);\n}\n\nstatic const uint64_t",
+                  "return (x->idx < y->idx) - (x->idx > y->idx);\n}\n\nstatic const uint64_t"),
+    "round_not_floor": ("return (uint32_t)floor(t);", "return (uint32_t)floor(t + 0.5);"),
+    "centre_half": ("off[0] = ((double)ijk[0] + 0.5) * h;", "off[0] = ((double)ijk[0]) * h;"),
+    "depth_cap": ("#define TBO_MAX_DEPTH 21", "#define TBO_MAX_DEPTH 20"),
+}
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _pin_checks(lib):
+    """Run a compact set of the pins against ``lib``; return the names that fail."""
+    failures = []
+
+    def check(name, fn):
+        try:
+            fn()
+        except Exception:  # a failed pin, or the planted bug crashing the checker
+            failures.append(name)
+
+    def hand_keys():
+        rows = [ln.split() for ln in open(os.path.join(GOLDEN, "hand_keys.txt"))
+                if ln.strip() and not ln.startswith("#")]
+        pos = np.array([[float(r[0]), float(r[1]), float(r[2])] for r in rows], np.float32)
+        _, k = oracle.keys(pos, lib=lib)
+        assert np.array_equal(k, np.array([int(r[3]) for r in rows], np.uint64))
+
+    def set_definition():
+        rng = _rng(11)
+        base = rng.random((5, 3), dtype=np.float32)
+        for pos, nl in [(rng.random((120, 3), dtype=np.float32), 4),
+                        (np.repeat(base, [1, 2, 7, 9, 3], axis=0), 4)]:
+            t = oracle.build(pos, np.ones(pos.shape[0], np.float32), nl, moments=False, lib=lib)
+            g = tc.geometric_tree(pos, nl)
+            assert t["n_cells"] == len(g["cells"])
+            assert np.array_equal(t["perm"], g["perm"])
+            for c, cl in enumerate(g["cells"]):
+                assert int(t["cell_key"][c]) == cl["key"]
+                f, n = int(t["cell_first"][c]), int(t["cell_count"][c])
+                assert list(t["perm"][f:f + n]) == cl["members"]
+
+    def coincident():
+        pos = np.tile(np.array([[0.3, 0.7, 0.1]], np.float32), (40, 1))
+        t = oracle.build(pos, np.ones(40, np.float32), 8, lib=lib)
+        assert t["n_cells"] == 22 and np.all(t["cell_count"] == 40)
+
+    def exact_moments():
+        rng = _rng(201)
+        pos = rng.random((40, 3), dtype=np.float32)
+        mass = (rng.random(40) + 0.1).astype(np.float32)
+        t = oracle.build(pos, mass, 3, lib=lib)
+        for c in range(t["n_cells"]):
+            f, n = int(t["cell_first"][c]), int(t["cell_count"][c])
+            lv = int(t["cell_level"][c])
+            M, cx, qx = tc.exact_moments(pos, mass, list(t["perm"][f:f + n]), int(t["cell_key"][c]), lv)
+            l = 2.0 ** -lv
+            assert abs(t["com"][c, 3] - float(M)) <= 1e-15 * float(M)
+            assert max(abs(t["com"][c, a] - float(cx[a])) for a in range(3)) <= 1e-15 * l
+            assert max(abs(t["quad"][c, i] - float(qx[i])) for i in range(6)) <= 1e-14 * float(M) * l * l
+
+    check("hand_keys", hand_keys)
+    check("set_definition", set_definition)
+    check("coincident", coincident)
+    check("exact_moments", exact_moments)
+    return failures
+
+
+def _compile(tmp_path, name, src_text):
+    src = tmp_path / f"{name}.c"
+    src.write_text(src_text)
+    out = str(tmp_path / f"lib{name}.so")
+    oracle.build_library(str(src), out)
+    return oracle.load(out)
+
+
+def test_unmodified_oracle_passes_pins(tmp_path):
+    text = open(oracle.SRC).read()
+    lib = _compile(tmp_path, "original", text)
+    assert _pin_checks(lib) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    text = open(oracle.SRC).read()
+    assert text.count(old) == 1, f"mutation site for {name} not found exactly once"
+    lib = _compile(tmp_path, name, text.replace(old, new))
+    assert _pin_checks(lib), f"no pin caught the planted mistake {name}"
