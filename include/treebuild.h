@@ -1,0 +1,182 @@
+/*
+ * treebuild.h -- C ABI of the MI355X (gfx950) leaf-first oct-tree builder.
+ *
+ * The library builds the hashed oct-tree of Tokuue & Ishiyama (2023) on one GPU:
+ *
+ *   1. root box whose side is a power of two (Sec. 2.2);
+ *   2. one 64-bit Morton key per particle: each coordinate quantised in FP64 to a
+ *      21-bit integer, bits interleaved below a leading 1 (Sec. 2.2);
+ *   3. a stable sort of (key, index) pairs; the index payload is `perm`
+ *      (Sec. 2.3, steps ii-iii);
+ *   4. every leaf straight from the sorted keys, with the leaf depth
+ *      D_k = max(minDepth(k, k-1), minDepth(k, k+n_leaf)) of Sec. 2.3.1 and
+ *      Appendix A, evaluated for all particles at once;
+ *   5. the parents, one depth at a time from the deepest upwards, each created
+ *      by the first of its children in key order and linked to all of them
+ *      (Sec. 2.3.2, Algorithm 2);
+ *   6. monopole, centre of mass and traceless quadrupole of every cell, leaves
+ *      from their particles and parents from their children as soon as the
+ *      children are complete (Sec. 2.3.2 and its footnotes).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named "device" are HIP device memory (e.g. PyTorch CUDA tensors);
+ *   all of them are owned by the caller.  The library never allocates device
+ *   memory on the build path; scratch space is the caller's `workspace`.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Builds are asynchronous: outputs are valid once the caller synchronises
+ *   the stream.  A build performs no host/device synchronisation and no
+ *   hipMemsetAsync, so a whole build may be captured into a hipGraph.
+ * - Concurrent builds must use distinct workspaces and outputs.
+ * - Return codes: TB_OK (0) or a negative TB_ERR_* value.  Host-detectable
+ *   errors are returned synchronously before anything is launched.  Data errors
+ *   found by kernels (non-finite position, non-positive mass) are OR-ed into
+ *   the device status word `tb_tree.status` as bit flags; tb_build_sync() reads
+ *   it back and returns the matching code.
+ *
+ * Key and cell layout
+ * -------------------
+ * - q_a = floor(fl64(x_a - lo_a) * 2^21 / side), clamped to [0, 2^21 - 1].
+ *   Points outside the box are clamped into the edge cells.
+ * - key = 2^63 | sum_b (qx_b << (3b+2) | qy_b << (3b+1) | qz_b << 3b), i.e. each
+ *   3-bit octant digit is (x, y, z) with x most significant and 1 = upper half.
+ * - A depth-d cell key is the upper 3d+1 bits of its particles' keys; the root
+ *   key is 1.  Depths run from 0 to 21; a depth-21 leaf holds all particles
+ *   with one key and may therefore exceed n_leaf.
+ * - Cells are listed by (depth ascending, key ascending); cell 0 is the root.
+ *   Children of a cell are contiguous at the next depth.
+ * - Number of cells C <= C_max = N + 21 * floor(N / (n_leaf + 1)).
+ *
+ * Moment frames
+ * -------------
+ * - u = fl64(x - lo) is a particle's position in the box frame.  The centre of
+ *   a depth-d cell with integer coordinates (i, j, k) is
+ *   off = ((i, j, k) + 1/2) * side * 2^-d in that frame (exact).
+ * - com[c] = {dx, dy, dz, M}: (dx, dy, dz) = sum m (u - off) / M, the centre of
+ *   mass relative to the cell centre; M = sum m.
+ * - quad[c] = {xx, xy, xz, yy, yz, zz} of Q_ab = sum m (3 r_a r_b - |r|^2 d_ab),
+ *   r = u - off - (dx, dy, dz).  Q is traceless.
+ * - TB_FP64: com and quad are double.  TB_MIXED: they are float, accumulated in
+ *   FP32 with Kahan-compensated sums in cell-relative units; FP64 is used only
+ *   for the quantisation and the root box.
+ */
+#ifndef TREEBUILD_H
+#define TREEBUILD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TB_OK 0
+#define TB_ERR_ARG (-1)       /* bad size, n_leaf, flag or NULL required pointer */
+#define TB_ERR_BOX (-2)       /* side not a positive finite power of two, or lo not finite */
+#define TB_ERR_WORKSPACE (-3) /* workspace NULL or smaller than tb_workspace_bytes() */
+#define TB_ERR_HIP (-4)       /* a HIP runtime call failed */
+#define TB_ERR_NONFINITE (-5) /* a position is NaN or infinite (device-detected) */
+#define TB_ERR_MASS (-6)      /* a mass is not finite and positive (device-detected) */
+#define TB_ERR_INTERNAL (-7)  /* a kernel found an inconsistent intermediate (a library bug) */
+
+/* Bits of the device status word. */
+#define TB_STATUS_NONFINITE 1
+#define TB_STATUS_MASS 2
+#define TB_STATUS_INTERNAL 4 /* an index computed on the device fell out of range */
+
+/* Precision flags (bits 0..7). */
+#define TB_FP64 0u
+#define TB_MIXED 1u
+
+/* Optional radix-sort shape in flag bits 8..15: an index into the table that
+ * tb_sort_configs() lists; 0 is the default.  Every shape gives bit-identical
+ * results; only speed and workspace size differ. */
+#define TB_SORT_CONFIG(k) (((uint32_t)(k)&0xffu) << 8)
+
+#define TB_MAX_DEPTH 21
+#define TB_MAX_NLEAF 1024 /* largest supported n_leaf */
+#define TB_MAX_N 2147483647LL
+
+typedef struct {
+  double lo[3]; /* lower corner of the root cube */
+  double side;  /* edge length: a positive power of two */
+} tb_box;
+
+/* Output buffers, all caller-owned DEVICE memory unless noted.  C_max is the
+ * value returned by tb_max_cells(). */
+typedef struct {
+  int32_t *perm;         /* [N]        perm[s] = original index at sorted position s  */
+  uint64_t *cell_key;    /* [C_max]    hashed oct-tree key                              */
+  uint8_t *cell_level;   /* [C_max]    depth 0..21                                      */
+  int32_t *cell_first;   /* [C_max]    first sorted position of the cell's particles    */
+  int32_t *cell_count;   /* [C_max]    number of particles                              */
+  int32_t *child_ptr;    /* [C_max][2] {first child cell, number of children}; {-1,0} leaf */
+  void *com;             /* [C_max][4] double (TB_FP64) or float (TB_MIXED)              */
+  void *quad;            /* [C_max][6] double (TB_FP64) or float (TB_MIXED)              */
+  int64_t *level_offset; /* [23]       first cell of each depth; [22] = number of cells  */
+  int64_t *n_cells;      /* [1]        number of cells                                   */
+  int32_t *status;       /* [1]        OR of TB_STATUS_* bits; written by every build    */
+  double *box_out;       /* [4] or NULL  the box used: lo[3], side                      */
+  float *pos_sorted;     /* [N][3] or NULL  positions in sorted order (reorder, Sec. 2.3) */
+  float *mass_sorted;    /* [N] or NULL     masses in sorted order                       */
+  uint64_t *key_sorted;  /* [N] or NULL     particle keys in sorted order                */
+} tb_tree;
+
+/* C_max for N particles and leaf capacity n_leaf (0 for N = 0).
+ * Errors: TB_ERR_ARG for N < 0, N > TB_MAX_N, n_leaf outside [1, TB_MAX_NLEAF]
+ * or c_max == NULL. */
+int tb_max_cells(int64_t n, int32_t n_leaf, int64_t *c_max);
+
+/* Bytes of device workspace that tb_build() needs for these arguments.
+ * Errors: as tb_max_cells(), plus TB_ERR_ARG for unknown flags. */
+int tb_workspace_bytes(int64_t n, int32_t n_leaf, uint32_t flags, size_t *bytes);
+
+/* Build the tree of N particles (steps 1-6 above), asynchronously on `stream`.
+ *   pos   [N][3] float, device, AoS (x, y, z)
+ *   mass  [N]    float, device, finite and > 0
+ *   box   host pointer; NULL = choose it from the data: lo = per-axis minimum,
+ *         side = the smallest power of two strictly above the largest extent
+ *         (1 if every extent is 0), computed in FP64 on the device
+ *   flags TB_FP64 or TB_MIXED
+ *   workspace / ws_bytes  device scratch of at least tb_workspace_bytes()
+ *   out   host pointer to a tb_tree of device buffers (box_out, pos_sorted,
+ *         mass_sorted, key_sorted may be NULL; the others are required when N > 0;
+ *         level_offset, n_cells and status are required always)
+ * Errors (synchronous): TB_ERR_ARG, TB_ERR_BOX, TB_ERR_WORKSPACE, TB_ERR_HIP. */
+int tb_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, const tb_box *box,
+             uint32_t flags, void *workspace, size_t ws_bytes, const tb_tree *out, void *stream);
+
+/* tb_build() followed by a stream synchronisation and a read of the status
+ * word; returns TB_ERR_NONFINITE or TB_ERR_MASS if the kernels flagged bad data. */
+int tb_build_sync(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                  const tb_box *box, uint32_t flags, void *workspace, size_t ws_bytes,
+                  const tb_tree *out, void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Kernel timing.  When enabled, every kernel launch of a build is bracketed by
+ * HIP events recorded on the build's stream; the per-kernel durations are
+ * summed when tb_trace_read() is called (which synchronises on the events).
+ * Tracing is process-wide and not thread-safe; it is meant for benchmarks.   */
+typedef struct {
+  char name[48];     /* kernel name */
+  int64_t launches;  /* number of launches recorded */
+  double total_ms;   /* summed event-to-event duration */
+} tb_trace_entry;
+
+int tb_trace_enable(int on);
+/* Copy up to `cap` entries into `out` and set *count; resets the accumulators. */
+int tb_trace_read(tb_trace_entry *out, int cap, int *count);
+
+/* The selectable radix-sort shapes: desc[3k..3k+2] = {digit bits, keys per
+ * thread, threads per workgroup} of TB_SORT_CONFIG(k).  With cap = 0 only
+ * *count (the table size) is written. */
+int tb_sort_configs(int32_t *desc, int cap, int *count);
+
+/* Library version string, e.g. "treebuild 0.1 gfx950". */
+const char *tb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TREEBUILD_H */

@@ -1,0 +1,292 @@
+// tb_api.cpp -- the C ABI of include/treebuild.h: argument checks, workspace
+// plan, the fixed launch sequence of one build, and kernel timing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "tb_internal.h"
+
+namespace tb {
+
+bool sort_config_supported(const SortConfig &c);
+size_t cell_emit_lds(int nl);
+
+// Table of sort shapes selectable through TB_SORT_CONFIG(k); entry 0 is the default.
+static const SortConfig kSortTable[] = {
+    {8, 16, 256}, {9, 16, 256}, {8, 12, 256}, {9, 12, 256},
+    {8, 8, 512},  {10, 16, 256}, {11, 16, 256},
+};
+static const int kSortTableSize = (int)(sizeof(kSortTable) / sizeof(kSortTable[0]));
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+SortConfig default_sort_config(int64_t) { return kSortTable[0]; }
+
+static int64_t max_cells(int64_t n, int32_t n_leaf) {
+  if (n <= 0) return 0;
+  return n + (int64_t)kMaxDepth * (n / ((int64_t)n_leaf + 1));
+}
+
+int make_plan(int64_t n, int32_t n_leaf, uint32_t flags, const SortConfig &sc, Plan *p) {
+  std::memset(p, 0, sizeof(*p));
+  p->n = n;
+  p->n_leaf = n_leaf;
+  p->flags = flags;
+  p->sort = sc;
+  p->sort_tiles = (n + sc.tile() - 1) / sc.tile();
+  p->cell_tiles = (n + kCellTile - 1) / kCellTile;
+  p->c_max = max_cells(n, n_leaf);
+  const int P = sc.passes(), R = sc.radix();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + (bytes ? bytes : 1));
+    return o;
+  };
+  p->keys0 = take(8 * (size_t)n);
+  p->keys1 = take(8 * (size_t)n);
+  p->vals1 = take(4 * (size_t)n);
+  p->hist = take(4 * (size_t)P * R);
+  p->hist_part = take(4 * (size_t)keygen_blocks(n) * P * R);
+  p->status0 = take(8 * (size_t)p->sort_tiles * R);
+  p->status1 = take(8 * (size_t)p->sort_tiles * R);
+  p->counters = take(4 * 64);
+  p->box = take(8 * 4);
+  p->bbox_part = take(8 * 6 * (size_t)kBboxBlocks);
+  p->cell_status = take(8 * (size_t)p->cell_tiles * kLevels);
+  p->cell_incl = take(4 * (size_t)p->cell_tiles * kLevels);
+  p->total = off;
+  return TB_OK;
+}
+
+Work carve(const Plan &p, void *base) {
+  unsigned char *b = static_cast<unsigned char *>(base);
+  Work w;
+  w.keys0 = reinterpret_cast<uint64_t *>(b + p.keys0);
+  w.keys1 = reinterpret_cast<uint64_t *>(b + p.keys1);
+  w.vals1 = reinterpret_cast<uint32_t *>(b + p.vals1);
+  w.hist = reinterpret_cast<uint32_t *>(b + p.hist);
+  w.hist_part = reinterpret_cast<uint32_t *>(b + p.hist_part);
+  w.status0 = reinterpret_cast<uint64_t *>(b + p.status0);
+  w.status1 = reinterpret_cast<uint64_t *>(b + p.status1);
+  w.counters = reinterpret_cast<uint32_t *>(b + p.counters);
+  w.box = reinterpret_cast<double *>(b + p.box);
+  w.bbox_part = reinterpret_cast<double *>(b + p.bbox_part);
+  w.cell_status = reinterpret_cast<uint64_t *>(b + p.cell_status);
+  w.cell_incl = reinterpret_cast<uint32_t *>(b + p.cell_incl);
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+struct TraceRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+struct TraceAcc {
+  int64_t launches = 0;
+  double ms = 0.0;
+};
+static bool g_trace = false;
+static std::vector<TraceRec> g_pending;
+static std::map<std::string, TraceAcc> g_acc;
+
+template <class F>
+static hipError_t traced(const char *name, hipStream_t s, F &&f) {
+  if (!g_trace) return f();
+  TraceRec r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return hipErrorOutOfMemory;
+  (void)hipEventRecord(r.a, s);
+  const hipError_t e = f();
+  (void)hipEventRecord(r.b, s);
+  g_pending.push_back(r);
+  return e;
+}
+
+static int flush_trace() {
+  for (auto &r : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      TraceAcc &acc = g_acc[r.name];
+      acc.launches += 1;
+      acc.ms += ms;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_pending.clear();
+  return TB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+static bool is_pow2(double side) {
+  if (!(side > 0.0) || !std::isfinite(side)) return false;
+  int e;
+  return std::frexp(side, &e) == 0.5;
+}
+
+static int check_sizes(int64_t n, int32_t n_leaf) {
+  if (n < 0 || n > TB_MAX_N) return TB_ERR_ARG;
+  if (n_leaf < 1 || n_leaf > TB_MAX_NLEAF) return TB_ERR_ARG;
+  if (max_cells(n, n_leaf) > 2147483647LL) return TB_ERR_ARG;  // child_ptr is int32
+  return TB_OK;
+}
+
+static int config_from_flags(uint32_t flags, SortConfig *sc) {
+  const uint32_t prec = flags & 0xffu;
+  if (prec != TB_FP64 && prec != TB_MIXED) return TB_ERR_ARG;
+  if (flags & ~0xffffu) return TB_ERR_ARG;
+  const int k = (int)((flags >> 8) & 0xffu);
+  if (k >= kSortTableSize) return TB_ERR_ARG;
+  *sc = kSortTable[k];
+  return sort_config_supported(*sc) ? TB_OK : TB_ERR_ARG;
+}
+
+static int build_impl(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                      const tb_box *box, uint32_t flags, void *workspace, size_t ws_bytes,
+                      const tb_tree *out, hipStream_t s) {
+  int rc = check_sizes(n, n_leaf);
+  if (rc) return rc;
+  SortConfig sc;
+  rc = config_from_flags(flags, &sc);
+  if (rc) return rc;
+  if (!out || !out->level_offset || !out->n_cells || !out->status) return TB_ERR_ARG;
+  if (box) {
+    if (!std::isfinite(box->lo[0]) || !std::isfinite(box->lo[1]) || !std::isfinite(box->lo[2]) ||
+        !is_pow2(box->side))
+      return TB_ERR_BOX;
+  }
+  if (n == 0) {
+    return traced("empty", s, [&] { return launch_empty(*out, box, s); }) == hipSuccess
+               ? TB_OK
+               : TB_ERR_HIP;
+  }
+  if (!pos || !mass || !out->perm || !out->cell_key || !out->cell_level || !out->cell_first ||
+      !out->cell_count || !out->child_ptr || !out->com || !out->quad)
+    return TB_ERR_ARG;
+  if ((flags & 0xffu) == TB_MIXED) return TB_ERR_ARG;  // not available yet
+  Plan p;
+  make_plan(n, n_leaf, flags, sc, &p);
+  if (!workspace || ws_bytes < p.total) return TB_ERR_WORKSPACE;
+  const Work w = carve(p, workspace);
+
+  hipError_t e = hipSuccess;
+  auto run = [&](const char *name, auto &&f) {
+    if (e == hipSuccess) e = traced(name, s, f);
+  };
+  run("init", [&] { return launch_init(p, w, box, *out, s); });
+  if (!box) run("bbox", [&] { return launch_bbox(p, w, pos, s); });
+  run("keygen", [&] { return launch_keygen(p, w, pos, *out, s); });
+  run("hist_reduce", [&] { return launch_hist_reduce(p, w, s); });
+  for (int pass = 0; pass < p.sort.passes(); ++pass)
+    run("sort_pass", [&] { return launch_sort_pass(p, w, pass, *out, s); });
+  run("cell_count", [&] { return launch_cell_count(p, w, out->status, s); });
+  run("cell_emit", [&] { return launch_cell_emit(p, w, pos, mass, *out, s); });
+  for (int d = kMaxDepth - 1; d >= 0; --d)
+    run("parents", [&] { return launch_parents(p, w, d, *out, s); });
+  if (out->key_sorted)
+    run("copy_keys", [&] {
+      return hipMemcpyAsync(out->key_sorted, sorted_keys(p, w), 8 * (size_t)n,
+                            hipMemcpyDeviceToDevice, s);
+    });
+  return e == hipSuccess ? TB_OK : TB_ERR_HIP;
+}
+
+}  // namespace tb
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int tb_max_cells(int64_t n, int32_t n_leaf, int64_t *c_max) {
+  if (!c_max) return TB_ERR_ARG;
+  const int rc = tb::check_sizes(n, n_leaf);
+  if (rc) return rc;
+  *c_max = tb::max_cells(n, n_leaf);
+  return TB_OK;
+}
+
+int tb_workspace_bytes(int64_t n, int32_t n_leaf, uint32_t flags, size_t *bytes) {
+  if (!bytes) return TB_ERR_ARG;
+  int rc = tb::check_sizes(n, n_leaf);
+  if (rc) return rc;
+  tb::SortConfig sc;
+  rc = tb::config_from_flags(flags, &sc);
+  if (rc) return rc;
+  if (n == 0) {
+    *bytes = 0;
+    return TB_OK;
+  }
+  tb::Plan p;
+  tb::make_plan(n, n_leaf, flags, sc, &p);
+  *bytes = p.total;
+  return TB_OK;
+}
+
+int tb_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, const tb_box *box,
+             uint32_t flags, void *workspace, size_t ws_bytes, const tb_tree *out, void *stream) {
+  return tb::build_impl(pos, mass, n, n_leaf, box, flags, workspace, ws_bytes, out,
+                        static_cast<hipStream_t>(stream));
+}
+
+int tb_build_sync(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                  const tb_box *box, uint32_t flags, void *workspace, size_t ws_bytes,
+                  const tb_tree *out, void *stream) {
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = tb::build_impl(pos, mass, n, n_leaf, box, flags, workspace, ws_bytes, out, s);
+  if (rc) return rc;
+  int32_t status = 0;
+  if (hipMemcpyAsync(&status, out->status, sizeof(status), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return TB_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TB_ERR_HIP;
+  if (status & TB_STATUS_NONFINITE) return TB_ERR_NONFINITE;
+  if (status & TB_STATUS_MASS) return TB_ERR_MASS;
+  if (status & TB_STATUS_INTERNAL) return TB_ERR_INTERNAL;
+  return TB_OK;
+}
+
+int tb_trace_enable(int on) {
+  tb::g_trace = on != 0;
+  return TB_OK;
+}
+
+int tb_trace_read(tb_trace_entry *out, int cap, int *count) {
+  if (!count || (cap > 0 && !out)) return TB_ERR_ARG;
+  tb::flush_trace();
+  int k = 0;
+  for (const auto &kv : tb::g_acc) {
+    if (k < cap) {
+      std::memset(&out[k], 0, sizeof(out[k]));
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", kv.first.c_str());
+      out[k].launches = kv.second.launches;
+      out[k].total_ms = kv.second.ms;
+    }
+    ++k;
+  }
+  *count = k < cap ? k : cap;
+  tb::g_acc.clear();
+  return TB_OK;
+}
+
+int tb_sort_configs(int32_t *desc, int cap, int *count) {
+  if (!count || (cap > 0 && !desc)) return TB_ERR_ARG;
+  int k = 0;
+  for (; k < tb::kSortTableSize && k < cap; ++k) {
+    desc[3 * k + 0] = tb::kSortTable[k].bits;
+    desc[3 * k + 1] = tb::kSortTable[k].ipt;
+    desc[3 * k + 2] = tb::kSortTable[k].threads;
+  }
+  *count = cap > 0 ? k : tb::kSortTableSize;
+  return TB_OK;
+}
+
+const char *tb_version(void) { return "treebuild 0.1 gfx950"; }
+
+}  // extern "C"

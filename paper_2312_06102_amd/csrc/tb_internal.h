@@ -1,0 +1,177 @@
+// tb_internal.h -- shared definitions of the gfx950 tree-build kernels.
+//
+// Internal to the library: kernels, launch wrappers, the workspace plan and a
+// few wave64 helpers.  The public C ABI is include/treebuild.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "treebuild.h"
+
+namespace tb {
+
+// ---------------------------------------------------------------------------
+// Fixed configuration
+// ---------------------------------------------------------------------------
+constexpr int kMaxDepth = TB_MAX_DEPTH;  // deepest cell (21 bits per axis)
+constexpr int kLevels = kMaxDepth + 1;   // depths 0..21
+constexpr int kLevelWords = (kLevels + 1) / 2;  // 16-bit level counters packed in u32
+
+// Cell kernels: one tile of particles per workgroup.
+constexpr int kCellThreads = 256;
+constexpr int kCellIpt = 8;
+constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
+
+// Parent kernel
+constexpr int kParentThreads = 256;
+
+// Lookback status word: flag in bits 63:62, value in bits 31:0.
+constexpr uint64_t kFlagAggregate = 1ull << 62;
+constexpr uint64_t kFlagInclusive = 2ull << 62;
+constexpr uint64_t kFlagMask = 3ull << 62;
+
+// Sort configuration chosen for one build (radix digit width and tile shape).
+struct SortConfig {
+  int bits;     // radix digit width, 8..11
+  int ipt;      // keys per thread
+  int threads;  // threads per workgroup
+  int tile() const { return ipt * threads; }
+  int radix() const { return 1 << bits; }
+  int passes() const { return (63 + bits - 1) / bits; }  // bit 63 is always 1
+};
+
+// Workspace plan: byte offsets of every scratch array inside the caller's
+// workspace, all 256-byte aligned.
+struct Plan {
+  int64_t n;
+  int32_t n_leaf;
+  uint32_t flags;
+  SortConfig sort;
+  int64_t sort_tiles;
+  int64_t cell_tiles;
+  int64_t c_max;
+  // offsets
+  size_t keys0, keys1;     // u64 [n] ping-pong key buffers
+  size_t vals1;            // u32 [n] payload buffer (the other one is out->perm)
+  size_t hist;             // u32 [passes][radix] global digit counts
+  size_t hist_part;        // u32 [keygen blocks][passes][radix] per-workgroup counts
+  size_t status0, status1; // u64 [sort_tiles][radix] lookback words (alternating passes)
+  size_t counters;         // u32 [64] dynamic tile counters
+  size_t box;              // f64 [4] the root box used by this build
+  size_t bbox_part;        // f64 [kBboxBlocks][6] per-block min/max partials
+  size_t cell_status;      // u64 [cell_tiles][kLevels] lookback of per-level cell counts
+  size_t cell_incl;        // u32 [cell_tiles][kLevels] inclusive per-level prefix per tile
+  size_t total;
+};
+
+constexpr int kBboxBlocks = 512;
+constexpr int kBboxThreads = 256;
+
+int make_plan(int64_t n, int32_t n_leaf, uint32_t flags, const SortConfig &sc, Plan *p);
+SortConfig default_sort_config(int64_t n);
+
+// Device views of the workspace
+struct Work {
+  uint64_t *keys0, *keys1;
+  uint32_t *vals1;
+  uint32_t *hist;
+  uint32_t *hist_part;
+  uint64_t *status0, *status1;
+  uint32_t *counters;
+  double *box;
+  double *bbox_part;
+  uint64_t *cell_status;
+  uint32_t *cell_incl;
+};
+
+Work carve(const Plan &p, void *base);
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (each defined in the .hip file that holds the kernel)
+// ---------------------------------------------------------------------------
+// tb_keys.hip
+hipError_t launch_init(const Plan &p, const Work &w, const tb_box *box, const tb_tree &out,
+                       hipStream_t s);
+hipError_t launch_bbox(const Plan &p, const Work &w, const float *pos, hipStream_t s);
+hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const tb_tree &out,
+                         hipStream_t s);
+hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s);
+int keygen_blocks(int64_t n);
+hipError_t launch_empty(const tb_tree &out, const tb_box *box, hipStream_t s);
+// tb_sort.hip
+hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tree &out,
+                            hipStream_t s);
+// tb_cells.hip
+hipError_t launch_cell_count(const Plan &p, const Work &w, int32_t *out_status, hipStream_t s);
+hipError_t launch_cell_emit(const Plan &p, const Work &w, const float *pos, const float *mass,
+                            const tb_tree &out, hipStream_t s);
+// tb_parents.hip
+hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
+                          hipStream_t s);
+
+// Final sorted keys live in keys0 or keys1 depending on the number of passes.
+inline uint64_t *sorted_keys(const Plan &p, const Work &w) {
+  return (p.sort.passes() % 2 == 0) ? w.keys0 : w.keys1;
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (uint64_t(1) << lane_id()) - 1u;
+}
+
+__device__ __forceinline__ uint64_t atomic_load_agent(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void atomic_store_agent(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until a look-back word is published.  Predecessor tiles always publish,
+// so the wait is short; the bound only turns a broken invariant into an error
+// flag (and an exit) instead of a hang.
+constexpr uint32_t kSpinLimit = 1u << 25;
+
+__device__ inline uint64_t wait_published(const uint64_t *p, bool &timed_out) {
+  uint64_t sw = atomic_load_agent(p);
+  uint32_t spins = 0;
+  while ((sw & kFlagMask) == 0) {
+    if (++spins > kSpinLimit) {
+      timed_out = true;
+      return kFlagInclusive;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    sw = atomic_load_agent(p);
+  }
+  return sw;
+}
+
+// Minimum distinguished depth of two particle keys (Sec. 2.3.1): leading zeros
+// of the XOR divided by three, rounded up; identical keys give 22.
+__device__ __forceinline__ int min_depth(uint64_t a, uint64_t b) {
+  uint64_t x = a ^ b;
+  int z = x ? __clzll(static_cast<long long>(x)) : 64;
+  return (z + 2) / 3;
+}
+
+// Inclusive wave64 scan of a u32 (shuffle-based).
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+#endif
+
+}  // namespace tb

@@ -1,0 +1,249 @@
+// tb_sort.hip -- stable LSD radix sort of (key, index) pairs (Sec. 2.3, step ii).
+//
+// One kernel launch per digit pass ("onesweep" structure):
+//   * every workgroup takes the next tile of keys (dynamic tile id, so all
+//     earlier tiles are already running and the look-back always progresses);
+//   * each wave ranks its keys with 64-lane ballots: for every digit bit a
+//     ballot, AND-ed into the mask of lanes holding the same digit, whose
+//     population below the lane is the lane's rank among equal digits; items
+//     are processed in index order, so the ranking is stable;
+//   * per-wave digit counts are combined in LDS; the tile publishes its
+//     per-digit counts, then looks back over earlier tiles (decoupled look-back)
+//     for its global exclusive prefix;
+//   * keys and payloads are first sorted by digit inside the tile in LDS, then
+//     written so that consecutive lanes store consecutive addresses of a digit
+//     run.
+// The global digit counts come from the key-generation pass, so the keys are
+// read only once per pass.  The index payload of the last pass is `perm`.
+#include "tb_internal.h"
+
+namespace tb {
+
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *s_tmp,
+                                                        uint32_t *total) {
+  constexpr int WAVES = THREADS / 64;
+  const int wv = threadIdx.x / 64;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane_id() == 63) s_tmp[wv] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < WAVES; ++k) {
+    const uint32_t t = s_tmp[k];
+    off += (k < wv) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+template <int BITS, int IPT, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_onesweep(
+    const uint64_t *__restrict__ kin, uint64_t *__restrict__ kout,
+    const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
+    uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
+    int32_t *__restrict__ status_word, int64_t n_tiles) {
+  constexpr int R = 1 << BITS;
+  constexpr int WAVES = THREADS / 64;
+  constexpr int TILE = THREADS * IPT;
+  constexpr int DPT = (R + THREADS - 1) / THREADS;  // digits per thread
+  constexpr uint32_t MASK = R - 1;
+
+  __shared__ uint64_t s_keys[TILE];
+  __shared__ uint32_t s_vals[TILE];
+  __shared__ uint32_t s_wc[WAVES * R];  // per-wave digit counters, then wave offsets
+  __shared__ uint32_t s_tstart[R];      // tile-local start of each digit
+  __shared__ int64_t s_goff[R];         // global position minus tile-local position
+  __shared__ uint32_t s_tmp[WAVES];
+  __shared__ uint32_t s_tile;
+
+  if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+  for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
+  __syncthreads();
+  const int64_t tile = s_tile;
+  if (tile >= n_tiles) {  // the counter was not reset: never true after k_init
+    if (threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
+    return;
+  }
+  const int64_t base = tile * TILE;
+  const int wv = threadIdx.x / 64;
+  const int ln = lane_id();
+  const uint64_t lt = lanemask_lt();
+
+  // wave-striped load: item j of lane l is key base + wv*64*IPT + j*64 + l
+  uint64_t k[IPT];
+  uint32_t v[IPT];
+  uint32_t rk[IPT];
+  const int64_t wbase = base + (int64_t)wv * 64 * IPT + ln;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t idx = wbase + j * 64;
+    if (idx < n) {
+      k[j] = kin[idx];
+      v[j] = vin ? vin[idx] : (uint32_t)idx;
+    } else {
+      k[j] = 0;
+      v[j] = 0;
+    }
+  }
+
+  // stable wave-level ranking
+  uint32_t *wc = s_wc + wv * R;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const bool valid = wbase + j * 64 < n;
+    const uint32_t d = (uint32_t)(k[j] >> shift) & MASK;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t pre = (uint32_t)__popcll(peers & lt);
+    uint32_t cnt = 0;
+    if (valid) cnt = wc[d];
+    rk[j] = cnt + pre;
+    if (valid && pre == 0) wc[d] = cnt + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+
+  // per digit: exclusive offsets across waves and the tile count
+  uint32_t tcnt[DPT];
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    uint32_t run = 0;
+    if (d < R) {
+#pragma unroll
+      for (int q = 0; q < WAVES; ++q) {
+        const uint32_t c = s_wc[q * R + d];
+        s_wc[q * R + d] = run;
+        run += c;
+      }
+      atomic_store_agent(&status[tile * R + d],
+                         (tile == 0 ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
+    }
+    tcnt[t] = run;
+  }
+
+  // tile-local digit starts and global digit starts (block scans over digits)
+  uint32_t g[DPT];
+  uint32_t tsum = 0, gsum = 0;
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    g[t] = (d < R) ? hist[d] : 0u;
+    tsum += tcnt[t];
+    gsum += g[t];
+  }
+  uint32_t dummy;
+  uint32_t trun = block_exclusive_sum<THREADS>(tsum, s_tmp, &dummy);
+  uint32_t grun = block_exclusive_sum<THREADS>(gsum, s_tmp, &dummy);
+
+  // decoupled look-back, one thread per digit
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    if (d < R) {
+      uint32_t excl = 0;
+      if (tile > 0) {
+        int64_t q = tile - 1;
+        bool timed_out = false;
+        while (true) {
+          const uint64_t sw = wait_published(&status[q * R + d], timed_out);
+          excl += (uint32_t)sw;
+          if ((sw & kFlagMask) == kFlagInclusive || q == 0) break;
+          --q;
+        }
+        if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
+        atomic_store_agent(&status[tile * R + d], kFlagInclusive | (uint64_t)(excl + tcnt[t]));
+      }
+      s_tstart[d] = trun;
+      s_goff[d] = (int64_t)grun + excl - (int64_t)trun;
+    }
+    trun += tcnt[t];
+    grun += g[t];
+  }
+  __syncthreads();
+
+  // sort the tile by digit in LDS
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if (wbase + j * 64 < n) {
+      const uint32_t d = (uint32_t)(k[j] >> shift) & MASK;
+      const uint32_t p = s_tstart[d] + wc[d] + rk[j];
+      s_keys[p] = k[j];
+      s_vals[p] = v[j];
+    }
+  }
+  // the next pass's look-back words for this tile start cleared
+  for (int i = threadIdx.x; i < R; i += THREADS) status_next[tile * R + i] = 0;
+  __syncthreads();
+
+  // coalesced scatter: consecutive lanes write consecutive slots of a digit run
+  const int64_t rem = n - base;
+  const int tile_n = rem < TILE ? (int)rem : TILE;
+  bool bad = false;
+  for (int i = threadIdx.x; i < tile_n; i += THREADS) {
+    const uint64_t key = s_keys[i];
+    const uint32_t d = (uint32_t)(key >> shift) & MASK;
+    const int64_t gp = s_goff[d] + i;
+    if (gp < 0 || gp >= n) {  // cannot happen with consistent histograms
+      bad = true;
+      continue;
+    }
+    kout[gp] = key;
+    vout[gp] = s_vals[i];
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
+}
+
+template <int BITS, int IPT, int THREADS>
+static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb_tree &out,
+                                hipStream_t s) {
+  const int P = p.sort.passes();
+  uint64_t *K[2] = {w.keys0, w.keys1};
+  // the last pass must write its payload into out.perm
+  uint32_t *V[2];
+  V[P % 2] = reinterpret_cast<uint32_t *>(out.perm);
+  V[(P + 1) % 2] = w.vals1;
+  uint64_t *S[2] = {w.status0, w.status1};
+  const uint32_t *vin = pass == 0 ? nullptr : V[pass % 2];
+  const int R = 1 << BITS;
+  k_onesweep<BITS, IPT, THREADS><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
+      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], p.n, pass * BITS,
+      w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, out.status,
+      p.sort_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tree &out,
+                            hipStream_t s) {
+  const SortConfig &c = p.sort;
+#define TB_SORT_CASE(B, I, T)                                         \
+  if (c.bits == B && c.ipt == I && c.threads == T)                    \
+    return launch_pass_t<B, I, T>(p, w, pass, out, s);
+  TB_SORT_CASE(8, 16, 256)
+  TB_SORT_CASE(8, 12, 256)
+  TB_SORT_CASE(8, 8, 512)
+  TB_SORT_CASE(9, 16, 256)
+  TB_SORT_CASE(9, 12, 256)
+  TB_SORT_CASE(10, 16, 256)
+  TB_SORT_CASE(11, 16, 256)
+#undef TB_SORT_CASE
+  return hipErrorInvalidValue;
+}
+
+bool sort_config_supported(const SortConfig &c) {
+  static const int table[][3] = {{8, 16, 256}, {8, 12, 256}, {8, 8, 512}, {9, 16, 256},
+                                 {9, 12, 256}, {10, 16, 256}, {11, 16, 256}};
+  for (const auto &r : table)
+    if (r[0] == c.bits && r[1] == c.ipt && r[2] == c.threads) return true;
+  return false;
+}
+
+}  // namespace tb

@@ -1,0 +1,327 @@
+"""Python binding of the gfx950 tree-build library (include/treebuild.h).
+
+Argument marshalling only: every step of a build runs in the HIP kernels of
+``libtreebuild.so``.  PyTorch supplies device memory and the stream.  There is
+no CPU fallback: without the native library, or with tensors that are not on a
+GPU, every call raises.
+
+The functions ``tb_max_cells``, ``tb_workspace_bytes``, ``tb_build``,
+``tb_build_sync``, ``tb_trace_enable``, ``tb_trace_read``, ``tb_sort_configs``
+and ``tb_version`` mirror the C entry points of the same names.  ``Builder``
+keeps a workspace and output buffers for repeated builds; ``build`` is the
+one-shot convenience form.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtreebuild.so")
+
+TB_OK = 0
+TB_ERR_ARG = -1
+TB_ERR_BOX = -2
+TB_ERR_WORKSPACE = -3
+TB_ERR_HIP = -4
+TB_ERR_NONFINITE = -5
+TB_ERR_MASS = -6
+TB_ERR_INTERNAL = -7
+TB_STATUS_NONFINITE = 1
+TB_STATUS_MASS = 2
+TB_STATUS_INTERNAL = 4
+TB_FP64 = 0
+TB_MIXED = 1
+TB_MAX_DEPTH = 21
+TB_MAX_NLEAF = 1024
+
+EXPORTS = ("tb_max_cells", "tb_workspace_bytes", "tb_build", "tb_build_sync", "tb_trace_enable",
+           "tb_trace_read", "tb_sort_configs", "tb_version")
+
+_ERRNAMES = {TB_ERR_ARG: "TB_ERR_ARG", TB_ERR_BOX: "TB_ERR_BOX", TB_ERR_WORKSPACE: "TB_ERR_WORKSPACE",
+             TB_ERR_HIP: "TB_ERR_HIP", TB_ERR_NONFINITE: "TB_ERR_NONFINITE", TB_ERR_MASS: "TB_ERR_MASS",
+             TB_ERR_INTERNAL: "TB_ERR_INTERNAL"}
+
+
+def TB_SORT_CONFIG(k: int) -> int:
+    return (int(k) & 0xFF) << 8
+
+
+class TbBox(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("side", ctypes.c_double)]
+
+
+class TbTree(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in (
+        "perm", "cell_key", "cell_level", "cell_first", "cell_count", "child_ptr", "com", "quad",
+        "level_offset", "n_cells", "status", "box_out", "pos_sorted", "mass_sorted", "key_sorted")]
+
+
+class TbTraceEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+class TreeBuildError(RuntimeError):
+    def __init__(self, code: int, what: str = "tb_build"):
+        super().__init__(f"{what} failed: {_ERRNAMES.get(code, code)}")
+        self.code = code
+
+
+class TreeBuildArgError(TreeBuildError, ValueError):
+    pass
+
+
+def _raise(code: int, what: str):
+    if code in (TB_ERR_ARG, TB_ERR_BOX, TB_ERR_WORKSPACE, TB_ERR_NONFINITE, TB_ERR_MASS):
+        raise TreeBuildArgError(code, what)
+    raise TreeBuildError(code, what)
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtreebuild.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2312_06102_amd.build_lib` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.tb_max_cells.argtypes = [i64, i32, ctypes.POINTER(i64)]
+    lib.tb_workspace_bytes.argtypes = [i64, i32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]
+    sig = [P, P, i64, i32, ctypes.POINTER(TbBox), ctypes.c_uint32, P, ctypes.c_size_t,
+           ctypes.POINTER(TbTree), P]
+    lib.tb_build.argtypes = sig
+    lib.tb_build_sync.argtypes = sig
+    lib.tb_trace_enable.argtypes = [ctypes.c_int]
+    lib.tb_trace_read.argtypes = [ctypes.POINTER(TbTraceEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.tb_sort_configs.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.tb_version.restype = ctypes.c_char_p
+    for f in EXPORTS[:-1]:
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ----------------------------------------------------------------------------
+# the C entry points
+# ----------------------------------------------------------------------------
+
+def tb_max_cells(n: int, n_leaf: int) -> int:
+    out = ctypes.c_int64(0)
+    rc = load_library().tb_max_cells(int(n), int(n_leaf), ctypes.byref(out))
+    if rc:
+        _raise(rc, "tb_max_cells")
+    return out.value
+
+
+def tb_workspace_bytes(n: int, n_leaf: int, flags: int = TB_FP64) -> int:
+    out = ctypes.c_size_t(0)
+    rc = load_library().tb_workspace_bytes(int(n), int(n_leaf), int(flags), ctypes.byref(out))
+    if rc:
+        _raise(rc, "tb_workspace_bytes")
+    return out.value
+
+
+def tb_build(pos_ptr: int, mass_ptr: int, n: int, n_leaf: int, box: Optional[TbBox], flags: int,
+             ws_ptr: int, ws_bytes: int, out: TbTree, stream: int) -> int:
+    """Raw call: device pointers as ints; returns the C return code."""
+    return load_library().tb_build(ctypes.c_void_p(pos_ptr), ctypes.c_void_p(mass_ptr), int(n),
+                                   int(n_leaf), ctypes.byref(box) if box is not None else None,
+                                   int(flags), ctypes.c_void_p(ws_ptr), int(ws_bytes),
+                                   ctypes.byref(out), ctypes.c_void_p(stream))
+
+
+def tb_build_sync(pos_ptr: int, mass_ptr: int, n: int, n_leaf: int, box: Optional[TbBox],
+                  flags: int, ws_ptr: int, ws_bytes: int, out: TbTree, stream: int) -> int:
+    return load_library().tb_build_sync(ctypes.c_void_p(pos_ptr), ctypes.c_void_p(mass_ptr), int(n),
+                                        int(n_leaf), ctypes.byref(box) if box is not None else None,
+                                        int(flags), ctypes.c_void_p(ws_ptr), int(ws_bytes),
+                                        ctypes.byref(out), ctypes.c_void_p(stream))
+
+
+def tb_trace_enable(on: bool = True) -> None:
+    load_library().tb_trace_enable(1 if on else 0)
+
+
+def tb_trace_read() -> dict:
+    """{kernel name: (launches, total_ms)}; resets the accumulators."""
+    lib = load_library()
+    cap = 64
+    arr = (TbTraceEntry * cap)()
+    cnt = ctypes.c_int(0)
+    rc = lib.tb_trace_read(arr, cap, ctypes.byref(cnt))
+    if rc:
+        _raise(rc, "tb_trace_read")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
+
+
+def tb_sort_configs() -> list:
+    """[(digit bits, keys per thread, threads)] indexed by TB_SORT_CONFIG(k)."""
+    lib = load_library()
+    cnt = ctypes.c_int(0)
+    lib.tb_sort_configs(None, 0, ctypes.byref(cnt))
+    arr = (ctypes.c_int32 * (3 * cnt.value))()
+    lib.tb_sort_configs(arr, cnt.value, ctypes.byref(cnt))
+    return [tuple(arr[3 * k:3 * k + 3]) for k in range(cnt.value)]
+
+
+def tb_version() -> str:
+    return load_library().tb_version().decode()
+
+
+# ----------------------------------------------------------------------------
+# torch-side buffers
+# ----------------------------------------------------------------------------
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _check_device_tensor(t: torch.Tensor, name: str, dtype, shape_tail=()):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU (no CPU path exists)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+@dataclass
+class TreeBuffers:
+    """Device output buffers of one build (sized for C_max cells)."""
+    perm: torch.Tensor
+    cell_key: torch.Tensor
+    cell_level: torch.Tensor
+    cell_first: torch.Tensor
+    cell_count: torch.Tensor
+    child_ptr: torch.Tensor
+    com: torch.Tensor
+    quad: torch.Tensor
+    level_offset: torch.Tensor
+    n_cells: torch.Tensor
+    status: torch.Tensor
+    box_out: torch.Tensor
+    pos_sorted: Optional[torch.Tensor] = None
+    mass_sorted: Optional[torch.Tensor] = None
+    key_sorted: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def allocate(n: int, n_leaf: int, precision: str = "fp64", device="cuda",
+                 sorted_particles: bool = False, sorted_keys: bool = False) -> "TreeBuffers":
+        cmax = max(tb_max_cells(n, n_leaf), 1)
+        fdt = torch.float64 if precision == "fp64" else torch.float32
+        kw = dict(device=device)
+        nn = max(n, 1)
+        return TreeBuffers(
+            perm=torch.empty(nn, dtype=torch.int32, **kw),
+            cell_key=torch.empty(cmax, dtype=torch.int64, **kw),  # uint64 bit patterns
+            cell_level=torch.empty(cmax, dtype=torch.uint8, **kw),
+            cell_first=torch.empty(cmax, dtype=torch.int32, **kw),
+            cell_count=torch.empty(cmax, dtype=torch.int32, **kw),
+            child_ptr=torch.empty((cmax, 2), dtype=torch.int32, **kw),
+            com=torch.empty((cmax, 4), dtype=fdt, **kw),
+            quad=torch.empty((cmax, 6), dtype=fdt, **kw),
+            level_offset=torch.empty(TB_MAX_DEPTH + 2, dtype=torch.int64, **kw),
+            n_cells=torch.empty(1, dtype=torch.int64, **kw),
+            status=torch.empty(1, dtype=torch.int32, **kw),
+            box_out=torch.empty(4, dtype=torch.float64, **kw),
+            pos_sorted=torch.empty((nn, 3), dtype=torch.float32, **kw) if sorted_particles else None,
+            mass_sorted=torch.empty(nn, dtype=torch.float32, **kw) if sorted_particles else None,
+            key_sorted=torch.empty(nn, dtype=torch.int64, **kw) if sorted_keys else None,
+        )
+
+    def struct(self) -> TbTree:
+        t = TbTree()
+        for f, _ in TbTree._fields_:
+            v = getattr(self, f)
+            setattr(t, f, _ptr(v))
+        return t
+
+
+def _box_struct(box) -> Optional[TbBox]:
+    if box is None:
+        return None
+    lo, side = box
+    b = TbBox()
+    for a in range(3):
+        b.lo[a] = float(lo[a])
+    b.side = float(side)
+    return b
+
+
+class Builder:
+    """Reusable workspace + outputs for repeated builds of N particles."""
+
+    def __init__(self, n: int, n_leaf: int = 16, precision: str = "fp64", sort_config: int = 0,
+                 device="cuda", sorted_particles: bool = False, sorted_keys: bool = False):
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        self.n, self.n_leaf, self.precision = int(n), int(n_leaf), precision
+        self.flags = (TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
+        self.ws_bytes = tb_workspace_bytes(self.n, self.n_leaf, self.flags)
+        self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
+                                        sorted_keys)
+        self._struct = self.out.struct()
+
+    def launch(self, pos: torch.Tensor, mass: torch.Tensor, box=None, stream=None) -> None:
+        """Asynchronous build on `stream` (default: torch's current stream)."""
+        _check_device_tensor(pos, "pos", torch.float32, (3,))
+        _check_device_tensor(mass, "mass", torch.float32)
+        if pos.shape[0] != self.n or mass.shape[0] != self.n:
+            raise ValueError(f"this Builder is sized for N={self.n}")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = tb_build(pos.data_ptr(), mass.data_ptr(), self.n, self.n_leaf, _box_struct(box),
+                      self.flags, self.workspace.data_ptr(), self.ws_bytes, self._struct,
+                      s.cuda_stream)
+        if rc:
+            _raise(rc, "tb_build")
+
+    def result(self) -> dict:
+        """Synchronise and return the outputs trimmed to n_cells (device tensors)."""
+        torch.cuda.synchronize()
+        st = int(self.out.status.item())
+        if st & TB_STATUS_NONFINITE:
+            _raise(TB_ERR_NONFINITE, "tb_build")
+        if st & TB_STATUS_MASS:
+            _raise(TB_ERR_MASS, "tb_build")
+        if st & TB_STATUS_INTERNAL:
+            _raise(TB_ERR_INTERNAL, "tb_build")
+        c = int(self.out.n_cells.item())
+        o = self.out
+        res = dict(perm=o.perm[:self.n], cell_key=o.cell_key[:c], cell_level=o.cell_level[:c],
+                   cell_first=o.cell_first[:c], cell_count=o.cell_count[:c],
+                   child_ptr=o.child_ptr[:c], com=o.com[:c], quad=o.quad[:c],
+                   level_offset=o.level_offset.clone(), n_cells=c, box=o.box_out.clone())
+        if o.pos_sorted is not None:
+            res["pos_sorted"] = o.pos_sorted[:self.n]
+            res["mass_sorted"] = o.mass_sorted[:self.n]
+        if o.key_sorted is not None:
+            res["key_sorted"] = o.key_sorted[:self.n]
+        return res
+
+
+def build(pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 16, box=None,
+          precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
+          sorted_keys: bool = False) -> dict:
+    """One-shot build; returns device tensors trimmed to n_cells.
+
+    box: None (derive from data) or (lo[3], side) with side a power of two.
+    cell_key is returned as int64 holding the uint64 bit pattern."""
+    b = Builder(pos.shape[0], n_leaf, precision, sort_config, pos.device, sorted_particles,
+                sorted_keys)
+    b.launch(pos, mass, box)
+    return b.result()
