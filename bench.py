@@ -43,7 +43,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22,
                     help="particles of the workload the oracle builds for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies of 256 MiB (to scale HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """Five plain device-to-device copies of 2^28 bytes each: a kernel whose HBM
+    traffic is known exactly (2^28 read + 2^28 written per launch), to scale the
+    FETCH_SIZE / WRITE_SIZE counters of the build kernels."""
+    import torch
+    src = torch.empty(1 << 26, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": 1 << 28, "launches": 5}))
 
 
 def algorithmic_bytes(n: int, cells: int, leaves: int, passes: int, precision: str) -> dict:
@@ -70,6 +86,9 @@ def algorithmic_bytes(n: int, cells: int, leaves: int, passes: int, precision: s
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))

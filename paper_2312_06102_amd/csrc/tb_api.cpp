@@ -13,11 +13,12 @@ namespace tb {
 
 bool sort_config_supported(const SortConfig &c);
 size_t cell_emit_lds(int nl);
+size_t cell_lds_limit();
 
 // Table of sort shapes selectable through TB_SORT_CONFIG(k); entry 0 is the default.
 static const SortConfig kSortTable[] = {
-    {8, 16, 256}, {9, 16, 256}, {8, 12, 256}, {9, 12, 256},
-    {8, 8, 512},  {10, 16, 256}, {11, 16, 256},
+    {8, 8, 512},  {8, 16, 256}, {9, 16, 256}, {8, 12, 256},
+    {9, 12, 256}, {8, 8, 256},  {8, 12, 512},
 };
 static const int kSortTableSize = (int)(sizeof(kSortTable) / sizeof(kSortTable[0]));
 
@@ -56,8 +57,11 @@ int make_plan(int64_t n, int32_t n_leaf, uint32_t flags, const SortConfig &sc, P
   p->counters = take(4 * 64);
   p->box = take(8 * 4);
   p->bbox_part = take(8 * 6 * (size_t)kBboxBlocks);
-  p->cell_status = take(8 * (size_t)p->cell_tiles * kLevels);
-  p->cell_incl = take(4 * (size_t)p->cell_tiles * kLevels);
+  p->cell_cnt = take(4 * (size_t)p->cell_tiles * kLevels);
+  p->cell_excl = take(4 * (size_t)(p->cell_tiles + 1) * kLevels);
+  p->packed = take(16 * (size_t)n);
+  p->sorted = take(16 * (size_t)n);
+  p->head_parent = take(4 * (size_t)p->c_max);
   p->total = off;
   return TB_OK;
 }
@@ -75,8 +79,11 @@ Work carve(const Plan &p, void *base) {
   w.counters = reinterpret_cast<uint32_t *>(b + p.counters);
   w.box = reinterpret_cast<double *>(b + p.box);
   w.bbox_part = reinterpret_cast<double *>(b + p.bbox_part);
-  w.cell_status = reinterpret_cast<uint64_t *>(b + p.cell_status);
-  w.cell_incl = reinterpret_cast<uint32_t *>(b + p.cell_incl);
+  w.cell_cnt = reinterpret_cast<uint32_t *>(b + p.cell_cnt);
+  w.cell_excl = reinterpret_cast<uint32_t *>(b + p.cell_excl);
+  w.packed = reinterpret_cast<float4 *>(b + p.packed);
+  w.sorted = reinterpret_cast<float4 *>(b + p.sorted);
+  w.head_parent = reinterpret_cast<int32_t *>(b + p.head_parent);
   return w;
 }
 
@@ -174,6 +181,8 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t n_
   Plan p;
   make_plan(n, n_leaf, flags, sc, &p);
   if (!workspace || ws_bytes < p.total) return TB_ERR_WORKSPACE;
+  // the cell kernels stage a tile plus an n_leaf halo in LDS
+  if (cell_emit_lds(n_leaf) > cell_lds_limit()) return TB_ERR_ARG;
   const Work w = carve(p, workspace);
 
   hipError_t e = hipSuccess;
@@ -186,8 +195,10 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t n_
   run("hist_reduce", [&] { return launch_hist_reduce(p, w, s); });
   for (int pass = 0; pass < p.sort.passes(); ++pass)
     run("sort_pass", [&] { return launch_sort_pass(p, w, pass, *out, s); });
-  run("cell_count", [&] { return launch_cell_count(p, w, out->status, s); });
-  run("cell_emit", [&] { return launch_cell_emit(p, w, pos, mass, *out, s); });
+  run("cell_count", [&] { return launch_cell_count(p, w, pos, mass, s); });
+  run("cell_scan", [&] { return launch_cell_scan(p, w, s); });
+  run("reorder", [&] { return launch_reorder(p, w, *out, s); });
+  run("cell_emit", [&] { return launch_cell_emit(p, w, *out, s); });
   for (int d = kMaxDepth - 1; d >= 0; --d)
     run("parents", [&] { return launch_parents(p, w, d, *out, s); });
   if (out->key_sorted)

@@ -19,11 +19,11 @@
 // bottom-up pass below knows, before any parent exists, how many cells each
 // depth will hold and where each cell goes in the (depth, key) order.
 //
-// k_cell_count : per tile, per-depth cell counts; decoupled look-back gives
-//                every tile its per-depth prefix.
+// k_cell_count : per tile, per-depth cell counts (and packed particle records);
+// k_cell_scan  : per-depth prefix over tiles;
+// k_reorder    : particles in key order (the reorder step);
 // k_cell_emit  : writes key, depth, first particle and first-child slot of
-//                every cell, and count plus moments of every leaf (the leaf's
-//                particles are gathered through perm: the reorder step).
+//                every cell, and count plus moments of every leaf.
 #include "tb_internal.h"
 
 namespace tb {
@@ -38,14 +38,22 @@ struct CellLds {
   uint8_t *a;      // [T + NL]        a_i, i in [t0, t1 + NL)
   uint32_t *wtot;  // [kWaves][kLevelWords]
   uint32_t *lvl;   // [kLevels]       per-depth base of this tile
-  uint32_t *off;   // [kLevels][kCellThreads] next cell index per depth per thread
+  uint16_t *off;   // [kLevels][kCellThreads] next cell slot per depth per thread (tile-relative)
+  float4 *rec;     // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL)
+  uint32_t *leaf_ci;   // [T]         cell slot of each leaf starting in the tile
+  uint16_t *leaf_tag;  // [T]         local first particle | depth << 11
+  uint32_t *nleaf;     // [1]
 };
 
 __host__ __device__ inline size_t cell_lds_bytes(int nl, bool emit) {
   size_t b = (size_t)(kCellTile + 2 * nl + 1) * 8;
   b += 2 * (size_t)((kCellTile + nl + 15) & ~15);
   b += (size_t)kWaves * kLevelWords * 4 + kLevels * 4;
-  if (emit) b += (size_t)kLevels * kCellThreads * 4;
+  if (emit) {
+    b += (size_t)kLevels * kCellThreads * 2;
+    b = (b + 15) & ~size_t(15);
+    b += (size_t)(kCellTile + nl) * 16 + (size_t)kCellTile * 6 + 16;
+  }
   return b;
 }
 
@@ -62,7 +70,23 @@ __device__ inline CellLds carve_lds(unsigned char *base, int nl, bool emit) {
   base += kWaves * kLevelWords * 4;
   s.lvl = reinterpret_cast<uint32_t *>(base);
   base += kLevels * 4;
-  s.off = emit ? reinterpret_cast<uint32_t *>(base) : nullptr;
+  s.off = nullptr;
+  s.rec = nullptr;
+  s.leaf_ci = nullptr;
+  s.leaf_tag = nullptr;
+  s.nleaf = nullptr;
+  if (emit) {
+    s.off = reinterpret_cast<uint16_t *>(base);
+    base += kLevels * kCellThreads * 2;
+    base = reinterpret_cast<unsigned char *>((reinterpret_cast<uintptr_t>(base) + 15) & ~uintptr_t(15));
+    s.rec = reinterpret_cast<float4 *>(base);
+    base += (size_t)(kCellTile + nl) * 16;
+    s.leaf_ci = reinterpret_cast<uint32_t *>(base);
+    base += (size_t)kCellTile * 4;
+    s.leaf_tag = reinterpret_cast<uint16_t *>(base);
+    base += (size_t)kCellTile * 2;
+    s.nleaf = reinterpret_cast<uint32_t *>(base);
+  }
   return s;
 }
 
@@ -74,9 +98,22 @@ __device__ inline void tile_depths(const CellLds &s, const uint64_t *__restrict_
   const int T = (int)(t1 - t0);
   const int64_t ws = t0 - nl - 1;  // window start (may be negative)
   const int wn = T + 2 * nl + 1;
-  for (int i = threadIdx.x; i < wn; i += kCellThreads) {
-    const int64_t g = ws + i;
-    s.keys[i] = (g >= 0 && g < n) ? keys[g] : 0ull;
+  // all loads of a batch are issued before any is stored, so a tile waits for
+  // one or two memory round trips instead of one per key
+  constexpr int kBatch = 8;
+  for (int i0 = 0; i0 < wn; i0 += kBatch * kCellThreads) {
+    uint64_t v[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int i = i0 + r * kCellThreads + threadIdx.x;
+      const int64_t g = ws + i;
+      v[r] = (i < wn && g >= 0 && g < n) ? keys[g] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int i = i0 + r * kCellThreads + threadIdx.x;
+      if (i < wn) s.keys[i] = v[r];
+    }
   }
   __syncthreads();
   // a_i for i in [t0, t1 + nl)
@@ -183,54 +220,140 @@ __device__ __forceinline__ uint32_t unpack(const uint32_t w[kLevelWords], int d)
 // ---------------------------------------------------------------------------
 // count pass
 // ---------------------------------------------------------------------------
+// Per tile, the number of cells each depth will hold whose first particle lies
+// in the tile (stored depth-major: cnt[d][tile]).  The same workgroups also
+// pack (x, y, z, m) of their chunk of particles into one 16-byte record each
+// (original order), so the reorder pass gathers one record per particle.
 __global__ __launch_bounds__(kCellThreads) void k_cell_count(
-    const uint64_t *__restrict__ keys, int64_t n, int nl, uint64_t *__restrict__ cstatus,
-    uint32_t *__restrict__ cincl, uint32_t *__restrict__ tile_counter, int64_t n_tiles,
-    int32_t *__restrict__ status_word) {
+    const uint64_t *__restrict__ keys, int64_t n, int nl, int64_t n_tiles,
+    uint32_t *__restrict__ tile_cnt, const float *__restrict__ pos,
+    const float *__restrict__ mass, float4 *__restrict__ packed) {
   extern __shared__ __align__(16) unsigned char lds[];
   const CellLds s = carve_lds(lds, nl, false);
-  __shared__ uint32_t s_tile;
-  if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-  __syncthreads();
-  const int64_t tile = s_tile;
-  if (tile >= n_tiles) {  // the counter was not reset: never true after k_init
-    if (threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
-    return;
-  }
+  const int64_t tile = blockIdx.x;
   const int64_t t0 = tile * kCellTile;
   const int64_t t1 = min(t0 + (int64_t)kCellTile, n);
+  {
+    float4 rec[kCellIpt];
+#pragma unroll
+    for (int r = 0; r < kCellIpt; ++r) {
+      const int64_t i = t0 + r * kCellThreads + threadIdx.x;
+      rec[r] = i < t1 ? make_float4(pos[3 * i + 0], pos[3 * i + 1], pos[3 * i + 2], mass[i])
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < kCellIpt; ++r) {
+      const int64_t i = t0 + r * kCellThreads + threadIdx.x;
+      if (i < t1) packed[i] = rec[r];
+    }
+  }
   uint8_t A[kCellIpt], D[kCellIpt];
   tile_depths(s, keys, n, nl, t0, t1, A, D);
   uint32_t c[kLevelWords], tot[kLevelWords];
   thread_level_counts(A, D, c);
   block_level_scan(s, c, tot);
-  // thread d publishes this tile's depth-d count and looks back for its prefix
   const int d = threadIdx.x;
   if (d < kLevels) {
     uint32_t cnt = 0;
 #pragma unroll
     for (int wi = 0; wi < kLevelWords; ++wi)
       if (wi == (d >> 1)) cnt = (tot[wi] >> ((d & 1) * 16)) & 0xffffu;
-    uint64_t *st = cstatus + tile * kLevels + d;
-    if (tile == 0) {
-      atomic_store_agent(st, kFlagInclusive | cnt);
-      cincl[d] = cnt;
-    } else {
-      atomic_store_agent(st, kFlagAggregate | cnt);
-      uint32_t excl = 0;
-      int64_t q = tile - 1;
-      bool timed_out = false;
-      while (true) {
-        const uint64_t sw = wait_published(cstatus + q * kLevels + d, timed_out);
-        excl += (uint32_t)sw;
-        if ((sw & kFlagMask) == kFlagInclusive || q == 0) break;
-        --q;
+    tile_cnt[d * n_tiles + tile] = cnt;
+  }
+}
+
+// Exclusive prefix over tiles of the per-tile counts, one workgroup per depth:
+// excl[d][t] = depth-d cells before tile t, excl[d][n_tiles] = depth-d total.
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+
+__global__ __launch_bounds__(kScanThreads) void k_cell_scan(const uint32_t *__restrict__ tile_cnt,
+                                                            int64_t n_tiles,
+                                                            uint32_t *__restrict__ excl) {
+  __shared__ uint32_t s_w[kScanThreads / 64];
+  const int d = blockIdx.x;
+  const uint32_t *row = tile_cnt + d * n_tiles;
+  uint32_t *out = excl + d * (n_tiles + 1);
+  const int wv = threadIdx.x / 64;
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n_tiles; c0 += (int64_t)kScanThreads * kScanItems) {
+    const int64_t b = c0 + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], sum = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      v[r] = (b + r < n_tiles) ? row[b + r] : 0u;
+      sum += v[r];
+    }
+    const uint32_t inc = wave_inclusive_scan(sum);
+    if (lane_id() == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kScanThreads / 64; ++q) {
+      const uint32_t t = s_w[q];
+      off += (q < wv) ? t : 0u;
+      tot += t;
+    }
+    __syncthreads();
+    uint32_t run = carry + off + inc - sum;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      if (b + r < n_tiles) out[b + r] = run;
+      run += v[r];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n_tiles] = carry;
+}
+
+// ---------------------------------------------------------------------------
+// reorder pass (Sec. 2.3, step iii)
+// ---------------------------------------------------------------------------
+// sorted[s] = packed[perm[s]]: the particles in key order, one 16-byte record
+// each.  Every thread issues all of its index loads, then all of its gathers,
+// so the random reads overlap.  Also fills the optional pos_sorted /
+// mass_sorted outputs and checks the masses.
+constexpr int kReorderThreads = 256;
+constexpr int kReorderIpt = 8;
+
+__global__ __launch_bounds__(kReorderThreads) void k_reorder(
+    const int32_t *__restrict__ perm, const float4 *__restrict__ packed, int64_t n,
+    float4 *__restrict__ sorted, float *__restrict__ pos_sorted,
+    float *__restrict__ mass_sorted, int32_t *__restrict__ status_word) {
+  const int64_t base = (int64_t)blockIdx.x * kReorderThreads * kReorderIpt + threadIdx.x;
+  int32_t p[kReorderIpt];
+#pragma unroll
+  for (int r = 0; r < kReorderIpt; ++r) {
+    const int64_t sp = base + r * kReorderThreads;
+    p[r] = perm[sp < n ? sp : n - 1];
+  }
+  // branch-free gathers (out-of-range indices are clamped and reported) so
+  // that all of them are in flight together
+  float4 rec[kReorderIpt];
+  bool internal = false, bad = false;
+#pragma unroll
+  for (int r = 0; r < kReorderIpt; ++r) {
+    const int64_t sp = base + r * kReorderThreads;
+    const bool ok = p[r] >= 0 && p[r] < n;
+    internal |= (sp < n) && !ok;
+    rec[r] = packed[ok ? p[r] : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < kReorderIpt; ++r) {
+    const int64_t sp = base + r * kReorderThreads;
+    if (sp < n) {
+      sorted[sp] = rec[r];
+      bad |= !(rec[r].w > 0.0f && isfinite(rec[r].w));
+      if (pos_sorted) {
+        pos_sorted[3 * sp + 0] = rec[r].x;
+        pos_sorted[3 * sp + 1] = rec[r].y;
+        pos_sorted[3 * sp + 2] = rec[r].z;
       }
-      if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
-      atomic_store_agent(st, kFlagInclusive | (uint64_t)(excl + cnt));
-      cincl[tile * kLevels + d] = excl + cnt;
+      if (mass_sorted) mass_sorted[sp] = rec[r].w;
     }
   }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_MASS);
+  if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
 // ---------------------------------------------------------------------------
@@ -268,59 +391,36 @@ __device__ inline int64_t leaf_end(const CellLds &s, const uint64_t *__restrict_
   return lo;
 }
 
-struct LeafOut {
-  double *com;
-  double *quad;
-  float *comf;
-  float *quadf;
-  float *pos_sorted;
-  float *mass_sorted;
+// FP64 leaf moments in the leaf's frame: one pass of sums of m, m r and m r r
+// (r relative to the leaf centre, so every term is bounded by the leaf size),
+// then the centre of mass and the traceless quadrupole about it.
+struct LeafSums {
+  double s0, s1[3], s2[6];
 };
 
-// FP64 leaf moments in the leaf's frame.
-__device__ inline bool leaf_moments_fp64(const float *__restrict__ pos,
-                                         const float *__restrict__ mass,
-                                         const int32_t *__restrict__ perm, int64_t n, int64_t i0, int64_t i1,
-                                         const double lo[3], const double off[3], double com[4],
-                                         double quad[6], float *__restrict__ pos_sorted,
-                                         float *__restrict__ mass_sorted, bool &internal) {
-  double s0 = 0, s1[3] = {0, 0, 0}, s2[6] = {0, 0, 0, 0, 0, 0};
-  bool bad = false;
-  for (int64_t s = i0; s < i1; ++s) {
-    const int64_t p = perm[s];
-    if (p < 0 || p >= n) {  // perm is a permutation of [0, n)
-      internal = true;
-      continue;
-    }
-    const float x = pos[3 * p + 0], y = pos[3 * p + 1], z = pos[3 * p + 2];
-    const float mf = mass[p];
-    bad |= !(mf > 0.0f && isfinite(mf));
-    if (pos_sorted) {
-      pos_sorted[3 * s + 0] = x;
-      pos_sorted[3 * s + 1] = y;
-      pos_sorted[3 * s + 2] = z;
-    }
-    if (mass_sorted) mass_sorted[s] = mf;
-    const double m = (double)mf;
-    const double r0 = __dsub_rn(__dsub_rn((double)x, lo[0]), off[0]);
-    const double r1 = __dsub_rn(__dsub_rn((double)y, lo[1]), off[1]);
-    const double r2 = __dsub_rn(__dsub_rn((double)z, lo[2]), off[2]);
-    s0 += m;
-    s1[0] += m * r0;
-    s1[1] += m * r1;
-    s1[2] += m * r2;
-    s2[0] += m * r0 * r0;
-    s2[1] += m * r0 * r1;
-    s2[2] += m * r0 * r2;
-    s2[3] += m * r1 * r1;
-    s2[4] += m * r1 * r2;
-    s2[5] += m * r2 * r2;
-  }
-  const double M = s0;
-  const double c0 = s1[0] / M, c1 = s1[1] / M, c2 = s1[2] / M;
-  // second moments about the centre of mass, then the traceless combination
-  const double xx = s2[0] - M * c0 * c0, xy = s2[1] - M * c0 * c1, xz = s2[2] - M * c0 * c2;
-  const double yy = s2[3] - M * c1 * c1, yz = s2[4] - M * c1 * c2, zz = s2[5] - M * c2 * c2;
+__device__ __forceinline__ void leaf_add(LeafSums &a, float4 rec, const double lo[3],
+                                         const double off[3]) {
+  const double m = (double)rec.w;
+  const double r0 = __dsub_rn(__dsub_rn((double)rec.x, lo[0]), off[0]);
+  const double r1 = __dsub_rn(__dsub_rn((double)rec.y, lo[1]), off[1]);
+  const double r2 = __dsub_rn(__dsub_rn((double)rec.z, lo[2]), off[2]);
+  a.s0 += m;
+  a.s1[0] += m * r0;
+  a.s1[1] += m * r1;
+  a.s1[2] += m * r2;
+  a.s2[0] += m * r0 * r0;
+  a.s2[1] += m * r0 * r1;
+  a.s2[2] += m * r0 * r2;
+  a.s2[3] += m * r1 * r1;
+  a.s2[4] += m * r1 * r2;
+  a.s2[5] += m * r2 * r2;
+}
+
+__device__ __forceinline__ void leaf_finish(const LeafSums &a, double com[4], double quad[6]) {
+  const double M = a.s0;
+  const double c0 = a.s1[0] / M, c1 = a.s1[1] / M, c2 = a.s1[2] / M;
+  const double xx = a.s2[0] - M * c0 * c0, xy = a.s2[1] - M * c0 * c1, xz = a.s2[2] - M * c0 * c2;
+  const double yy = a.s2[3] - M * c1 * c1, yz = a.s2[4] - M * c1 * c2, zz = a.s2[5] - M * c2 * c2;
   const double tr = xx + yy + zz;
   com[0] = c0;
   com[1] = c1;
@@ -332,65 +432,93 @@ __device__ inline bool leaf_moments_fp64(const float *__restrict__ pos,
   quad[3] = 3.0 * yy - tr;
   quad[4] = 3.0 * yz;
   quad[5] = 3.0 * zz - tr;
-  return bad;
 }
 
 __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
-    const uint64_t *__restrict__ keys, int64_t n, int nl, const uint32_t *__restrict__ cincl,
-    int64_t n_tiles, const double *__restrict__ box, const float *__restrict__ pos,
-    const float *__restrict__ mass, const int32_t *__restrict__ perm,
+    const uint64_t *__restrict__ keys, int64_t n, int nl, const uint32_t *__restrict__ excl,
+    int64_t n_tiles, const double *__restrict__ box, const float4 *__restrict__ sorted,
     uint64_t *__restrict__ cell_key, uint8_t *__restrict__ cell_level,
     int32_t *__restrict__ cell_first, int32_t *__restrict__ cell_count,
     int32_t *__restrict__ child_ptr, double *__restrict__ com, double *__restrict__ quad,
-    int64_t *__restrict__ level_offset, int64_t *__restrict__ n_cells, int64_t c_max,
-    int32_t *__restrict__ status_word, double *__restrict__ box_out,
-    float *__restrict__ pos_sorted, float *__restrict__ mass_sorted) {
+    int32_t *__restrict__ head_parent, int64_t *__restrict__ level_offset,
+    int64_t *__restrict__ n_cells, int64_t c_max, int32_t *__restrict__ status_word,
+    double *__restrict__ box_out) {
   extern __shared__ __align__(16) unsigned char lds[];
   const CellLds s = carve_lds(lds, nl, true);
   const int64_t tile = blockIdx.x;
   const int64_t t0 = tile * kCellTile;
   const int64_t t1 = min(t0 + (int64_t)kCellTile, n);
 
-  // per-depth base of this tile: level offset + prefix of earlier tiles
-  if (threadIdx.x == 0) {
+  // per-depth base of this tile: level offset + cells of earlier tiles
+  if (threadIdx.x < kLevels) {
+    const int d = threadIdx.x;
     uint32_t run = 0;
-    for (int d = 0; d < kLevels; ++d) {
-      const uint32_t tot = cincl[(n_tiles - 1) * kLevels + d];
-      const uint32_t before = tile > 0 ? cincl[(tile - 1) * kLevels + d] : 0u;
-      s.lvl[d] = run + before;
-      if (tile == 0) level_offset[d] = run;
-      run += tot;
-    }
+    for (int q = 0; q < d; ++q) run += excl[q * (n_tiles + 1) + n_tiles];
+    s.lvl[d] = run + excl[d * (n_tiles + 1) + tile];
     if (tile == 0) {
-      level_offset[kLevels] = run;
-      *n_cells = run;
-      if (box_out) {
-        box_out[0] = box[0];
-        box_out[1] = box[1];
-        box_out[2] = box[2];
-        box_out[3] = box[3];
+      level_offset[d] = run;
+      if (d == kLevels - 1) {
+        const uint32_t total = run + excl[d * (n_tiles + 1) + n_tiles];
+        level_offset[kLevels] = total;
+        *n_cells = total;
+        if (box_out) {
+          box_out[0] = box[0];
+          box_out[1] = box[1];
+          box_out[2] = box[2];
+          box_out[3] = box[3];
+        }
       }
     }
   }
+  // the tile's particles in key order plus the n_leaf halo, one batched load
+  const int span = (int)(min(t1 + (int64_t)nl, n) - t0);
+  {
+    constexpr int kRecBatch = (kCellTile + 32 + kCellThreads - 1) / kCellThreads;
+    for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
+      float4 r[kRecBatch];
+#pragma unroll
+      for (int u = 0; u < kRecBatch; ++u) {
+        const int x = x0 + u * kCellThreads + threadIdx.x;
+        r[u] = sorted[t0 + (x < span ? x : span - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < kRecBatch; ++u) {
+        const int x = x0 + u * kCellThreads + threadIdx.x;
+        if (x < span) s.rec[x] = r[u];
+      }
+    }
+  }
+  if (threadIdx.x == 0) *s.nleaf = 0;
+
   uint8_t A[kCellIpt], D[kCellIpt];
-  tile_depths(s, keys, n, nl, t0, t1, A, D);  // contains barriers after s.lvl is written
+  tile_depths(s, keys, n, nl, t0, t1, A, D);  // its barriers also publish s.lvl, s.rec
   uint32_t c[kLevelWords], tot[kLevelWords];
   thread_level_counts(A, D, c);
   block_level_scan(s, c, tot);
 #pragma unroll
-  for (int d = 0; d < kLevels; ++d) s.off[d * kCellThreads + threadIdx.x] = s.lvl[d] + unpack(c, d);
+  for (int d = 0; d < kLevels; ++d) s.off[d * kCellThreads + threadIdx.x] = (uint16_t)unpack(c, d);
+  // this thread's leaves go to a contiguous run of the leaf list
+  uint32_t my_leaves = 0;
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) my_leaves += (A[j] <= D[j]) ? 1u : 0u;
+  const uint32_t inc = wave_inclusive_scan(my_leaves);
+  uint32_t wave_base = 0;
+  if (lane_id() == 63) wave_base = atomicAdd(s.nleaf, inc);
+  wave_base = __shfl(wave_base, 63, 64);
+  uint32_t leaf_slot = wave_base + inc - my_leaves;
 
-  const double lo[3] = {box[0], box[1], box[2]};
-  const double side = box[3];
-  bool bad = false, internal = false;
+  // cell structure; leaves are queued for the moment phase
+  bool internal = false;
   for (int j = 0; j < kCellIpt; ++j) {
     const int a = A[j], dl = D[j];
     if (a > dl) continue;
-    const int64_t i = t0 + threadIdx.x * kCellIpt + j;
-    const uint64_t key = s.keys[(i - t0) + nl + 1];
+    const int li = threadIdx.x * kCellIpt + j;
+    const int64_t i = t0 + li;
+    const uint64_t key = s.keys[li + nl + 1];
     for (int d = a; d <= dl; ++d) {
-      const uint32_t ci = s.off[d * kCellThreads + threadIdx.x];
-      s.off[d * kCellThreads + threadIdx.x] = ci + 1;
+      const uint32_t rel = s.off[d * kCellThreads + threadIdx.x];
+      s.off[d * kCellThreads + threadIdx.x] = (uint16_t)(rel + 1);
+      const uint32_t ci = s.lvl[d] + rel;
       if ((int64_t)ci >= c_max) {  // cannot happen with consistent counts
         internal = true;
         continue;
@@ -400,49 +528,103 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
       cell_first[ci] = (int32_t)i;
       if (d < dl) {
         // first child: this particle's cell one depth down (emitted next)
-        const uint32_t fc = s.off[(d + 1) * kCellThreads + threadIdx.x];
-        child_ptr[2 * (int64_t)ci] = (int32_t)fc;
-        child_ptr[2 * (int64_t)ci + 1] = 0;
+        const uint32_t fc = s.lvl[d + 1] + s.off[(d + 1) * kCellThreads + threadIdx.x];
+        reinterpret_cast<int2 *>(child_ptr)[ci] = make_int2((int32_t)fc, 0);
+        if ((int64_t)fc < c_max) head_parent[fc] = (int32_t)ci;
       } else {
-        child_ptr[2 * (int64_t)ci] = -1;
-        child_ptr[2 * (int64_t)ci + 1] = 0;
-        const int64_t e = leaf_end(s, keys, n, nl, t0, i, dl);
-        cell_count[ci] = (int32_t)(e - i);
-        const double h = ldexp(side, -dl);
-        const int sh = kMaxDepth - dl;
-        const double off[3] = {((double)(compact3(key >> 2) >> sh) + 0.5) * h,
-                               ((double)(compact3(key >> 1) >> sh) + 0.5) * h,
-                               ((double)(compact3(key) >> sh) + 0.5) * h};
-        double cm[4], qd[6];
-        bad |= leaf_moments_fp64(pos, mass, perm, n, i, e, lo, off, cm, qd, pos_sorted, mass_sorted,
-                                 internal);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) com[4 * (int64_t)ci + q] = cm[q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) quad[6 * (int64_t)ci + q] = qd[q];
+        reinterpret_cast<int2 *>(child_ptr)[ci] = make_int2(-1, 0);
+        s.leaf_ci[leaf_slot] = ci;
+        s.leaf_tag[leaf_slot] = (uint16_t)(li | (dl << 11));
+        ++leaf_slot;
       }
     }
   }
-  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_MASS);
+  __syncthreads();
+
+  // leaf moments: one lane per leaf, particles read from LDS
+  const double lo[3] = {box[0], box[1], box[2]};
+  const double side = box[3];
+  const uint32_t nlv = *s.nleaf;
+  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
+    const uint32_t ci = s.leaf_ci[x];
+    const int li = s.leaf_tag[x] & 0x7ff;
+    const int dl = s.leaf_tag[x] >> 11;
+    const int64_t i = t0 + li;
+    const uint64_t key = s.keys[li + nl + 1];
+    const int64_t e = leaf_end(s, keys, n, nl, t0, i, dl);
+    cell_count[ci] = (int32_t)(e - i);
+    const double h = ldexp(side, -dl);
+    const int sh = kMaxDepth - dl;
+    const double off[3] = {((double)(compact3(key >> 2) >> sh) + 0.5) * h,
+                           ((double)(compact3(key >> 1) >> sh) + 0.5) * h,
+                           ((double)(compact3(key) >> sh) + 0.5) * h};
+    LeafSums acc = {0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+    const int64_t e_lds = min(e, t0 + (int64_t)span);
+    for (int64_t q = i; q < e_lds; ++q) leaf_add(acc, s.rec[q - t0], lo, off);
+    // only a saturated depth-21 leaf reaches past the staged halo
+    for (int64_t q = e_lds; q < e; ++q) leaf_add(acc, sorted[q], lo, off);
+    double cm[4], qd[6];
+    leaf_finish(acc, cm, qd);
+    double2 *cd = reinterpret_cast<double2 *>(com + 4 * (int64_t)ci);
+    cd[0] = make_double2(cm[0], cm[1]);
+    cd[1] = make_double2(cm[2], cm[3]);
+    double2 *qq = reinterpret_cast<double2 *>(quad + 6 * (int64_t)ci);
+    qq[0] = make_double2(qd[0], qd[1]);
+    qq[1] = make_double2(qd[2], qd[3]);
+    qq[2] = make_double2(qd[4], qd[5]);
+  }
   if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
-hipError_t launch_cell_count(const Plan &p, const Work &w, int32_t *out_status, hipStream_t s) {
+hipError_t launch_cell_count(const Plan &p, const Work &w, const float *pos, const float *mass,
+                             hipStream_t s) {
   const size_t lds = cell_lds_bytes(p.n_leaf, false);
   k_cell_count<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
-      sorted_keys(p, w), p.n, p.n_leaf, w.cell_status, w.cell_incl, w.counters + 32, p.cell_tiles,
-      out_status);
+      sorted_keys(p, w), p.n, p.n_leaf, p.cell_tiles, w.cell_cnt, pos, mass, w.packed);
   return hipGetLastError();
 }
 
-hipError_t launch_cell_emit(const Plan &p, const Work &w, const float *pos, const float *mass,
-                            const tb_tree &out, hipStream_t s) {
+hipError_t launch_cell_scan(const Plan &p, const Work &w, hipStream_t s) {
+  k_cell_scan<<<kLevels, kScanThreads, 0, s>>>(w.cell_cnt, p.cell_tiles, w.cell_excl);
+  return hipGetLastError();
+}
+
+hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
+  const int64_t per = (int64_t)kReorderThreads * kReorderIpt;
+  k_reorder<<<(unsigned)((p.n + per - 1) / per), kReorderThreads, 0, s>>>(
+      out.perm, w.packed, p.n, w.sorted, out.pos_sorted, out.mass_sorted, out.status);
+  return hipGetLastError();
+}
+
+// Largest dynamic LDS a workgroup may use on the current device (cached per
+// device), after opting the cell kernels in to it.
+size_t cell_lds_limit() {
+  static int cached_dev = -1;
+  static size_t cached = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (dev != cached_dev) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    const int want = (int)cell_lds_bytes(TB_MAX_NLEAF, true);
+    const int opt = v < want ? v : want;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, opt);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_count),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, opt);
+    cached = (size_t)v;
+    cached_dev = dev;
+  }
+  return cached;
+}
+
+hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
   const size_t lds = cell_lds_bytes(p.n_leaf, true);
   k_cell_emit<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
-      sorted_keys(p, w), p.n, p.n_leaf, w.cell_incl, p.cell_tiles, w.box, pos, mass, out.perm,
+      sorted_keys(p, w), p.n, p.n_leaf, w.cell_excl, p.cell_tiles, w.box, w.sorted,
       out.cell_key, out.cell_level, out.cell_first, out.cell_count, out.child_ptr,
-      static_cast<double *>(out.com), static_cast<double *>(out.quad), out.level_offset,
-      out.n_cells, p.c_max, out.status, out.box_out, out.pos_sorted, out.mass_sorted);
+      static_cast<double *>(out.com), static_cast<double *>(out.quad), w.head_parent,
+      out.level_offset, out.n_cells, p.c_max, out.status, out.box_out);
   return hipGetLastError();
 }
 

@@ -60,8 +60,11 @@ struct Plan {
   size_t counters;         // u32 [64] dynamic tile counters
   size_t box;              // f64 [4] the root box used by this build
   size_t bbox_part;        // f64 [kBboxBlocks][6] per-block min/max partials
-  size_t cell_status;      // u64 [cell_tiles][kLevels] lookback of per-level cell counts
-  size_t cell_incl;        // u32 [cell_tiles][kLevels] inclusive per-level prefix per tile
+  size_t cell_cnt;         // u32 [cell_tiles][kLevels] per-tile cell counts per depth
+  size_t cell_excl;        // u32 [cell_tiles + 1][kLevels] exclusive prefix over tiles, then totals
+  size_t packed;           // f32x4 [n] (x, y, z, m) records in original order
+  size_t sorted;           // f32x4 [n] the same records in key order
+  size_t head_parent;      // i32 [c_max] parent slot of every first child
   size_t total;
 };
 
@@ -81,8 +84,11 @@ struct Work {
   uint32_t *counters;
   double *box;
   double *bbox_part;
-  uint64_t *cell_status;
-  uint32_t *cell_incl;
+  uint32_t *cell_cnt;
+  uint32_t *cell_excl;
+  float4 *packed;
+  float4 *sorted;
+  int32_t *head_parent;
 };
 
 Work carve(const Plan &p, void *base);
@@ -103,9 +109,11 @@ hipError_t launch_empty(const tb_tree &out, const tb_box *box, hipStream_t s);
 hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tree &out,
                             hipStream_t s);
 // tb_cells.hip
-hipError_t launch_cell_count(const Plan &p, const Work &w, int32_t *out_status, hipStream_t s);
-hipError_t launch_cell_emit(const Plan &p, const Work &w, const float *pos, const float *mass,
-                            const tb_tree &out, hipStream_t s);
+hipError_t launch_cell_count(const Plan &p, const Work &w, const float *pos, const float *mass,
+                             hipStream_t s);
+hipError_t launch_cell_scan(const Plan &p, const Work &w, hipStream_t s);
+hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
+hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
 // tb_parents.hip
 hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
                           hipStream_t s);
@@ -151,6 +159,37 @@ __device__ inline uint64_t wait_published(const uint64_t *p, bool &timed_out) {
     sw = atomic_load_agent(p);
   }
   return sw;
+}
+
+// Exclusive prefix of column `col` over tiles [0, tile) by decoupled look-back:
+// every tile publishes its own count (aggregate) as soon as it has it and its
+// inclusive prefix once known; a successor sums predecessors' words backwards
+// until it meets an inclusive one.  W predecessor words are requested at once,
+// so a chain of aggregates costs one memory round trip per W tiles.
+template <int W>
+__device__ inline uint32_t lookback(const uint64_t *status, int64_t stride, int64_t tile, int col,
+                                    bool &timed_out) {
+  uint32_t excl = 0;
+  int64_t q = tile - 1;
+  while (q >= 0) {
+    uint64_t sw[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+      sw[k] = (q - k >= 0) ? atomic_load_agent(&status[(q - k) * stride + col]) : kFlagInclusive;
+    bool done = false;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      if (!done) {
+        uint64_t v = sw[k];
+        if ((v & kFlagMask) == 0) v = wait_published(&status[(q - k) * stride + col], timed_out);
+        excl += (uint32_t)v;
+        done = (v & kFlagMask) == kFlagInclusive;
+      }
+    }
+    if (done) break;
+    q -= W;
+  }
+  return excl;
 }
 
 // Minimum distinguished depth of two particle keys (Sec. 2.3.1): leading zeros

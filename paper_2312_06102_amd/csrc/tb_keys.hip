@@ -16,18 +16,18 @@ namespace tb {
 constexpr int kInitThreads = 256;
 constexpr int kKeygenThreads = 512;
 constexpr int kKeygenMaxBlocks = 512;
+constexpr int kKeygenIpt = 4;
 
 // ---------------------------------------------------------------------------
 // init
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kInitThreads) void k_init(
-    uint64_t *__restrict__ status0, int64_t n_status0, uint64_t *__restrict__ cell_status,
-    int64_t n_cell_status, uint32_t *__restrict__ counters, int32_t *__restrict__ status_word,
+    uint64_t *__restrict__ status0, int64_t n_status0, uint32_t *__restrict__ counters,
+    int32_t *__restrict__ status_word,
     double *__restrict__ box, int box_given, double lo0, double lo1, double lo2, double side) {
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < n_status0; i += stride) status0[i] = 0;
-  for (int64_t i = tid; i < n_cell_status; i += stride) cell_status[i] = 0;
   if (tid < 64) counters[tid] = 0;
   if (tid == 0) {
     *status_word = 0;
@@ -43,13 +43,10 @@ __global__ __launch_bounds__(kInitThreads) void k_init(
 hipError_t launch_init(const Plan &p, const Work &w, const tb_box *box, const tb_tree &out,
                        hipStream_t s) {
   const int64_t n0 = p.sort_tiles * (int64_t)p.sort.radix();
-  const int64_t n1 = p.cell_tiles * (int64_t)kLevels;
-  const int64_t work = n0 > n1 ? n0 : n1;
-  int blocks = (int)((work + kInitThreads - 1) / kInitThreads);
+  int blocks = (int)((n0 + kInitThreads - 1) / kInitThreads);
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  k_init<<<blocks, kInitThreads, 0, s>>>(w.status0, n0, w.cell_status, n1, w.counters,
-                                         out.status, w.box, box ? 1 : 0, box ? box->lo[0] : 0.0,
+  k_init<<<blocks, kInitThreads, 0, s>>>(w.status0, n0, w.counters, out.status, w.box, box ? 1 : 0, box ? box->lo[0] : 0.0,
                                          box ? box->lo[1] : 0.0, box ? box->lo[2] : 0.0,
                                          box ? box->side : 1.0);
   return hipGetLastError();
@@ -184,28 +181,43 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
   const double lo0 = box[0], lo1 = box[1], lo2 = box[2];
   const double scale = 2097152.0 / box[3];
   bool bad = false;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
-    const uint64_t qx = quantise(x, lo0, scale);
-    const uint64_t qy = quantise(y, lo1, scale);
-    const uint64_t qz = quantise(z, lo2, scale);
-    const uint64_t key =
-        (1ull << 63) | (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
-    keys[i] = key;
-    // digit histograms of every radix pass; a wave whose lanes all share the
-    // digit adds once (the upper digits of clustered data are mostly uniform)
-    const uint64_t active = __ballot(1);
+  // each step a thread handles kKeygenIpt particles whose loads are all issued
+  // before any is used (indices past the end are clamped and masked)
+  const int64_t step = (int64_t)gridDim.x * blockDim.x * kKeygenIpt;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kKeygenIpt + threadIdx.x; i0 < n;
+       i0 += step) {
+    float x[kKeygenIpt], y[kKeygenIpt], z[kKeygenIpt];
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) {
-      if (p < passes) {
-        const uint32_t d = (uint32_t)(key >> (p * BITS)) & (R - 1);
-        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-        if (__ballot(d == d0) == active) {
-          if (lane_id() == __ffsll((long long)active) - 1) atomicAdd(&h[p * R + d0], (uint32_t)__popcll(active));
-        } else {
-          atomicAdd(&h[p * R + d], 1u);
+    for (int r = 0; r < kKeygenIpt; ++r) {
+      const int64_t i = min(i0 + (int64_t)r * blockDim.x, n - 1);
+      x[r] = pos[3 * i + 0];
+      y[r] = pos[3 * i + 1];
+      z[r] = pos[3 * i + 2];
+    }
+#pragma unroll
+    for (int r = 0; r < kKeygenIpt; ++r) {
+      const int64_t i = i0 + (int64_t)r * blockDim.x;
+      const bool valid = i < n;
+      bad |= valid && !(isfinite(x[r]) && isfinite(y[r]) && isfinite(z[r]));
+      const uint64_t qx = quantise(x[r], lo0, scale);
+      const uint64_t qy = quantise(y[r], lo1, scale);
+      const uint64_t qz = quantise(z[r], lo2, scale);
+      const uint64_t key = (1ull << 63) | (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+      if (valid) keys[i] = key;
+      // digit histograms of every radix pass; a wave whose lanes all share the
+      // digit adds once (the upper digits of clustered data are mostly uniform)
+      const uint64_t active = __ballot(valid);
+      if (valid) {
+#pragma unroll
+        for (int p = 0; p < MAXP; ++p) {
+          const uint32_t d = (uint32_t)(key >> (p * BITS)) & (R - 1);
+          const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+          if (__ballot(d == d0) == active) {
+            if (lane_id() == __ffsll((long long)active) - 1)
+              atomicAdd(&h[p * R + d0], (uint32_t)__popcll(active));
+          } else {
+            atomicAdd(&h[p * R + d], 1u);
+          }
         }
       }
     }
@@ -216,20 +228,27 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
   for (int i = threadIdx.x; i < passes * R; i += blockDim.x) dst[i] = h[i];
 }
 
-// hist[c] = sum over rows b of part[b][c], for c < cols.
+// hist[c] = sum over rows b of part[b][c], for c < cols.  16 columns per
+// workgroup, 16 row groups per column, so each thread sums only rows/16 values.
 __global__ __launch_bounds__(256) void k_hist_reduce(const uint32_t *__restrict__ part, int rows,
                                                      int cols, uint32_t *__restrict__ hist) {
-  // 64 columns per workgroup, 4 row groups of 64 lanes
-  __shared__ uint32_t red[4][64];
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int g = threadIdx.x >> 6;
+  __shared__ uint32_t red[16][17];
+  const int col = threadIdx.x & 15;
+  const int g = threadIdx.x >> 4;
+  const int c = blockIdx.x * 16 + col;
   uint32_t s = 0;
   if (c < cols) {
-    for (int b = g; b < rows; b += 4) s += part[(int64_t)b * cols + c];
+#pragma unroll 8
+    for (int b = g; b < rows; b += 16) s += part[(int64_t)b * cols + c];
   }
-  red[g][threadIdx.x & 63] = s;
+  red[g][col] = s;
   __syncthreads();
-  if (g == 0 && c < cols) hist[c] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  if (threadIdx.x < 16 && c < cols) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += red[k][col];
+    hist[c] = t;
+  }
 }
 
 int keygen_blocks(int64_t n) {
@@ -256,7 +275,7 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const t
 
 hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s) {
   const int cols = p.sort.passes() * p.sort.radix();
-  k_hist_reduce<<<(cols + 63) / 64, 256, 0, s>>>(w.hist_part, keygen_blocks(p.n), cols, w.hist);
+  k_hist_reduce<<<(cols + 15) / 16, 256, 0, s>>>(w.hist_part, keygen_blocks(p.n), cols, w.hist);
   return hipGetLastError();
 }
 

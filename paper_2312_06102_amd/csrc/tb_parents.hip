@@ -7,10 +7,11 @@
 // paper notes, any higher multipole) is computed from its children once they
 // are all registered.  In the (depth, key)-ordered array the children of a
 // depth-d cell are one contiguous run at depth d+1, and the cell placement pass
-// already recorded each internal cell's first child.  One launch per depth:
-// every internal depth-d cell walks forward from its first child while the
-// child key, shifted right by three, equals its own key -- the same boundary
-// test Algorithm 2 applies -- and combines the children:
+// already recorded each internal cell's first child and, for that first child,
+// the slot of its parent.  One launch per depth: the depth-(d+1) cells are
+// staged through LDS in key order; a child whose key, shifted right by three,
+// differs from its predecessor's -- the boundary test of Algorithm 2 -- opens
+// the run of its siblings and combines them into their parent:
 //
 //   M   = sum M_c
 //   com = sum M_c (com_c + s_c) / M
@@ -23,76 +24,151 @@
 
 namespace tb {
 
+constexpr int kChunk = kParentThreads;  // children staged per workgroup step
+constexpr int kHalo = 7;                 // a parent has at most 8 children
+
 __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
     int depth, const int64_t *__restrict__ level_offset, const uint64_t *__restrict__ cell_key,
     int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr,
-    double *__restrict__ com, double *__restrict__ quad, const double *__restrict__ box) {
-  const int64_t L0 = level_offset[depth], L1 = level_offset[depth + 1];
-  const int64_t L2 = level_offset[depth + 2];
-  const double q = ldexp(box[3], -(depth + 2));  // a quarter of the parent side
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t pc = L0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; pc < L1; pc += stride) {
-    const int32_t fc = child_ptr[2 * pc];
-    if (fc < 0) continue;  // leaf
-    const uint64_t kp = cell_key[pc];
-    int64_t c1 = fc;
-    double M = 0, S[3] = {0, 0, 0};
-    int64_t cnt = 0;
-    while (c1 < L2 && c1 < fc + 8 && (cell_key[c1] >> 3) == kp) {
-      const uint32_t o = (uint32_t)(cell_key[c1] & 7u);
-      const double mc = com[4 * c1 + 3];
-      const double r0 = com[4 * c1 + 0] + ((o & 4u) ? q : -q);
-      const double r1 = com[4 * c1 + 1] + ((o & 2u) ? q : -q);
-      const double r2 = com[4 * c1 + 2] + ((o & 1u) ? q : -q);
-      M += mc;
-      S[0] += mc * r0;
-      S[1] += mc * r1;
-      S[2] += mc * r2;
-      cnt += cell_count[c1];
-      ++c1;
-    }
-    const double c0 = S[0] / M, cy = S[1] / M, cz = S[2] / M;
-    double Q[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t c = fc; c < c1; ++c) {
-      const uint32_t o = (uint32_t)(cell_key[c] & 7u);
-      const double mc = com[4 * c + 3];
-      const double d0 = com[4 * c + 0] + ((o & 4u) ? q : -q) - c0;
-      const double d1 = com[4 * c + 1] + ((o & 2u) ? q : -q) - cy;
-      const double d2 = com[4 * c + 2] + ((o & 1u) ? q : -q) - cz;
-      const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-      Q[0] += quad[6 * c + 0] + mc * (3.0 * d0 * d0 - dd);
-      Q[1] += quad[6 * c + 1] + mc * (3.0 * d0 * d1);
-      Q[2] += quad[6 * c + 2] + mc * (3.0 * d0 * d2);
-      Q[3] += quad[6 * c + 3] + mc * (3.0 * d1 * d1 - dd);
-      Q[4] += quad[6 * c + 4] + mc * (3.0 * d1 * d2);
-      Q[5] += quad[6 * c + 5] + mc * (3.0 * d2 * d2 - dd);
-    }
-    cell_count[pc] = (int32_t)cnt;
-    child_ptr[2 * pc + 1] = (int32_t)(c1 - fc);
-    com[4 * pc + 0] = c0;
-    com[4 * pc + 1] = cy;
-    com[4 * pc + 2] = cz;
-    com[4 * pc + 3] = M;
+    double *__restrict__ com, double *__restrict__ quad, const int32_t *__restrict__ head_parent,
+    const double *__restrict__ box, int32_t *__restrict__ status_word) {
+  __shared__ uint64_t s_key[kChunk + kHalo + 1];  // keys of [base - 1, base + kChunk + kHalo)
+  __shared__ int32_t s_cnt[kChunk + kHalo];
+  __shared__ __align__(16) double s_com[(kChunk + kHalo) * 4];
+  __shared__ __align__(16) double s_quad[(kChunk + kHalo) * 6];
+
+  const int64_t P0 = level_offset[depth], P1 = level_offset[depth + 1];
+  const int64_t L1 = P1, L2 = level_offset[depth + 2];  // the children at depth + 1
+  const double q = ldexp(box[3], -(depth + 2));          // a quarter of the parent side
+  bool internal = false;
+  for (int64_t base = L1 + (int64_t)blockIdx.x * kChunk; base < L2;
+       base += (int64_t)gridDim.x * kChunk) {
+    // stage the chunk: every load is issued before the first LDS store
+    const int64_t lim = min((int64_t)(kChunk + kHalo), L2 - base);
+    constexpr int KN = (kChunk + kHalo + 1 + kParentThreads - 1) / kParentThreads;
+    constexpr int CN = (kChunk + kHalo + kParentThreads - 1) / kParentThreads;
+    constexpr int MN = ((kChunk + kHalo) * 2 + kParentThreads - 1) / kParentThreads;
+    constexpr int QN = ((kChunk + kHalo) * 3 + kParentThreads - 1) / kParentThreads;
+    uint64_t kv[KN];
+    int32_t cv[CN];
+    double2 mv[MN], qv[QN];
+    const double2 *com2 = reinterpret_cast<const double2 *>(com) + 2 * base;
+    const double2 *quad2 = reinterpret_cast<const double2 *>(quad) + 3 * base;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) quad[6 * pc + k] = Q[k];
+    for (int r = 0; r < KN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      const int64_t c = base - 1 + x;
+      kv[r] = (x < kChunk + kHalo + 1 && c >= L1 && c < L2) ? cell_key[c] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < CN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      cv[r] = x < lim ? cell_count[base + x] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < MN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      mv[r] = x < 2 * lim ? com2[x] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < QN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      qv[r] = x < 3 * lim ? quad2[x] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < KN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      if (x < kChunk + kHalo + 1) s_key[x] = kv[r];  // 0 never matches a parent key
+    }
+#pragma unroll
+    for (int r = 0; r < CN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      if (x < lim) s_cnt[x] = cv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < MN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      if (x < 2 * lim) reinterpret_cast<double2 *>(s_com)[x] = mv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < QN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      if (x < 3 * lim) reinterpret_cast<double2 *>(s_quad)[x] = qv[r];
+    }
+    __syncthreads();
+
+    const int t = threadIdx.x;
+    const int64_t c = base + t;
+    const uint64_t kp = s_key[t + 1] >> 3;
+    // Algorithm 2's test: a child opens a new parent when its key >> 3 differs
+    // from the previous child's
+    if (c < L2 && (c == L1 || (s_key[t] >> 3) != kp)) {
+      const int64_t pc = head_parent[c];
+      int nch = 0;
+      while (nch < 8 && t + nch < lim && (s_key[t + nch + 1] >> 3) == kp) ++nch;
+      if (pc < P0 || pc >= P1) {
+        internal = true;
+      } else {
+        double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
+        int64_t cnt = 0;
+        for (int k = 0; k < nch; ++k) {
+          const int x = t + k;
+          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const double mc = s_com[4 * x + 3];
+          M += mc;
+          S0 += mc * (s_com[4 * x + 0] + ((o & 4u) ? q : -q));
+          S1 += mc * (s_com[4 * x + 1] + ((o & 2u) ? q : -q));
+          S2 += mc * (s_com[4 * x + 2] + ((o & 1u) ? q : -q));
+          cnt += s_cnt[x];
+        }
+        const double cx = S0 / M, cy = S1 / M, cz = S2 / M;
+        double Q[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < nch; ++k) {
+          const int x = t + k;
+          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const double mc = s_com[4 * x + 3];
+          const double d0 = s_com[4 * x + 0] + ((o & 4u) ? q : -q) - cx;
+          const double d1 = s_com[4 * x + 1] + ((o & 2u) ? q : -q) - cy;
+          const double d2 = s_com[4 * x + 2] + ((o & 1u) ? q : -q) - cz;
+          const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+          Q[0] += s_quad[6 * x + 0] + mc * (3.0 * d0 * d0 - dd);
+          Q[1] += s_quad[6 * x + 1] + mc * (3.0 * d0 * d1);
+          Q[2] += s_quad[6 * x + 2] + mc * (3.0 * d0 * d2);
+          Q[3] += s_quad[6 * x + 3] + mc * (3.0 * d1 * d1 - dd);
+          Q[4] += s_quad[6 * x + 4] + mc * (3.0 * d1 * d2);
+          Q[5] += s_quad[6 * x + 5] + mc * (3.0 * d2 * d2 - dd);
+        }
+        cell_count[pc] = (int32_t)cnt;
+        child_ptr[2 * pc + 1] = nch;
+        double2 *cd = reinterpret_cast<double2 *>(com + 4 * pc);
+        cd[0] = make_double2(cx, cy);
+        cd[1] = make_double2(cz, M);
+        double2 *qd = reinterpret_cast<double2 *>(quad + 6 * pc);
+        qd[0] = make_double2(Q[0], Q[1]);
+        qd[1] = make_double2(Q[2], Q[3]);
+        qd[2] = make_double2(Q[4], Q[5]);
+      }
+    }
+    __syncthreads();
   }
+  if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
 hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
                           hipStream_t s) {
-  (void)w;
-  // at most 8^depth cells at this depth
+  // at most 8^(depth+1) children one depth down
   int64_t bound = p.c_max;
-  if (depth < 10) {
-    const int64_t b8 = int64_t(1) << (3 * depth);
+  if (depth + 1 < 10) {
+    const int64_t b8 = int64_t(1) << (3 * (depth + 1));
     if (b8 < bound) bound = b8;
   }
-  int64_t blocks = (bound + kParentThreads - 1) / kParentThreads;
-  if (blocks > 2048) blocks = 2048;
+  int64_t blocks = (bound + kChunk - 1) / kChunk;
+  if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
   k_parents_fp64<<<(unsigned)blocks, kParentThreads, 0, s>>>(
       depth, out.level_offset, out.cell_key, out.cell_count, out.child_ptr,
-      static_cast<double *>(out.com), static_cast<double *>(out.quad), w.box);
+      static_cast<double *>(out.com), static_cast<double *>(out.quad), w.head_parent, w.box,
+      out.status);
   return hipGetLastError();
 }
 

@@ -4,7 +4,7 @@
 //   * every workgroup takes the next tile of keys (dynamic tile id, so all
 //     earlier tiles are already running and the look-back always progresses);
 //   * each wave ranks its keys with 64-lane ballots: for every digit bit a
-//     ballot, AND-ed into the mask of lanes holding the same digit, whose
+//     ballot, folded into the mask of lanes holding the same digit, whose
 //     population below the lane is the lane's rank among equal digits; items
 //     are processed in index order, so the ranking is stable;
 //   * per-wave digit counts are combined in LDS; the tile publishes its
@@ -39,70 +39,92 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *s_
   return off + inc - v;
 }
 
+// Digit of a 64-bit key at bit offset `shift` (uniform), from its two halves.
+template <int BITS>
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
+  const uint32_t lo = (uint32_t)k, hi = (uint32_t)(k >> 32);
+  const uint32_t w = shift < 32 ? __builtin_amdgcn_alignbit(hi, lo, (uint32_t)shift)
+                                : (hi >> (shift - 32));
+  return w & ((1u << BITS) - 1u);
+}
+
 template <int BITS, int IPT, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const uint64_t *__restrict__ kin, uint64_t *__restrict__ kout,
-    const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
     const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
-    int32_t *__restrict__ status_word, int64_t n_tiles) {
+    int32_t *__restrict__ status_word, uint32_t n_tiles) {
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
   constexpr int TILE = THREADS * IPT;
   constexpr int DPT = (R + THREADS - 1) / THREADS;  // digits per thread
-  constexpr uint32_t MASK = R - 1;
 
   __shared__ uint64_t s_keys[TILE];
   __shared__ uint32_t s_vals[TILE];
-  __shared__ uint32_t s_wc[WAVES * R];  // per-wave digit counters, then wave offsets
-  __shared__ uint32_t s_tstart[R];      // tile-local start of each digit
-  __shared__ int64_t s_goff[R];         // global position minus tile-local position
+  __shared__ uint32_t s_wc[WAVES * R];     // per-wave digit counters, then wave offsets
+  __shared__ uint32_t s_tstart[R];         // tile-local start of each digit
+  __shared__ int32_t s_goff[R];            // global position minus tile-local position
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
 
   if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+  // the global digit counts do not depend on the tile: fetch them meanwhile
+  uint32_t g[DPT];
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    g[t] = (d < R) ? hist[d] : 0u;
+  }
   for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
   __syncthreads();
-  const int64_t tile = s_tile;
+  const uint32_t tile = s_tile;
   if (tile >= n_tiles) {  // the counter was not reset: never true after k_init
     if (threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
     return;
   }
-  const int64_t base = tile * TILE;
+  const uint32_t base = tile * TILE;
   const int wv = threadIdx.x / 64;
   const int ln = lane_id();
   const uint64_t lt = lanemask_lt();
 
-  // wave-striped load: item j of lane l is key base + wv*64*IPT + j*64 + l
+  // wave-striped load: item j of lane l is key base + wv*64*IPT + j*64 + l.
+  // Loads are branch-free (indices past the end are clamped and the items
+  // masked later) so that all of them are in flight together.
   uint64_t k[IPT];
   uint32_t v[IPT];
   uint32_t rk[IPT];
-  const int64_t wbase = base + (int64_t)wv * 64 * IPT + ln;
+  const uint32_t wbase = base + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const int64_t idx = wbase + j * 64;
-    if (idx < n) {
-      k[j] = kin[idx];
-      v[j] = vin ? vin[idx] : (uint32_t)idx;
-    } else {
-      k[j] = 0;
-      v[j] = 0;
-    }
+  for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, n - 1u)];
+  if (vin) {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, n - 1u)];
+  } else {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
   }
 
-  // stable wave-level ranking
+  // Stable wave-level ranking: for every digit bit a ballot; XOR-ing the
+  // ballot with "all ones unless my bit is set" keeps exactly the lanes that
+  // agree with me on that bit, so the AND over all bits is the set of lanes
+  // holding my digit.  Its population below my lane is my rank among them.
   uint32_t *wc = s_wc + wv * R;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const bool valid = wbase + j * 64 < n;
-    const uint32_t d = (uint32_t)(k[j] >> shift) & MASK;
-    uint64_t peers = __ballot(valid);
+    const uint32_t d = digit_of<BITS>(k[j], shift);
+    const uint64_t vmask = __ballot(valid);
+    uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-      const bool bit = (d >> b) & 1u;
+      const uint32_t bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
+      const uint32_t flip = bit - 1u;  // 0 if my bit is set, all ones if clear
+      plo &= (uint32_t)bb ^ flip;
+      phi &= (uint32_t)(bb >> 32) ^ flip;
     }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
     const uint32_t pre = (uint32_t)__popcll(peers & lt);
     uint32_t cnt = 0;
     if (valid) cnt = wc[d];
@@ -124,19 +146,16 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
         s_wc[q * R + d] = run;
         run += c;
       }
-      atomic_store_agent(&status[tile * R + d],
+      atomic_store_agent(&status[(size_t)tile * R + d],
                          (tile == 0 ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
     }
     tcnt[t] = run;
   }
 
   // tile-local digit starts and global digit starts (block scans over digits)
-  uint32_t g[DPT];
   uint32_t tsum = 0, gsum = 0;
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
-    const int d = threadIdx.x * DPT + t;
-    g[t] = (d < R) ? hist[d] : 0u;
     tsum += tcnt[t];
     gsum += g[t];
   }
@@ -151,19 +170,14 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     if (d < R) {
       uint32_t excl = 0;
       if (tile > 0) {
-        int64_t q = tile - 1;
         bool timed_out = false;
-        while (true) {
-          const uint64_t sw = wait_published(&status[q * R + d], timed_out);
-          excl += (uint32_t)sw;
-          if ((sw & kFlagMask) == kFlagInclusive || q == 0) break;
-          --q;
-        }
+        excl = lookback<4>(status, R, tile, d, timed_out);
         if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
-        atomic_store_agent(&status[tile * R + d], kFlagInclusive | (uint64_t)(excl + tcnt[t]));
+        atomic_store_agent(&status[(size_t)tile * R + d],
+                           kFlagInclusive | (uint64_t)(excl + tcnt[t]));
       }
       s_tstart[d] = trun;
-      s_goff[d] = (int64_t)grun + excl - (int64_t)trun;
+      s_goff[d] = (int32_t)(grun + excl - trun);
     }
     trun += tcnt[t];
     grun += g[t];
@@ -174,25 +188,24 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     if (wbase + j * 64 < n) {
-      const uint32_t d = (uint32_t)(k[j] >> shift) & MASK;
+      const uint32_t d = digit_of<BITS>(k[j], shift);
       const uint32_t p = s_tstart[d] + wc[d] + rk[j];
       s_keys[p] = k[j];
       s_vals[p] = v[j];
     }
   }
   // the next pass's look-back words for this tile start cleared
-  for (int i = threadIdx.x; i < R; i += THREADS) status_next[tile * R + i] = 0;
+  for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
   __syncthreads();
 
   // coalesced scatter: consecutive lanes write consecutive slots of a digit run
-  const int64_t rem = n - base;
-  const int tile_n = rem < TILE ? (int)rem : TILE;
+  const uint32_t tile_n = (n - base) < (uint32_t)TILE ? (n - base) : (uint32_t)TILE;
   bool bad = false;
-  for (int i = threadIdx.x; i < tile_n; i += THREADS) {
+  for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
     const uint64_t key = s_keys[i];
-    const uint32_t d = (uint32_t)(key >> shift) & MASK;
-    const int64_t gp = s_goff[d] + i;
-    if (gp < 0 || gp >= n) {  // cannot happen with consistent histograms
+    const uint32_t d = digit_of<BITS>(key, shift);
+    const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
+    if (gp >= n) {  // cannot happen with consistent histograms
       bad = true;
       continue;
     }
@@ -215,9 +228,9 @@ static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb
   const uint32_t *vin = pass == 0 ? nullptr : V[pass % 2];
   const int R = 1 << BITS;
   k_onesweep<BITS, IPT, THREADS><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
-      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], p.n, pass * BITS,
+      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, pass * BITS,
       w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, out.status,
-      p.sort_tiles);
+      (uint32_t)p.sort_tiles);
   return hipGetLastError();
 }
 
@@ -228,19 +241,19 @@ hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tre
   if (c.bits == B && c.ipt == I && c.threads == T)                    \
     return launch_pass_t<B, I, T>(p, w, pass, out, s);
   TB_SORT_CASE(8, 16, 256)
-  TB_SORT_CASE(8, 12, 256)
-  TB_SORT_CASE(8, 8, 512)
   TB_SORT_CASE(9, 16, 256)
+  TB_SORT_CASE(8, 12, 256)
   TB_SORT_CASE(9, 12, 256)
-  TB_SORT_CASE(10, 16, 256)
-  TB_SORT_CASE(11, 16, 256)
+  TB_SORT_CASE(8, 8, 512)
+  TB_SORT_CASE(8, 8, 256)
+  TB_SORT_CASE(8, 12, 512)
 #undef TB_SORT_CASE
   return hipErrorInvalidValue;
 }
 
 bool sort_config_supported(const SortConfig &c) {
-  static const int table[][3] = {{8, 16, 256}, {8, 12, 256}, {8, 8, 512}, {9, 16, 256},
-                                 {9, 12, 256}, {10, 16, 256}, {11, 16, 256}};
+  static const int table[][3] = {{8, 16, 256}, {9, 16, 256}, {8, 12, 256}, {9, 12, 256},
+                                 {8, 8, 512},  {8, 8, 256},  {8, 12, 512}};
   for (const auto &r : table)
     if (r[0] == c.bits && r[1] == c.ipt && r[2] == c.threads) return true;
   return false;
