@@ -62,6 +62,7 @@ int make_plan(int64_t n, int32_t n_leaf, uint32_t flags, const SortConfig &sc, P
   p->packed = take(16 * (size_t)n);
   p->sorted = take(16 * (size_t)n);
   p->head_parent = take(4 * (size_t)p->c_max);
+  p->m_lo = take((flags & 0xffu) == TB_MIXED ? 4 * (size_t)p->c_max : 0);
   p->total = off;
   return TB_OK;
 }
@@ -84,6 +85,7 @@ Work carve(const Plan &p, void *base) {
   w.packed = reinterpret_cast<float4 *>(b + p.packed);
   w.sorted = reinterpret_cast<float4 *>(b + p.sorted);
   w.head_parent = reinterpret_cast<int32_t *>(b + p.head_parent);
+  w.m_lo = reinterpret_cast<float *>(b + p.m_lo);
   return w;
 }
 
@@ -177,7 +179,6 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t n_
   if (!pos || !mass || !out->perm || !out->cell_key || !out->cell_level || !out->cell_first ||
       !out->cell_count || !out->child_ptr || !out->com || !out->quad)
     return TB_ERR_ARG;
-  if ((flags & 0xffu) == TB_MIXED) return TB_ERR_ARG;  // not available yet
   Plan p;
   make_plan(n, n_leaf, flags, sc, &p);
   if (!workspace || ws_bytes < p.total) return TB_ERR_WORKSPACE;

@@ -434,15 +434,82 @@ __device__ __forceinline__ void leaf_finish(const LeafSums &a, double com[4], do
   quad[5] = 3.0 * zz - tr;
 }
 
+// ---- mixed precision: FP32 sums with Kahan compensation, in cell units ----
+__device__ __forceinline__ void kahan_add(float &sum, float &comp, float x) {
+  const float y = x - comp;
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
+}
+
+struct LeafSumsF {
+  float s[10], c[10];  // m, m u (3), m u u (6): sums and Kahan compensations
+};
+
+// One particle's contribution in units of the leaf side.  The offset from the
+// leaf centre is formed from the particle's quantised coordinate: FP64 only
+// recomputes t = fl64(x - lo) * 2^21 / side exactly as the key does; then
+// (q - base - half) is exact in FP32 and adding the fraction t - q rounds once.
+__device__ __forceinline__ void leaf_add_f(LeafSumsF &a, float4 rec, const double lo[3],
+                                           double scale, const uint32_t base[3], float half,
+                                           int dl) {
+  const float m = rec.w;
+  const float xv[3] = {rec.x, rec.y, rec.z};
+  float u[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double t = __dmul_rn(__dsub_rn((double)xv[k], lo[k]), scale);
+    double qd = floor(t);
+    if (!(qd >= 0.0)) qd = 0.0;  // also a NaN position (flagged by the key pass)
+    if (qd > 2097151.0) qd = 2097151.0;
+    const int32_t q = (int32_t)qd;
+    const float frac = (float)(t - qd);
+    const float r = ((float)(q - (int32_t)base[k]) - half) + frac;  // grid units
+    u[k] = ldexpf(r, dl - kMaxDepth);                                 // leaf units
+  }
+  kahan_add(a.s[0], a.c[0], m);
+  kahan_add(a.s[1], a.c[1], m * u[0]);
+  kahan_add(a.s[2], a.c[2], m * u[1]);
+  kahan_add(a.s[3], a.c[3], m * u[2]);
+  kahan_add(a.s[4], a.c[4], m * u[0] * u[0]);
+  kahan_add(a.s[5], a.c[5], m * u[0] * u[1]);
+  kahan_add(a.s[6], a.c[6], m * u[0] * u[2]);
+  kahan_add(a.s[7], a.c[7], m * u[1] * u[1]);
+  kahan_add(a.s[8], a.c[8], m * u[1] * u[2]);
+  kahan_add(a.s[9], a.c[9], m * u[2] * u[2]);
+}
+
+// com (in cell units), M, its compensation, and Q (cell units).
+__device__ __forceinline__ void leaf_finish_f(const LeafSumsF &a, float com[4], float &m_lo,
+                                              float quad[6]) {
+  const float M = a.s[0];
+  const float c0 = a.s[1] / M, c1 = a.s[2] / M, c2 = a.s[3] / M;
+  const float xx = a.s[4] - M * c0 * c0, xy = a.s[5] - M * c0 * c1, xz = a.s[6] - M * c0 * c2;
+  const float yy = a.s[7] - M * c1 * c1, yz = a.s[8] - M * c1 * c2, zz = a.s[9] - M * c2 * c2;
+  const float tr = xx + yy + zz;
+  com[0] = c0;
+  com[1] = c1;
+  com[2] = c2;
+  com[3] = M;
+  m_lo = -a.c[0];
+  quad[0] = 3.0f * xx - tr;
+  quad[1] = 3.0f * xy;
+  quad[2] = 3.0f * xz;
+  quad[3] = 3.0f * yy - tr;
+  quad[4] = 3.0f * yz;
+  quad[5] = 3.0f * zz - tr;
+}
+
+template <bool MIXED>
 __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     const uint64_t *__restrict__ keys, int64_t n, int nl, const uint32_t *__restrict__ excl,
     int64_t n_tiles, const double *__restrict__ box, const float4 *__restrict__ sorted,
     uint64_t *__restrict__ cell_key, uint8_t *__restrict__ cell_level,
     int32_t *__restrict__ cell_first, int32_t *__restrict__ cell_count,
-    int32_t *__restrict__ child_ptr, double *__restrict__ com, double *__restrict__ quad,
-    int32_t *__restrict__ head_parent, int64_t *__restrict__ level_offset,
-    int64_t *__restrict__ n_cells, int64_t c_max, int32_t *__restrict__ status_word,
-    double *__restrict__ box_out) {
+    int32_t *__restrict__ child_ptr, void *__restrict__ com_v, void *__restrict__ quad_v,
+    float *__restrict__ m_lo, int32_t *__restrict__ head_parent,
+    int64_t *__restrict__ level_offset, int64_t *__restrict__ n_cells, int64_t c_max,
+    int32_t *__restrict__ status_word, double *__restrict__ box_out) {
   extern __shared__ __align__(16) unsigned char lds[];
   const CellLds s = carve_lds(lds, nl, true);
   const int64_t tile = blockIdx.x;
@@ -553,25 +620,51 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     const uint64_t key = s.keys[li + nl + 1];
     const int64_t e = leaf_end(s, keys, n, nl, t0, i, dl);
     cell_count[ci] = (int32_t)(e - i);
-    const double h = ldexp(side, -dl);
     const int sh = kMaxDepth - dl;
-    const double off[3] = {((double)(compact3(key >> 2) >> sh) + 0.5) * h,
-                           ((double)(compact3(key >> 1) >> sh) + 0.5) * h,
-                           ((double)(compact3(key) >> sh) + 0.5) * h};
-    LeafSums acc = {0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+    const uint32_t ijk[3] = {compact3(key >> 2) >> sh, compact3(key >> 1) >> sh, compact3(key) >> sh};
     const int64_t e_lds = min(e, t0 + (int64_t)span);
-    for (int64_t q = i; q < e_lds; ++q) leaf_add(acc, s.rec[q - t0], lo, off);
-    // only a saturated depth-21 leaf reaches past the staged halo
-    for (int64_t q = e_lds; q < e; ++q) leaf_add(acc, sorted[q], lo, off);
-    double cm[4], qd[6];
-    leaf_finish(acc, cm, qd);
-    double2 *cd = reinterpret_cast<double2 *>(com + 4 * (int64_t)ci);
-    cd[0] = make_double2(cm[0], cm[1]);
-    cd[1] = make_double2(cm[2], cm[3]);
-    double2 *qq = reinterpret_cast<double2 *>(quad + 6 * (int64_t)ci);
-    qq[0] = make_double2(qd[0], qd[1]);
-    qq[1] = make_double2(qd[2], qd[3]);
-    qq[2] = make_double2(qd[4], qd[5]);
+    if constexpr (!MIXED) {
+      double *com = static_cast<double *>(com_v);
+      double *quad = static_cast<double *>(quad_v);
+      const double h = ldexp(side, -dl);
+      const double off[3] = {((double)ijk[0] + 0.5) * h, ((double)ijk[1] + 0.5) * h,
+                             ((double)ijk[2] + 0.5) * h};
+      LeafSums acc = {0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+      for (int64_t q = i; q < e_lds; ++q) leaf_add(acc, s.rec[q - t0], lo, off);
+      // only a saturated depth-21 leaf reaches past the staged halo
+      for (int64_t q = e_lds; q < e; ++q) leaf_add(acc, sorted[q], lo, off);
+      double cm[4], qd[6];
+      leaf_finish(acc, cm, qd);
+      double2 *cd = reinterpret_cast<double2 *>(com + 4 * (int64_t)ci);
+      cd[0] = make_double2(cm[0], cm[1]);
+      cd[1] = make_double2(cm[2], cm[3]);
+      double2 *qq = reinterpret_cast<double2 *>(quad + 6 * (int64_t)ci);
+      qq[0] = make_double2(qd[0], qd[1]);
+      qq[1] = make_double2(qd[2], qd[3]);
+      qq[2] = make_double2(qd[4], qd[5]);
+    } else {
+      float *com = static_cast<float *>(com_v);
+      float *quad = static_cast<float *>(quad_v);
+      const double scale = 2097152.0 / side;
+      const uint32_t base[3] = {ijk[0] << sh, ijk[1] << sh, ijk[2] << sh};
+      const float half = ldexpf(1.0f, sh - 1);
+      LeafSumsF acc;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) acc.s[k] = acc.c[k] = 0.0f;
+      for (int64_t q = i; q < e_lds; ++q) leaf_add_f(acc, s.rec[q - t0], lo, scale, base, half, dl);
+      for (int64_t q = e_lds; q < e; ++q) leaf_add_f(acc, sorted[q], lo, scale, base, half, dl);
+      float cm[4], qd[6], mlo;
+      leaf_finish_f(acc, cm, mlo, qd);
+      // stored in absolute units: scaling by the side (a power of two) is exact
+      const float l = ldexpf((float)side, -dl);
+      reinterpret_cast<float4 *>(com)[ci] = make_float4(cm[0] * l, cm[1] * l, cm[2] * l, cm[3]);
+      const float l2 = l * l;
+      float2 *qq = reinterpret_cast<float2 *>(quad + 6 * (int64_t)ci);
+      qq[0] = make_float2(qd[0] * l2, qd[1] * l2);
+      qq[1] = make_float2(qd[2] * l2, qd[3] * l2);
+      qq[2] = make_float2(qd[4] * l2, qd[5] * l2);
+      m_lo[ci] = mlo;
+    }
   }
   if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
@@ -608,7 +701,9 @@ size_t cell_lds_limit() {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
     const int want = (int)cell_lds_bytes(TB_MAX_NLEAF, true);
     const int opt = v < want ? v : want;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, opt);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, opt);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_count),
                               hipFuncAttributeMaxDynamicSharedMemorySize, opt);
@@ -620,11 +715,12 @@ size_t cell_lds_limit() {
 
 hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
   const size_t lds = cell_lds_bytes(p.n_leaf, true);
-  k_cell_emit<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
+  auto k = (p.flags & 0xffu) == TB_MIXED ? k_cell_emit<true> : k_cell_emit<false>;
+  k<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
       sorted_keys(p, w), p.n, p.n_leaf, w.cell_excl, p.cell_tiles, w.box, w.sorted,
-      out.cell_key, out.cell_level, out.cell_first, out.cell_count, out.child_ptr,
-      static_cast<double *>(out.com), static_cast<double *>(out.quad), w.head_parent,
-      out.level_offset, out.n_cells, p.c_max, out.status, out.box_out);
+      out.cell_key, out.cell_level, out.cell_first, out.cell_count, out.child_ptr, out.com,
+      out.quad, w.m_lo, w.head_parent, out.level_offset, out.n_cells, p.c_max, out.status,
+      out.box_out);
   return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct Plan {
   size_t packed;           // f32x4 [n] (x, y, z, m) records in original order
   size_t sorted;           // f32x4 [n] the same records in key order
   size_t head_parent;      // i32 [c_max] parent slot of every first child
+  size_t m_lo;             // f32 [c_max] compensation of each cell mass (mixed precision)
   size_t total;
 };
 
@@ -89,6 +90,7 @@ struct Work {
   float4 *packed;
   float4 *sorted;
   int32_t *head_parent;
+  float *m_lo;
 };
 
 Work carve(const Plan &p, void *base);

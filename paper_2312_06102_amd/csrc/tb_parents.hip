@@ -154,6 +154,149 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
   if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
+// Mixed precision: the same combination in FP32 with Kahan-compensated sums,
+// in units of the parent side (a child's frame maps to the parent's by an
+// exact halving and a shift of +-1/4).  The stored moments are in absolute
+// units; converting by powers of two is exact.  Each cell's mass also carries
+// its compensation term (m_lo) so that the mass stays correctly rounded at
+// every depth.
+__device__ __forceinline__ void kahan_add_p(float &sum, float &comp, float x) {
+  const float y = x - comp;
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
+}
+
+__global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
+    int depth, const int64_t *__restrict__ level_offset, const uint64_t *__restrict__ cell_key,
+    int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr,
+    float *__restrict__ com, float *__restrict__ quad, float *__restrict__ m_lo,
+    const int32_t *__restrict__ head_parent, const double *__restrict__ box,
+    int32_t *__restrict__ status_word) {
+  __shared__ uint64_t s_key[kChunk + kHalo + 1];
+  __shared__ int32_t s_cnt[kChunk + kHalo];
+  __shared__ float4 s_com[kChunk + kHalo];
+  __shared__ __align__(16) float s_quad[(kChunk + kHalo) * 6];
+  __shared__ float s_mlo[kChunk + kHalo];
+
+  const int64_t P0 = level_offset[depth], P1 = level_offset[depth + 1];
+  const int64_t L1 = P1, L2 = level_offset[depth + 2];
+  const float lc = ldexpf((float)box[3], -(depth + 1));  // child side
+  const float lp = 2.0f * lc;                            // parent side
+  const float inv_lc = 1.0f / lc, inv_lc2 = inv_lc * inv_lc;
+  bool internal = false;
+  for (int64_t base = L1 + (int64_t)blockIdx.x * kChunk; base < L2;
+       base += (int64_t)gridDim.x * kChunk) {
+    const int64_t lim = min((int64_t)(kChunk + kHalo), L2 - base);
+    constexpr int KN = (kChunk + kHalo + 1 + kParentThreads - 1) / kParentThreads;
+    constexpr int CN = (kChunk + kHalo + kParentThreads - 1) / kParentThreads;
+    constexpr int QN = ((kChunk + kHalo) * 3 + kParentThreads - 1) / kParentThreads;
+    uint64_t kv[KN];
+    int32_t cv[CN];
+    float4 mv[CN];
+    float lv[CN];
+    float2 qv[QN];
+    const float2 *quad2 = reinterpret_cast<const float2 *>(quad) + 3 * base;
+#pragma unroll
+    for (int r = 0; r < KN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      const int64_t c = base - 1 + x;
+      kv[r] = (x < kChunk + kHalo + 1 && c >= L1 && c < L2) ? cell_key[c] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < CN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      const int64_t c = base + (x < lim ? x : lim - 1);
+      cv[r] = cell_count[c];
+      mv[r] = reinterpret_cast<const float4 *>(com)[c];
+      lv[r] = m_lo[c];
+    }
+#pragma unroll
+    for (int r = 0; r < QN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      qv[r] = quad2[x < 3 * lim ? x : 3 * lim - 1];
+    }
+#pragma unroll
+    for (int r = 0; r < KN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      if (x < kChunk + kHalo + 1) s_key[x] = kv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < CN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      if (x < lim) {
+        s_cnt[x] = cv[r];
+        s_com[x] = mv[r];
+        s_mlo[x] = lv[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < QN; ++r) {
+      const int x = r * kParentThreads + threadIdx.x;
+      if (x < 3 * lim) reinterpret_cast<float2 *>(s_quad)[x] = qv[r];
+    }
+    __syncthreads();
+
+    const int t = threadIdx.x;
+    const int64_t c = base + t;
+    const uint64_t kp = s_key[t + 1] >> 3;
+    if (c < L2 && (c == L1 || (s_key[t] >> 3) != kp)) {
+      const int64_t pc = head_parent[c];
+      int nch = 0;
+      while (nch < 8 && t + nch < lim && (s_key[t + nch + 1] >> 3) == kp) ++nch;
+      if (pc < P0 || pc >= P1) {
+        internal = true;
+      } else {
+        float M = 0.f, Mc = 0.f, S[3] = {0.f, 0.f, 0.f}, Sc[3] = {0.f, 0.f, 0.f};
+        int64_t cnt = 0;
+        for (int k = 0; k < nch; ++k) {
+          const int x = t + k;
+          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const float4 cm = s_com[x];
+          const float up[3] = {0.5f * (cm.x * inv_lc) + ((o & 4u) ? 0.25f : -0.25f),
+                               0.5f * (cm.y * inv_lc) + ((o & 2u) ? 0.25f : -0.25f),
+                               0.5f * (cm.z * inv_lc) + ((o & 1u) ? 0.25f : -0.25f)};
+          kahan_add_p(M, Mc, cm.w);
+          kahan_add_p(M, Mc, s_mlo[x]);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) kahan_add_p(S[a], Sc[a], cm.w * up[a]);
+          cnt += s_cnt[x];
+        }
+        const float cx = S[0] / M, cy = S[1] / M, cz = S[2] / M;
+        float Q[6] = {0, 0, 0, 0, 0, 0}, Qc[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < nch; ++k) {
+          const int x = t + k;
+          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const float4 cm = s_com[x];
+          const float mc = cm.w;
+          const float d0 = 0.5f * (cm.x * inv_lc) + ((o & 4u) ? 0.25f : -0.25f) - cx;
+          const float d1 = 0.5f * (cm.y * inv_lc) + ((o & 2u) ? 0.25f : -0.25f) - cy;
+          const float d2 = 0.5f * (cm.z * inv_lc) + ((o & 1u) ? 0.25f : -0.25f) - cz;
+          const float dd = d0 * d0 + d1 * d1 + d2 * d2;
+          const float qs = 0.25f * inv_lc2;  // child units -> parent units
+          kahan_add_p(Q[0], Qc[0], s_quad[6 * x + 0] * qs + mc * (3.0f * d0 * d0 - dd));
+          kahan_add_p(Q[1], Qc[1], s_quad[6 * x + 1] * qs + mc * (3.0f * d0 * d1));
+          kahan_add_p(Q[2], Qc[2], s_quad[6 * x + 2] * qs + mc * (3.0f * d0 * d2));
+          kahan_add_p(Q[3], Qc[3], s_quad[6 * x + 3] * qs + mc * (3.0f * d1 * d1 - dd));
+          kahan_add_p(Q[4], Qc[4], s_quad[6 * x + 4] * qs + mc * (3.0f * d1 * d2));
+          kahan_add_p(Q[5], Qc[5], s_quad[6 * x + 5] * qs + mc * (3.0f * d2 * d2 - dd));
+        }
+        cell_count[pc] = (int32_t)cnt;
+        child_ptr[2 * pc + 1] = nch;
+        reinterpret_cast<float4 *>(com)[pc] = make_float4(cx * lp, cy * lp, cz * lp, M);
+        const float lp2 = lp * lp;
+        float2 *qd = reinterpret_cast<float2 *>(quad + 6 * pc);
+        qd[0] = make_float2(Q[0] * lp2, Q[1] * lp2);
+        qd[1] = make_float2(Q[2] * lp2, Q[3] * lp2);
+        qd[2] = make_float2(Q[4] * lp2, Q[5] * lp2);
+        m_lo[pc] = -Mc;
+      }
+    }
+    __syncthreads();
+  }
+  if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
+}
+
 hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
                           hipStream_t s) {
   // at most 8^(depth+1) children one depth down
@@ -165,10 +308,16 @@ hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree
   int64_t blocks = (bound + kChunk - 1) / kChunk;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  k_parents_fp64<<<(unsigned)blocks, kParentThreads, 0, s>>>(
-      depth, out.level_offset, out.cell_key, out.cell_count, out.child_ptr,
-      static_cast<double *>(out.com), static_cast<double *>(out.quad), w.head_parent, w.box,
-      out.status);
+  if ((p.flags & 0xffu) == TB_MIXED)
+    k_parents_mixed<<<(unsigned)blocks, kParentThreads, 0, s>>>(
+        depth, out.level_offset, out.cell_key, out.cell_count, out.child_ptr,
+        static_cast<float *>(out.com), static_cast<float *>(out.quad), w.m_lo, w.head_parent,
+        w.box, out.status);
+  else
+    k_parents_fp64<<<(unsigned)blocks, kParentThreads, 0, s>>>(
+        depth, out.level_offset, out.cell_key, out.cell_count, out.child_ptr,
+        static_cast<double *>(out.com), static_cast<double *>(out.quad), w.head_parent, w.box,
+        out.status);
   return hipGetLastError();
 }
 

@@ -194,6 +194,49 @@ def test_auto_box():
 
 
 # --------------------------------------------------------------------------
+# mixed precision: FP32 + Kahan moments against the FP64 oracle
+# --------------------------------------------------------------------------
+
+MIXED_TOL = 1e-6
+
+
+def mixed_parity(pos, mass, n_leaf, lo=(0.0, 0.0, 0.0), side=1.0):
+    o = oracle.build(pos, mass, n_leaf, lo=lo, side=side)
+    g = gpu_build(pos, mass, n_leaf, box=(lo, side), precision="mixed")
+    compare_structure(g, o)  # the tree does not depend on the moment precision
+    assert g["com"].dtype == np.float32 and g["quad"].dtype == np.float32
+    em, ec, eq = moment_errors(g["com"].astype(np.float64), g["quad"].astype(np.float64),
+                               o["com"], o["quad"], o["cell_level"], side)
+    print(f"[mixed] N={pos.shape[0]} max rel err M={em:.2e} com={ec:.2e} Q={eq:.2e}", flush=True)
+    assert em <= MIXED_TOL and ec <= MIXED_TOL and eq <= MIXED_TOL, (em, ec, eq)
+    return em, ec, eq
+
+
+def test_mixed_uniform64k():
+    pos, mass, nl = dg.workload("uniform64k")
+    mixed_parity(pos, mass, nl)
+
+
+def test_mixed_plummer():
+    pos, mass = dg.plummer(200000, seed=21)
+    mixed_parity(pos, mass, 16)
+
+
+def test_mixed_clustered_lognormal():
+    pos, mass = dg.clustered(200000, seed=5, n_halos=200, masses="lognormal")
+    mixed_parity(pos, mass, 8)
+
+
+def test_mixed_nonunit_box_and_duplicates():
+    rng = _rng(22)
+    base = (rng.standard_normal((3000, 3)) * 5.0).astype(np.float32)
+    pos = np.repeat(base, rng.integers(1, 12, 3000), axis=0)
+    pos = np.clip(pos, -31, 31)
+    mass = (rng.random(pos.shape[0]) + 0.01).astype(np.float32)
+    mixed_parity(pos, mass, 4, lo=(-32.0, -32.0, -32.0), side=64.0)
+
+
+# --------------------------------------------------------------------------
 # determinism and options
 # --------------------------------------------------------------------------
 
