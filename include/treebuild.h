@@ -83,6 +83,8 @@ extern "C" {
 #define TB_STATUS_NONFINITE 1
 #define TB_STATUS_MASS 2
 #define TB_STATUS_INTERNAL 4 /* an index computed on the device fell out of range */
+#define TB_STATUS_SETS 8     /* batch set offsets not 0 .. n_total and non-decreasing */
+#define TB_STATUS_BOX 16     /* a batch box (device memory) failed the tb_box rules     */
 
 /* Precision flags (bits 0..7). */
 #define TB_FP64 0u
@@ -153,6 +155,59 @@ int tb_build_sync(const float *pos, const float *mass, int64_t n, int32_t n_leaf
                   const tb_tree *out, void *stream);
 
 /* ------------------------------------------------------------------------- */
+/* Batched builds: B independent particle sets in one sequence of launches.
+ *
+ * The sets are stored back to back: set b owns input particles
+ * [set_offsets[b], set_offsets[b+1]) of pos / mass.  Each set gets its own tree,
+ * exactly the tree tb_build() would give for that set alone (Sec. 2.3 applied
+ * per set); the trees share the output arrays as follows:
+ *   perm           set b's sorted positions are the same range
+ *                  [set_offsets[b], set_offsets[b+1]); perm values stay global
+ *                  input indices inside that range
+ *   cells          set b's cells are the contiguous block
+ *                  [cell_offsets[b], cell_offsets[b+1]), in (depth, key) order
+ *                  within the block; cell_first and child_ptr hold global
+ *                  sorted positions and global cell indices
+ *   level_offset   [B][23]: row b = global first cell of each depth of set b,
+ *                  [b][22] = cell_offsets[b+1]
+ *   n_cells        total over all sets
+ *   box_out        [B][4] or NULL
+ * A set may be empty (no cells).  C_max = tb_max_cells(n_total, n_leaf) bounds
+ * the total number of cells.
+ *
+ *   nsets        B, 1 .. TB_MAX_SETS
+ *   set_offsets  [B+1] int64, DEVICE; 0 = set_offsets[0] <= ... <= set_offsets[B]
+ *                = n_total.  Offsets that break this are reported on the device
+ *                (TB_STATUS_SETS); the build then proceeds as one set, so no
+ *                kernel reads outside [0, n_total).
+ *   boxes        [B] tb_box, DEVICE, or NULL = each set's box from its own data
+ *                (as tb_build() with box NULL).  A box that breaks the tb_box
+ *                rules is reported (TB_STATUS_BOX) and replaced by the unit cube.
+ *   cell_offsets [B+1] int64, DEVICE, or NULL.
+ * Other arguments as tb_build(); the workspace size comes from
+ * tb_workspace_bytes_batched().  A batch performs no host/device
+ * synchronisation, so the whole batch may be captured into one hipGraph.
+ * Errors (synchronous): TB_ERR_ARG (also nsets outside 1..TB_MAX_SETS or
+ * set_offsets NULL), TB_ERR_WORKSPACE, TB_ERR_HIP. */
+#define TB_MAX_SETS 16383
+
+int tb_workspace_bytes_batched(int64_t n_total, int32_t nsets, int32_t n_leaf, uint32_t flags,
+                               size_t *bytes);
+
+int tb_build_batched(const float *pos, const float *mass, int64_t n_total, int32_t nsets,
+                     const int64_t *set_offsets, int32_t n_leaf, const tb_box *boxes,
+                     uint32_t flags, void *workspace, size_t ws_bytes, const tb_tree *out,
+                     int64_t *cell_offsets, void *stream);
+
+/* tb_build_batched() followed by a stream synchronisation and a read of the
+ * status word: TB_ERR_NONFINITE, TB_ERR_MASS, TB_ERR_ARG (TB_STATUS_SETS) or
+ * TB_ERR_BOX (TB_STATUS_BOX) if the kernels flagged the data. */
+int tb_build_batched_sync(const float *pos, const float *mass, int64_t n_total, int32_t nsets,
+                          const int64_t *set_offsets, int32_t n_leaf, const tb_box *boxes,
+                          uint32_t flags, void *workspace, size_t ws_bytes, const tb_tree *out,
+                          int64_t *cell_offsets, void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Kernel timing.  When enabled, every kernel launch of a build is bracketed by
  * HIP events recorded on the build's stream; the per-kernel durations are
  * summed when tb_trace_read() is called (which synchronises on the events).
@@ -172,7 +227,7 @@ int tb_trace_read(tb_trace_entry *out, int cap, int *count);
  * *count (the table size) is written. */
 int tb_sort_configs(int32_t *desc, int cap, int *count);
 
-/* Library version string, e.g. "treebuild 0.1 gfx950". */
+/* Library version string, e.g. "treebuild 0.2 gfx950". */
 const char *tb_version(void);
 
 #ifdef __cplusplus

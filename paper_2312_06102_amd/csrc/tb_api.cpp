@@ -1,5 +1,7 @@
 // tb_api.cpp -- the C ABI of include/treebuild.h: argument checks, workspace
-// plan, the fixed launch sequence of one build, and kernel timing.
+// plan, the fixed launch sequence of a build or a batch of builds, and
+// kernel timing.
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -11,10 +13,6 @@
 
 namespace tb {
 
-bool sort_config_supported(const SortConfig &c);
-size_t cell_emit_lds(int nl);
-size_t cell_lds_limit();
-
 // Table of sort shapes selectable through TB_SORT_CONFIG(k); entry 0 is the default.
 static const SortConfig kSortTable[] = {
     {8, 8, 512},  {8, 16, 256}, {9, 16, 256}, {8, 12, 256},
@@ -24,23 +22,34 @@ static const int kSortTableSize = (int)(sizeof(kSortTable) / sizeof(kSortTable[0
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-SortConfig default_sort_config(int64_t) { return kSortTable[0]; }
+// Internal plan flag: the root boxes are derived from the data.
+constexpr uint32_t kAutoBoxFlag = 0x10000u;
 
 static int64_t max_cells(int64_t n, int32_t n_leaf) {
   if (n <= 0) return 0;
   return n + (int64_t)kMaxDepth * (n / ((int64_t)n_leaf + 1));
 }
 
-int make_plan(int64_t n, int32_t n_leaf, uint32_t flags, const SortConfig &sc, Plan *p) {
+int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const SortConfig &sc,
+              Plan *p) {
   std::memset(p, 0, sizeof(*p));
   p->n = n;
   p->n_leaf = n_leaf;
   p->flags = flags;
+  p->nsets = nsets;
   p->sort = sc;
+  p->key_passes = sc.passes();
+  p->set_passes = 0;  // digits of the set id: 0 for a single set
+  for (int64_t span = 1; span < nsets; span <<= sc.bits) ++p->set_passes;
   p->sort_tiles = (n + sc.tile() - 1) / sc.tile();
-  p->cell_tiles = (n + kCellTile - 1) / kCellTile;
+  // tiles never straddle two sets: at most one partial tile per set
+  p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;
+  p->bbox_chunks = (flags & kAutoBoxFlag) ? (n + kBboxChunk - 1) / kBboxChunk + nsets : 1;
+  // a set of n_b particles has at most n_b + 21 floor(n_b / (n_leaf + 1)) cells,
+  // and the sum over the sets is bounded by the same expression of n
   p->c_max = max_cells(n, n_leaf);
-  const int P = sc.passes(), R = sc.radix();
+  const int P = p->key_passes + p->set_passes, R = sc.radix();
+  const size_t B1 = (size_t)nsets + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -51,14 +60,23 @@ int make_plan(int64_t n, int32_t n_leaf, uint32_t flags, const SortConfig &sc, P
   p->keys1 = take(8 * (size_t)n);
   p->vals1 = take(4 * (size_t)n);
   p->hist = take(4 * (size_t)P * R);
-  p->hist_part = take(4 * (size_t)keygen_blocks(n) * P * R);
+  p->hist_part = take(4 * (size_t)keygen_blocks(n) * p->key_passes * R);
   p->status0 = take(8 * (size_t)p->sort_tiles * R);
   p->status1 = take(8 * (size_t)p->sort_tiles * R);
   p->counters = take(4 * 64);
-  p->box = take(8 * 4);
-  p->bbox_part = take(8 * 6 * (size_t)kBboxBlocks);
+  p->set_off = take(8 * B1);
+  p->box = take(8 * 4 * (size_t)nsets);
+  p->bbox_part = take(8 * 6 * (size_t)p->bbox_chunks);
+  p->chunk_start = take(8 * B1);
+  p->chunk_set = take(4 * (size_t)p->bbox_chunks);
+  p->tile_start = take(8 * B1);
+  p->tile_set = take(4 * (size_t)p->cell_tiles);
   p->cell_cnt = take(4 * (size_t)p->cell_tiles * kLevels);
-  p->cell_excl = take(4 * (size_t)(p->cell_tiles + 1) * kLevels);
+  p->cell_excl = take(4 * (size_t)p->cell_tiles * kLevels);
+  p->set_tot = take(4 * (size_t)nsets * kLevels);
+  p->set_cells = take(8 * B1);
+  p->lvl_off = take(8 * (size_t)nsets * (kLevels + 1));
+  p->par_start = take(8 * (size_t)kLevels * B1);
   p->packed = take(16 * (size_t)n);
   p->sorted = take(16 * (size_t)n);
   p->head_parent = take(4 * (size_t)p->c_max);
@@ -78,10 +96,19 @@ Work carve(const Plan &p, void *base) {
   w.status0 = reinterpret_cast<uint64_t *>(b + p.status0);
   w.status1 = reinterpret_cast<uint64_t *>(b + p.status1);
   w.counters = reinterpret_cast<uint32_t *>(b + p.counters);
+  w.set_off = reinterpret_cast<int64_t *>(b + p.set_off);
   w.box = reinterpret_cast<double *>(b + p.box);
   w.bbox_part = reinterpret_cast<double *>(b + p.bbox_part);
+  w.chunk_start = reinterpret_cast<int64_t *>(b + p.chunk_start);
+  w.chunk_set = reinterpret_cast<int32_t *>(b + p.chunk_set);
+  w.tile_start = reinterpret_cast<int64_t *>(b + p.tile_start);
+  w.tile_set = reinterpret_cast<int32_t *>(b + p.tile_set);
   w.cell_cnt = reinterpret_cast<uint32_t *>(b + p.cell_cnt);
   w.cell_excl = reinterpret_cast<uint32_t *>(b + p.cell_excl);
+  w.set_tot = reinterpret_cast<uint32_t *>(b + p.set_tot);
+  w.set_cells = reinterpret_cast<int64_t *>(b + p.set_cells);
+  w.lvl_off = reinterpret_cast<int64_t *>(b + p.lvl_off);
+  w.par_start = reinterpret_cast<int64_t *>(b + p.par_start);
   w.packed = reinterpret_cast<float4 *>(b + p.packed);
   w.sorted = reinterpret_cast<float4 *>(b + p.sorted);
   w.head_parent = reinterpret_cast<int32_t *>(b + p.head_parent);
@@ -134,8 +161,10 @@ static int flush_trace() {
 // ---------------------------------------------------------------------------
 // argument checks
 // ---------------------------------------------------------------------------
+// positive, finite, normal power of two (the same test the device applies to
+// boxes it receives)
 static bool is_pow2(double side) {
-  if (!(side > 0.0) || !std::isfinite(side)) return false;
+  if (!(side >= DBL_MIN) || !std::isfinite(side)) return false;
   int e;
   return std::frexp(side, &e) == 0.5;
 }
@@ -157,22 +186,27 @@ static int config_from_flags(uint32_t flags, SortConfig *sc) {
   return sort_config_supported(*sc) ? TB_OK : TB_ERR_ARG;
 }
 
-static int build_impl(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
-                      const tb_box *box, uint32_t flags, void *workspace, size_t ws_bytes,
-                      const tb_tree *out, hipStream_t s) {
+static bool box_ok(const tb_box &b) {
+  return std::isfinite(b.lo[0]) && std::isfinite(b.lo[1]) && std::isfinite(b.lo[2]) &&
+         is_pow2(b.side);
+}
+
+// The launch sequence of one batch of nsets sets; a single build is nsets == 1.
+static int build_impl(const float *pos, const float *mass, int64_t n, int32_t nsets,
+                      int32_t n_leaf, const BatchIn &in, uint32_t flags, void *workspace,
+                      size_t ws_bytes, const tb_tree *out, int64_t *cell_offsets,
+                      hipStream_t s) {
   int rc = check_sizes(n, n_leaf);
   if (rc) return rc;
+  if (nsets < 1 || nsets > kMaxSetsLds) return TB_ERR_ARG;
   SortConfig sc;
   rc = config_from_flags(flags, &sc);
   if (rc) return rc;
   if (!out || !out->level_offset || !out->n_cells || !out->status) return TB_ERR_ARG;
-  if (box) {
-    if (!std::isfinite(box->lo[0]) || !std::isfinite(box->lo[1]) || !std::isfinite(box->lo[2]) ||
-        !is_pow2(box->side))
-      return TB_ERR_BOX;
-  }
+  if (in.host_box && !box_ok(*in.host_box)) return TB_ERR_BOX;
   if (n == 0) {
-    return traced("empty", s, [&] { return launch_empty(*out, box, s); }) == hipSuccess
+    return traced("empty", s, [&] { return launch_empty(*out, nsets, in, cell_offsets, s); }) ==
+                   hipSuccess
                ? TB_OK
                : TB_ERR_HIP;
   }
@@ -180,7 +214,7 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t n_
       !out->cell_count || !out->child_ptr || !out->com || !out->quad)
     return TB_ERR_ARG;
   Plan p;
-  make_plan(n, n_leaf, flags, sc, &p);
+  make_plan(n, nsets, n_leaf, flags | (in.auto_box ? kAutoBoxFlag : 0u), sc, &p);
   if (!workspace || ws_bytes < p.total) return TB_ERR_WORKSPACE;
   // the cell kernels stage a tile plus an n_leaf halo in LDS
   if (cell_emit_lds(n_leaf) > cell_lds_limit()) return TB_ERR_ARG;
@@ -190,24 +224,39 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t n_
   auto run = [&](const char *name, auto &&f) {
     if (e == hipSuccess) e = traced(name, s, f);
   };
-  run("init", [&] { return launch_init(p, w, box, *out, s); });
-  if (!box) run("bbox", [&] { return launch_bbox(p, w, pos, s); });
-  run("keygen", [&] { return launch_keygen(p, w, pos, *out, s); });
+  run("init", [&] { return launch_init(p, w, in, *out, s); });
+  run("setup", [&] { return launch_setup(p, w, in.auto_box, in.dev_boxes != nullptr, out->status, s); });
+  if (in.auto_box) run("bbox", [&] { return launch_bbox(p, w, pos, s); });
+  run("keygen", [&] { return launch_keygen(p, w, pos, mass, *out, s); });
   run("hist_reduce", [&] { return launch_hist_reduce(p, w, s); });
-  for (int pass = 0; pass < p.sort.passes(); ++pass)
-    run("sort_pass", [&] { return launch_sort_pass(p, w, pass, *out, s); });
-  run("cell_count", [&] { return launch_cell_count(p, w, pos, mass, s); });
-  run("cell_scan", [&] { return launch_cell_scan(p, w, s); });
+  for (int pass = 0; pass < p.key_passes + p.set_passes; ++pass)
+    run(pass < p.key_passes ? "sort_pass" : "set_pass",
+        [&] { return launch_sort_pass(p, w, pass, *out, s); });
+  run("cell_count", [&] { return launch_cell_count(p, w, s); });
+  run("cell_scan", [&] { return launch_cell_scan(p, w, *out, cell_offsets, s); });
   run("reorder", [&] { return launch_reorder(p, w, *out, s); });
   run("cell_emit", [&] { return launch_cell_emit(p, w, *out, s); });
   for (int d = kMaxDepth - 1; d >= 0; --d)
     run("parents", [&] { return launch_parents(p, w, d, *out, s); });
-  if (out->key_sorted)
-    run("copy_keys", [&] {
-      return hipMemcpyAsync(out->key_sorted, sorted_keys(p, w), 8 * (size_t)n,
-                            hipMemcpyDeviceToDevice, s);
-    });
+  if (out->key_sorted) run("copy_keys", [&] { return launch_copy_keys(p, w, *out, s); });
   return e == hipSuccess ? TB_OK : TB_ERR_HIP;
+}
+
+static int status_code(int32_t status) {
+  if (status & TB_STATUS_NONFINITE) return TB_ERR_NONFINITE;
+  if (status & TB_STATUS_MASS) return TB_ERR_MASS;
+  if (status & TB_STATUS_SETS) return TB_ERR_ARG;
+  if (status & TB_STATUS_BOX) return TB_ERR_BOX;
+  if (status & TB_STATUS_INTERNAL) return TB_ERR_INTERNAL;
+  return TB_OK;
+}
+
+static int wait_status(const tb_tree *out, hipStream_t s) {
+  int32_t status = 0;
+  if (hipMemcpyAsync(&status, out->status, sizeof(status), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return TB_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TB_ERR_HIP;
+  return status_code(status);
 }
 
 }  // namespace tb
@@ -225,43 +274,63 @@ int tb_max_cells(int64_t n, int32_t n_leaf, int64_t *c_max) {
   return TB_OK;
 }
 
-int tb_workspace_bytes(int64_t n, int32_t n_leaf, uint32_t flags, size_t *bytes) {
+int tb_workspace_bytes_batched(int64_t n_total, int32_t nsets, int32_t n_leaf, uint32_t flags,
+                               size_t *bytes) {
   if (!bytes) return TB_ERR_ARG;
-  int rc = tb::check_sizes(n, n_leaf);
+  int rc = tb::check_sizes(n_total, n_leaf);
   if (rc) return rc;
+  if (nsets < 1 || nsets > tb::kMaxSetsLds) return TB_ERR_ARG;
   tb::SortConfig sc;
   rc = tb::config_from_flags(flags, &sc);
   if (rc) return rc;
-  if (n == 0) {
+  if (n_total == 0) {
     *bytes = 0;
     return TB_OK;
   }
+  // sized for data-derived boxes, so one workspace serves both kinds of call
   tb::Plan p;
-  tb::make_plan(n, n_leaf, flags, sc, &p);
+  tb::make_plan(n_total, nsets, n_leaf, flags | tb::kAutoBoxFlag, sc, &p);
   *bytes = p.total;
   return TB_OK;
 }
 
+int tb_workspace_bytes(int64_t n, int32_t n_leaf, uint32_t flags, size_t *bytes) {
+  return tb_workspace_bytes_batched(n, 1, n_leaf, flags, bytes);
+}
+
 int tb_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, const tb_box *box,
              uint32_t flags, void *workspace, size_t ws_bytes, const tb_tree *out, void *stream) {
-  return tb::build_impl(pos, mass, n, n_leaf, box, flags, workspace, ws_bytes, out,
+  const tb::BatchIn in{nullptr, box, nullptr, box == nullptr};
+  return tb::build_impl(pos, mass, n, 1, n_leaf, in, flags, workspace, ws_bytes, out, nullptr,
                         static_cast<hipStream_t>(stream));
 }
 
 int tb_build_sync(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
                   const tb_box *box, uint32_t flags, void *workspace, size_t ws_bytes,
                   const tb_tree *out, void *stream) {
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  int rc = tb::build_impl(pos, mass, n, n_leaf, box, flags, workspace, ws_bytes, out, s);
+  const int rc = tb_build(pos, mass, n, n_leaf, box, flags, workspace, ws_bytes, out, stream);
   if (rc) return rc;
-  int32_t status = 0;
-  if (hipMemcpyAsync(&status, out->status, sizeof(status), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return TB_ERR_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return TB_ERR_HIP;
-  if (status & TB_STATUS_NONFINITE) return TB_ERR_NONFINITE;
-  if (status & TB_STATUS_MASS) return TB_ERR_MASS;
-  if (status & TB_STATUS_INTERNAL) return TB_ERR_INTERNAL;
-  return TB_OK;
+  return tb::wait_status(out, static_cast<hipStream_t>(stream));
+}
+
+int tb_build_batched(const float *pos, const float *mass, int64_t n_total, int32_t nsets,
+                     const int64_t *set_offsets, int32_t n_leaf, const tb_box *boxes,
+                     uint32_t flags, void *workspace, size_t ws_bytes, const tb_tree *out,
+                     int64_t *cell_offsets, void *stream) {
+  if (!set_offsets) return TB_ERR_ARG;
+  const tb::BatchIn in{set_offsets, nullptr, boxes, boxes == nullptr};
+  return tb::build_impl(pos, mass, n_total, nsets, n_leaf, in, flags, workspace, ws_bytes, out,
+                        cell_offsets, static_cast<hipStream_t>(stream));
+}
+
+int tb_build_batched_sync(const float *pos, const float *mass, int64_t n_total, int32_t nsets,
+                          const int64_t *set_offsets, int32_t n_leaf, const tb_box *boxes,
+                          uint32_t flags, void *workspace, size_t ws_bytes, const tb_tree *out,
+                          int64_t *cell_offsets, void *stream) {
+  const int rc = tb_build_batched(pos, mass, n_total, nsets, set_offsets, n_leaf, boxes, flags,
+                                  workspace, ws_bytes, out, cell_offsets, stream);
+  if (rc) return rc;
+  return tb::wait_status(out, static_cast<hipStream_t>(stream));
 }
 
 int tb_trace_enable(int on) {
@@ -299,6 +368,6 @@ int tb_sort_configs(int32_t *desc, int cap, int *count) {
   return TB_OK;
 }
 
-const char *tb_version(void) { return "treebuild 0.1 gfx950"; }
+const char *tb_version(void) { return "treebuild 0.2 gfx950"; }
 
 }  // extern "C"

@@ -91,9 +91,11 @@ __device__ inline CellLds carve_lds(unsigned char *base, int nl, bool emit) {
 }
 
 // Loads the key window, computes a_i and the windowed maximum, and returns
-// (in D[]) the leaf depth of this thread's IPT consecutive particles.
-__device__ inline void tile_depths(const CellLds &s, const uint64_t *__restrict__ keys, int64_t n,
-                                   int nl, int64_t t0, int64_t t1, uint8_t A[kCellIpt],
+// (in D[]) the leaf depth of this thread's IPT consecutive particles.  The
+// tile [t0, t1) lies inside one set [S, E): the set's first particle starts a
+// root (a = 0) and windows never reach across the set's ends.
+__device__ inline void tile_depths(const CellLds &s, const uint64_t *__restrict__ keys, int64_t S,
+                                   int64_t E, int nl, int64_t t0, int64_t t1, uint8_t A[kCellIpt],
                                    uint8_t D[kCellIpt]) {
   const int T = (int)(t1 - t0);
   const int64_t ws = t0 - nl - 1;  // window start (may be negative)
@@ -107,7 +109,7 @@ __device__ inline void tile_depths(const CellLds &s, const uint64_t *__restrict_
     for (int r = 0; r < kBatch; ++r) {
       const int i = i0 + r * kCellThreads + threadIdx.x;
       const int64_t g = ws + i;
-      v[r] = (i < wn && g >= 0 && g < n) ? keys[g] : 0ull;
+      v[r] = (i < wn && g >= S && g < E) ? keys[g] : 0ull;
     }
 #pragma unroll
     for (int r = 0; r < kBatch; ++r) {
@@ -120,14 +122,14 @@ __device__ inline void tile_depths(const CellLds &s, const uint64_t *__restrict_
   for (int i = threadIdx.x; i < T + nl; i += kCellThreads) {
     const int64_t g = t0 + i;
     uint8_t v = 0;
-    if (g > 0 && g < n) v = (uint8_t)min_depth(s.keys[i + nl], s.keys[i + nl + 1]);
+    if (g > S && g < E) v = (uint8_t)min_depth(s.keys[i + nl], s.keys[i + nl + 1]);
     s.a[i] = v;
   }
   // w_j for j in [t0 - nl, t1)
   for (int i = threadIdx.x; i < T + nl; i += kCellThreads) {
     const int64_t j = t0 - nl + i;
     uint8_t v = 0;
-    if (j >= 0 && j + nl < n) v = (uint8_t)min_depth(s.keys[i + 1], s.keys[i + 1 + nl]);
+    if (j >= S && j + nl < E) v = (uint8_t)min_depth(s.keys[i + 1], s.keys[i + 1 + nl]);
     s.m[i] = v;
   }
   __syncthreads();
@@ -220,35 +222,37 @@ __device__ __forceinline__ uint32_t unpack(const uint32_t w[kLevelWords], int d)
 // ---------------------------------------------------------------------------
 // count pass
 // ---------------------------------------------------------------------------
+// Tile t of set b covers [t0, t1) inside the set's range [S, E).
+struct TileRange {
+  int b;
+  int64_t S, E, t0, t1;
+};
+
+__device__ __forceinline__ TileRange tile_range(int64_t t, const int64_t *__restrict__ tile_start,
+                                                const int32_t *__restrict__ tile_set,
+                                                const int64_t *__restrict__ set_off) {
+  TileRange r;
+  r.b = tile_set[t];
+  r.S = set_off[r.b];
+  r.E = set_off[r.b + 1];
+  r.t0 = r.S + (t - tile_start[r.b]) * (int64_t)kCellTile;
+  r.t1 = min(r.t0 + (int64_t)kCellTile, r.E);
+  return r;
+}
+
 // Per tile, the number of cells each depth will hold whose first particle lies
-// in the tile (stored depth-major: cnt[d][tile]).  The same workgroups also
-// pack (x, y, z, m) of their chunk of particles into one 16-byte record each
-// (original order), so the reorder pass gathers one record per particle.
+// in the tile (stored depth-major: cnt[d][tile]).
 __global__ __launch_bounds__(kCellThreads) void k_cell_count(
-    const uint64_t *__restrict__ keys, int64_t n, int nl, int64_t n_tiles,
-    uint32_t *__restrict__ tile_cnt, const float *__restrict__ pos,
-    const float *__restrict__ mass, float4 *__restrict__ packed) {
+    const uint64_t *__restrict__ keys, int nl, int64_t cell_tiles,
+    const int64_t *__restrict__ tile_start, const int32_t *__restrict__ tile_set,
+    const int64_t *__restrict__ set_off, int32_t nsets, uint32_t *__restrict__ tile_cnt) {
   extern __shared__ __align__(16) unsigned char lds[];
   const CellLds s = carve_lds(lds, nl, false);
   const int64_t tile = blockIdx.x;
-  const int64_t t0 = tile * kCellTile;
-  const int64_t t1 = min(t0 + (int64_t)kCellTile, n);
-  {
-    float4 rec[kCellIpt];
-#pragma unroll
-    for (int r = 0; r < kCellIpt; ++r) {
-      const int64_t i = t0 + r * kCellThreads + threadIdx.x;
-      rec[r] = i < t1 ? make_float4(pos[3 * i + 0], pos[3 * i + 1], pos[3 * i + 2], mass[i])
-                      : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-#pragma unroll
-    for (int r = 0; r < kCellIpt; ++r) {
-      const int64_t i = t0 + r * kCellThreads + threadIdx.x;
-      if (i < t1) packed[i] = rec[r];
-    }
-  }
+  if (tile >= tile_start[nsets]) return;
+  const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
   uint8_t A[kCellIpt], D[kCellIpt];
-  tile_depths(s, keys, n, nl, t0, t1, A, D);
+  tile_depths(s, keys, tr.S, tr.E, nl, tr.t0, tr.t1, A, D);
   uint32_t c[kLevelWords], tot[kLevelWords];
   thread_level_counts(A, D, c);
   block_level_scan(s, c, tot);
@@ -258,52 +262,129 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_count(
 #pragma unroll
     for (int wi = 0; wi < kLevelWords; ++wi)
       if (wi == (d >> 1)) cnt = (tot[wi] >> ((d & 1) * 16)) & 0xffffu;
-    tile_cnt[d * n_tiles + tile] = cnt;
+    tile_cnt[d * cell_tiles + tile] = cnt;
   }
 }
 
-// Exclusive prefix over tiles of the per-tile counts, one workgroup per depth:
-// excl[d][t] = depth-d cells before tile t, excl[d][n_tiles] = depth-d total.
-constexpr int kScanThreads = 1024;
+// Exclusive prefix of the per-tile counts over the earlier tiles of the same
+// set, one workgroup per (depth, set); the set's total per depth goes to
+// set_tot[b][d].
+constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 
-__global__ __launch_bounds__(kScanThreads) void k_cell_scan(const uint32_t *__restrict__ tile_cnt,
-                                                            int64_t n_tiles,
-                                                            uint32_t *__restrict__ excl) {
+__global__ __launch_bounds__(kScanThreads) void k_cell_scan(
+    const uint32_t *__restrict__ tile_cnt, int64_t cell_tiles,
+    const int64_t *__restrict__ tile_start, int32_t nsets, uint32_t *__restrict__ excl,
+    uint32_t *__restrict__ set_tot) {
   __shared__ uint32_t s_w[kScanThreads / 64];
   const int d = blockIdx.x;
-  const uint32_t *row = tile_cnt + d * n_tiles;
-  uint32_t *out = excl + d * (n_tiles + 1);
+  const uint32_t *row = tile_cnt + d * cell_tiles;
+  uint32_t *out = excl + d * cell_tiles;
   const int wv = threadIdx.x / 64;
-  uint32_t carry = 0;
-  for (int64_t c0 = 0; c0 < n_tiles; c0 += (int64_t)kScanThreads * kScanItems) {
-    const int64_t b = c0 + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems], sum = 0;
+  for (int b = blockIdx.y; b < nsets; b += gridDim.y) {
+    const int64_t ts = tile_start[b], te = tile_start[b + 1];
+    uint32_t carry = 0;
+    for (int64_t c0 = ts; c0 < te; c0 += (int64_t)kScanThreads * kScanItems) {
+      const int64_t q = c0 + (int64_t)threadIdx.x * kScanItems;
+      uint32_t v[kScanItems], sum = 0;
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-      v[r] = (b + r < n_tiles) ? row[b + r] : 0u;
-      sum += v[r];
-    }
-    const uint32_t inc = wave_inclusive_scan(sum);
-    if (lane_id() == 63) s_w[wv] = inc;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
+      for (int r = 0; r < kScanItems; ++r) {
+        v[r] = (q + r < te) ? row[q + r] : 0u;
+        sum += v[r];
+      }
+      const uint32_t inc = wave_inclusive_scan(sum);
+      if (lane_id() == 63) s_w[wv] = inc;
+      __syncthreads();
+      uint32_t off = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < kScanThreads / 64; ++q) {
-      const uint32_t t = s_w[q];
-      off += (q < wv) ? t : 0u;
-      tot += t;
-    }
-    __syncthreads();
-    uint32_t run = carry + off + inc - sum;
+      for (int k = 0; k < kScanThreads / 64; ++k) {
+        const uint32_t t = s_w[k];
+        off += (k < wv) ? t : 0u;
+        tot += t;
+      }
+      __syncthreads();
+      uint32_t run = carry + off + inc - sum;
 #pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-      if (b + r < n_tiles) out[b + r] = run;
-      run += v[r];
+      for (int r = 0; r < kScanItems; ++r) {
+        if (q + r < te) out[q + r] = run;
+        run += v[r];
+      }
+      carry += tot;
     }
-    carry += tot;
+    if (threadIdx.x == 0) set_tot[b * kLevels + d] = carry;
   }
-  if (threadIdx.x == 0) out[n_tiles] = carry;
+}
+
+// One workgroup over all sets: the first cell of every set and of every depth
+// of every set, the outputs level_offset [B][23], cell_offsets [B+1] and
+// n_cells, the parent-pass chunk tables, and the boxes used.
+constexpr int kSetScanThreads = 1024;
+
+__global__ __launch_bounds__(kSetScanThreads) void k_set_scan(
+    const uint32_t *__restrict__ set_tot, int32_t nsets, int64_t *__restrict__ set_cells,
+    int64_t *__restrict__ lvl_off, int64_t *__restrict__ level_offset,
+    int64_t *__restrict__ cell_offsets, int64_t *__restrict__ n_cells,
+    int64_t *__restrict__ par_start, const double *__restrict__ box,
+    double *__restrict__ box_out) {
+  __shared__ uint32_t s_w[kSetScanThreads / 64];
+  __shared__ int64_t s_carry;
+  const int wv = threadIdx.x / 64;
+  // rows: 0 = cells per set, 1 + d = parent chunks at depth d (children at d + 1)
+  for (int row = 0; row < kLevels; ++row) {
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int r0 = 0; r0 < nsets; r0 += kSetScanThreads) {
+      const int b = r0 + threadIdx.x;
+      uint32_t v = 0;
+      if (b < nsets) {
+        if (row == 0) {
+          for (int d = 0; d < kLevels; ++d) v += set_tot[b * kLevels + d];
+        } else {
+          v = (set_tot[b * kLevels + row] + kParentChunk - 1) / kParentChunk;
+        }
+      }
+      const uint32_t inc = wave_inclusive_scan(v);
+      if (lane_id() == 63) s_w[wv] = inc;
+      __syncthreads();
+      int64_t off = s_carry, tot = 0;
+      for (int q = 0; q < kSetScanThreads / 64; ++q) {
+        off += (q < wv) ? s_w[q] : 0u;
+        tot += s_w[q];
+      }
+      off += inc - v;
+      if (b < nsets) {
+        if (row == 0) {
+          set_cells[b] = off;
+          if (cell_offsets) cell_offsets[b] = off;
+          int64_t run = off;
+          for (int d = 0; d < kLevels; ++d) {
+            lvl_off[b * (kLevels + 1) + d] = run;
+            level_offset[b * (kLevels + 1) + d] = run;
+            run += set_tot[b * kLevels + d];
+          }
+          lvl_off[b * (kLevels + 1) + kLevels] = run;
+          level_offset[b * (kLevels + 1) + kLevels] = run;
+          if (box_out)
+            for (int k = 0; k < 4; ++k) box_out[4 * b + k] = box[4 * b + k];
+        } else {
+          par_start[(row - 1) * (nsets + 1) + b] = off;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) s_carry += tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (row == 0) {
+        set_cells[nsets] = s_carry;
+        if (cell_offsets) cell_offsets[nsets] = s_carry;
+        *n_cells = s_carry;
+      } else {
+        par_start[(row - 1) * (nsets + 1) + nsets] = s_carry;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -374,6 +455,7 @@ __device__ __forceinline__ uint32_t compact3(uint64_t v) {
 // End (exclusive) of the leaf that starts at particle i with depth dl.
 __device__ inline int64_t leaf_end(const CellLds &s, const uint64_t *__restrict__ keys, int64_t n,
                                    int nl, int64_t t0, int64_t i, int dl) {
+  // n is the end of the particle's set
   const int64_t lim = min(n, i + nl + 1);
   for (int64_t j = i + 1; j < lim; ++j)
     if (s.a[j - t0] <= dl) return j;
@@ -502,40 +584,27 @@ __device__ __forceinline__ void leaf_finish_f(const LeafSumsF &a, float com[4], 
 
 template <bool MIXED>
 __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
-    const uint64_t *__restrict__ keys, int64_t n, int nl, const uint32_t *__restrict__ excl,
-    int64_t n_tiles, const double *__restrict__ box, const float4 *__restrict__ sorted,
-    uint64_t *__restrict__ cell_key, uint8_t *__restrict__ cell_level,
-    int32_t *__restrict__ cell_first, int32_t *__restrict__ cell_count,
-    int32_t *__restrict__ child_ptr, void *__restrict__ com_v, void *__restrict__ quad_v,
-    float *__restrict__ m_lo, int32_t *__restrict__ head_parent,
-    int64_t *__restrict__ level_offset, int64_t *__restrict__ n_cells, int64_t c_max,
-    int32_t *__restrict__ status_word, double *__restrict__ box_out) {
+    const uint64_t *__restrict__ keys, int nl, const uint32_t *__restrict__ excl,
+    int64_t cell_tiles, const int64_t *__restrict__ tile_start,
+    const int32_t *__restrict__ tile_set, const int64_t *__restrict__ set_off, int32_t nsets,
+    const int64_t *__restrict__ lvl_off, const double *__restrict__ box,
+    const float4 *__restrict__ sorted, uint64_t *__restrict__ cell_key,
+    uint8_t *__restrict__ cell_level, int32_t *__restrict__ cell_first,
+    int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr, void *__restrict__ com_v,
+    void *__restrict__ quad_v, float *__restrict__ m_lo, int32_t *__restrict__ head_parent,
+    int64_t c_max, int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
   const CellLds s = carve_lds(lds, nl, true);
   const int64_t tile = blockIdx.x;
-  const int64_t t0 = tile * kCellTile;
-  const int64_t t1 = min(t0 + (int64_t)kCellTile, n);
+  if (tile >= tile_start[nsets]) return;
+  const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
+  const int64_t t0 = tr.t0, t1 = tr.t1, n = tr.E;  // n: end of this tile's set
 
-  // per-depth base of this tile: level offset + cells of earlier tiles
+  // per-depth base of this tile: the set's first cell of the depth plus the
+  // cells of the set's earlier tiles
   if (threadIdx.x < kLevels) {
     const int d = threadIdx.x;
-    uint32_t run = 0;
-    for (int q = 0; q < d; ++q) run += excl[q * (n_tiles + 1) + n_tiles];
-    s.lvl[d] = run + excl[d * (n_tiles + 1) + tile];
-    if (tile == 0) {
-      level_offset[d] = run;
-      if (d == kLevels - 1) {
-        const uint32_t total = run + excl[d * (n_tiles + 1) + n_tiles];
-        level_offset[kLevels] = total;
-        *n_cells = total;
-        if (box_out) {
-          box_out[0] = box[0];
-          box_out[1] = box[1];
-          box_out[2] = box[2];
-          box_out[3] = box[3];
-        }
-      }
-    }
+    s.lvl[d] = (uint32_t)(lvl_off[tr.b * (kLevels + 1) + d] + excl[d * cell_tiles + tile]);
   }
   // the tile's particles in key order plus the n_leaf halo, one batched load
   const int span = (int)(min(t1 + (int64_t)nl, n) - t0);
@@ -558,7 +627,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   if (threadIdx.x == 0) *s.nleaf = 0;
 
   uint8_t A[kCellIpt], D[kCellIpt];
-  tile_depths(s, keys, n, nl, t0, t1, A, D);  // its barriers also publish s.lvl, s.rec
+  tile_depths(s, keys, tr.S, tr.E, nl, t0, t1, A, D);  // its barriers also publish s.lvl, s.rec
   uint32_t c[kLevelWords], tot[kLevelWords];
   thread_level_counts(A, D, c);
   block_level_scan(s, c, tot);
@@ -609,8 +678,8 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   __syncthreads();
 
   // leaf moments: one lane per leaf, particles read from LDS
-  const double lo[3] = {box[0], box[1], box[2]};
-  const double side = box[3];
+  const double lo[3] = {box[4 * tr.b + 0], box[4 * tr.b + 1], box[4 * tr.b + 2]};
+  const double side = box[4 * tr.b + 3];
   const uint32_t nlv = *s.nleaf;
   for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
     const uint32_t ci = s.leaf_ci[x];
@@ -669,16 +738,22 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
-hipError_t launch_cell_count(const Plan &p, const Work &w, const float *pos, const float *mass,
-                             hipStream_t s) {
+hipError_t launch_cell_count(const Plan &p, const Work &w, hipStream_t s) {
   const size_t lds = cell_lds_bytes(p.n_leaf, false);
   k_cell_count<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
-      sorted_keys(p, w), p.n, p.n_leaf, p.cell_tiles, w.cell_cnt, pos, mass, w.packed);
+      sorted_keys(p, w), p.n_leaf, p.cell_tiles, w.tile_start, w.tile_set, w.set_off, p.nsets,
+      w.cell_cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_cell_scan(const Plan &p, const Work &w, hipStream_t s) {
-  k_cell_scan<<<kLevels, kScanThreads, 0, s>>>(w.cell_cnt, p.cell_tiles, w.cell_excl);
+hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
+                            int64_t *cell_offsets, hipStream_t s) {
+  const int gy = p.nsets < 65535 ? p.nsets : 65535;
+  k_cell_scan<<<dim3(kLevels, gy), kScanThreads, 0, s>>>(w.cell_cnt, p.cell_tiles, w.tile_start,
+                                                         p.nsets, w.cell_excl, w.set_tot);
+  k_set_scan<<<1, kSetScanThreads, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
+                                           out.level_offset, cell_offsets, out.n_cells,
+                                           w.par_start, w.box, out.box_out);
   return hipGetLastError();
 }
 
@@ -717,10 +792,10 @@ hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hi
   const size_t lds = cell_lds_bytes(p.n_leaf, true);
   auto k = (p.flags & 0xffu) == TB_MIXED ? k_cell_emit<true> : k_cell_emit<false>;
   k<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
-      sorted_keys(p, w), p.n, p.n_leaf, w.cell_excl, p.cell_tiles, w.box, w.sorted,
-      out.cell_key, out.cell_level, out.cell_first, out.cell_count, out.child_ptr, out.com,
-      out.quad, w.m_lo, w.head_parent, out.level_offset, out.n_cells, p.c_max, out.status,
-      out.box_out);
+      sorted_keys(p, w), p.n_leaf, w.cell_excl, p.cell_tiles, w.tile_start, w.tile_set,
+      w.set_off, p.nsets, w.lvl_off, w.box, w.sorted, out.cell_key, out.cell_level,
+      out.cell_first, out.cell_count, out.child_ptr, out.com, out.quad, w.m_lo, w.head_parent,
+      p.c_max, out.status);
   return hipGetLastError();
 }
 

@@ -2,6 +2,11 @@
 //
 // Internal to the library: kernels, launch wrappers, the workspace plan and a
 // few wave64 helpers.  The public C ABI is include/treebuild.h.
+//
+// Every build is a batch of B >= 1 independent particle sets stored back to
+// back (a single build is the batch B = 1).  Set b owns particles
+// [set_off[b], set_off[b+1]) in the input and, after the sort, the same range
+// of sorted positions; its cells are one contiguous, (depth, key)-ordered block.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,17 +19,24 @@ namespace tb {
 // ---------------------------------------------------------------------------
 // Fixed configuration
 // ---------------------------------------------------------------------------
-constexpr int kMaxDepth = TB_MAX_DEPTH;  // deepest cell (21 bits per axis)
-constexpr int kLevels = kMaxDepth + 1;   // depths 0..21
+constexpr int kMaxDepth = TB_MAX_DEPTH;         // deepest cell (21 bits per axis)
+constexpr int kLevels = kMaxDepth + 1;          // depths 0..21
 constexpr int kLevelWords = (kLevels + 1) / 2;  // 16-bit level counters packed in u32
 
-// Cell kernels: one tile of particles per workgroup.
+// Cell kernels: one tile of particles (never straddling two sets) per workgroup.
 constexpr int kCellThreads = 256;
 constexpr int kCellIpt = 8;
 constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
 
-// Parent kernel
+// Parent kernel: children staged per workgroup step.
 constexpr int kParentThreads = 256;
+constexpr int kParentChunk = kParentThreads;
+
+// Bounding-box chunks (auto box only).
+constexpr int kBboxChunk = 65536;
+
+// Sets whose offsets fit the LDS table of the set-id radix passes.
+constexpr int kMaxSetsLds = TB_MAX_SETS;
 
 // Lookback status word: flag in bits 63:62, value in bits 31:0.
 constexpr uint64_t kFlagAggregate = 1ull << 62;
@@ -33,7 +45,7 @@ constexpr uint64_t kFlagMask = 3ull << 62;
 
 // Sort configuration chosen for one build (radix digit width and tile shape).
 struct SortConfig {
-  int bits;     // radix digit width, 8..11
+  int bits;     // radix digit width, 8..9
   int ipt;      // keys per thread
   int threads;  // threads per workgroup
   int tile() const { return ipt * threads; }
@@ -44,36 +56,46 @@ struct SortConfig {
 // Workspace plan: byte offsets of every scratch array inside the caller's
 // workspace, all 256-byte aligned.
 struct Plan {
-  int64_t n;
+  int64_t n;        // particles in the batch
   int32_t n_leaf;
   uint32_t flags;
+  int32_t nsets;    // B
   SortConfig sort;
+  int key_passes;   // radix passes over the 63 key bits
+  int set_passes;   // 8-bit radix passes over the set id (0 when B == 1)
   int64_t sort_tiles;
-  int64_t cell_tiles;
+  int64_t cell_tiles;   // upper bound of the cell tiles of all sets
+  int64_t bbox_chunks;  // upper bound of the bounding-box chunks of all sets
   int64_t c_max;
   // offsets
-  size_t keys0, keys1;     // u64 [n] ping-pong key buffers
-  size_t vals1;            // u32 [n] payload buffer (the other one is out->perm)
-  size_t hist;             // u32 [passes][radix] global digit counts
-  size_t hist_part;        // u32 [keygen blocks][passes][radix] per-workgroup counts
-  size_t status0, status1; // u64 [sort_tiles][radix] lookback words (alternating passes)
-  size_t counters;         // u32 [64] dynamic tile counters
-  size_t box;              // f64 [4] the root box used by this build
-  size_t bbox_part;        // f64 [kBboxBlocks][6] per-block min/max partials
-  size_t cell_cnt;         // u32 [cell_tiles][kLevels] per-tile cell counts per depth
-  size_t cell_excl;        // u32 [cell_tiles + 1][kLevels] exclusive prefix over tiles, then totals
-  size_t packed;           // f32x4 [n] (x, y, z, m) records in original order
-  size_t sorted;           // f32x4 [n] the same records in key order
-  size_t head_parent;      // i32 [c_max] parent slot of every first child
-  size_t m_lo;             // f32 [c_max] compensation of each cell mass (mixed precision)
+  size_t keys0, keys1;  // u64 [n] ping-pong key buffers
+  size_t vals1;         // u32 [n] payload buffer (the other one is out->perm)
+  size_t hist;          // u32 [key_passes + set_passes][radix] global digit counts
+  size_t hist_part;     // u32 [keygen blocks][key_passes][radix] per-workgroup counts
+  size_t status0, status1;  // u64 [sort_tiles][radix] look-back words (alternating passes)
+  size_t counters;      // u32 [64] dynamic tile counters
+  size_t set_off;       // i64 [B + 1] particle offsets of the sets
+  size_t box;           // f64 [B][4] the root box of each set
+  size_t bbox_part;     // f64 [bbox_chunks][6] per-chunk min/max
+  size_t chunk_start;   // i64 [B + 1] first bounding-box chunk of each set
+  size_t chunk_set;     // i32 [bbox_chunks] set of each bounding-box chunk
+  size_t tile_start;    // i64 [B + 1] first cell tile of each set
+  size_t tile_set;      // i32 [cell_tiles] set of each cell tile
+  size_t cell_cnt;      // u32 [kLevels][cell_tiles] per-tile cell counts per depth
+  size_t cell_excl;     // u32 [kLevels][cell_tiles] prefix over the earlier tiles of the set
+  size_t set_tot;       // u32 [B][kLevels] cells of each set and depth
+  size_t set_cells;     // i64 [B + 1] first cell of each set; [B] = all cells
+  size_t lvl_off;       // i64 [B][kLevels + 1] first cell of each depth of each set
+  size_t par_start;     // i64 [kLevels][B + 1] parent-pass chunks per depth and set
+  size_t packed;        // f32x4 [n] (x, y, z, m) records in original order
+  size_t sorted;        // f32x4 [n] the same records in key order
+  size_t head_parent;   // i32 [c_max] parent slot of every first child
+  size_t m_lo;          // f32 [c_max] compensation of each cell mass (mixed precision)
   size_t total;
 };
 
-constexpr int kBboxBlocks = 512;
-constexpr int kBboxThreads = 256;
-
-int make_plan(int64_t n, int32_t n_leaf, uint32_t flags, const SortConfig &sc, Plan *p);
-SortConfig default_sort_config(int64_t n);
+int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const SortConfig &sc,
+              Plan *p);
 
 // Device views of the workspace
 struct Work {
@@ -83,10 +105,19 @@ struct Work {
   uint32_t *hist_part;
   uint64_t *status0, *status1;
   uint32_t *counters;
+  int64_t *set_off;
   double *box;
   double *bbox_part;
+  int64_t *chunk_start;
+  int32_t *chunk_set;
+  int64_t *tile_start;
+  int32_t *tile_set;
   uint32_t *cell_cnt;
   uint32_t *cell_excl;
+  uint32_t *set_tot;
+  int64_t *set_cells;
+  int64_t *lvl_off;
+  int64_t *par_start;
   float4 *packed;
   float4 *sorted;
   int32_t *head_parent;
@@ -95,34 +126,49 @@ struct Work {
 
 Work carve(const Plan &p, void *base);
 
+// Where the set description comes from.
+struct BatchIn {
+  const int64_t *set_off;  // device [B + 1], or NULL for B == 1 (then {0, n})
+  const tb_box *host_box;  // single build: the caller's box (host), or NULL
+  const tb_box *dev_boxes; // batch: device [B], or NULL
+  bool auto_box;           // derive each set's box from its particles
+};
+
 // ---------------------------------------------------------------------------
 // Launch wrappers (each defined in the .hip file that holds the kernel)
 // ---------------------------------------------------------------------------
 // tb_keys.hip
-hipError_t launch_init(const Plan &p, const Work &w, const tb_box *box, const tb_tree &out,
+hipError_t launch_init(const Plan &p, const Work &w, const BatchIn &in, const tb_tree &out,
                        hipStream_t s);
+hipError_t launch_setup(const Plan &p, const Work &w, bool with_chunks, bool check_boxes,
+                        int32_t *status, hipStream_t s);
 hipError_t launch_bbox(const Plan &p, const Work &w, const float *pos, hipStream_t s);
-hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const tb_tree &out,
-                         hipStream_t s);
+hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const float *mass,
+                         const tb_tree &out, hipStream_t s);
 hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s);
+hipError_t launch_copy_keys(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
 int keygen_blocks(int64_t n);
-hipError_t launch_empty(const tb_tree &out, const tb_box *box, hipStream_t s);
+hipError_t launch_empty(const tb_tree &out, int32_t nsets, const BatchIn &in,
+                        int64_t *cell_offsets, hipStream_t s);
 // tb_sort.hip
 hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tree &out,
                             hipStream_t s);
+bool sort_config_supported(const SortConfig &c);
 // tb_cells.hip
-hipError_t launch_cell_count(const Plan &p, const Work &w, const float *pos, const float *mass,
-                             hipStream_t s);
-hipError_t launch_cell_scan(const Plan &p, const Work &w, hipStream_t s);
+hipError_t launch_cell_count(const Plan &p, const Work &w, hipStream_t s);
+hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
+                            int64_t *cell_offsets, hipStream_t s);
 hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
 hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
+size_t cell_emit_lds(int nl);
+size_t cell_lds_limit();
 // tb_parents.hip
 hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
                           hipStream_t s);
 
 // Final sorted keys live in keys0 or keys1 depending on the number of passes.
 inline uint64_t *sorted_keys(const Plan &p, const Work &w) {
-  return (p.sort.passes() % 2 == 0) ? w.keys0 : w.keys1;
+  return ((p.key_passes + p.set_passes) % 2 == 0) ? w.keys0 : w.keys1;
 }
 
 // ---------------------------------------------------------------------------
@@ -211,6 +257,21 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
     if (l >= o) v += t;
   }
   return v;
+}
+
+// Index b of the last entry of the sorted table tab[0..count) with tab[b] <= x
+// (the set holding position x when tab holds the set offsets).
+template <typename T>
+__device__ __forceinline__ int upper_index(const T *tab, int count, int64_t x) {
+  int lo = 0, hi = count - 1;  // invariant: tab[lo] <= x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)tab[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 #endif

@@ -1,13 +1,19 @@
-// tb_keys.hip -- build set-up, root box and Morton keys (Sec. 2.2; Sec. 2.3 step i).
+// tb_keys.hip -- build set-up, root boxes and Morton keys (Sec. 2.2; Sec. 2.3 step i).
 //
-// k_init        clears the counters and lookback words one build needs (a plain
-//               fill kernel, so a captured graph holds no memset node) and
-//               stores a caller-given root box on the device.
-// k_bbox_*      FP64 min/max over the positions -> root box with a power-of-two
-//               side (only when the caller gives no box).
+// k_init        clears the counters and look-back words one build needs (plain
+//               fill kernels, so a captured graph holds no memset node) and
+//               copies the set offsets and caller-given root boxes into the
+//               workspace.
+// k_setup       checks the set offsets and caller-given boxes, then builds the
+//               per-set tables: first cell tile and bounding-box chunk of each
+//               set, the set of every tile and chunk, and the digit counts of
+//               the set-id radix passes.
+// k_bbox_*      FP64 min/max over each set's positions -> root box with a
+//               power-of-two side (only when no box is given).
 // k_keygen      FP64 quantisation of each coordinate to 21 bits, bit interleave
 //               below a leading 1, plus per-workgroup digit histograms of every
-//               radix pass (so the sort never re-reads the keys to count them).
+//               radix pass (so the sort never re-reads the keys to count them)
+//               and the packed (x, y, z, m) record of every particle.
 // k_hist_reduce column sums of those per-workgroup histograms.
 #include "tb_internal.h"
 
@@ -17,21 +23,34 @@ constexpr int kInitThreads = 256;
 constexpr int kKeygenThreads = 512;
 constexpr int kKeygenMaxBlocks = 512;
 constexpr int kKeygenIpt = 4;
+constexpr int kSetupThreads = 1024;
 
 // ---------------------------------------------------------------------------
 // init
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kInitThreads) void k_init(
     uint64_t *__restrict__ status0, int64_t n_status0, uint32_t *__restrict__ counters,
-    int32_t *__restrict__ status_word,
-    double *__restrict__ box, int box_given, double lo0, double lo1, double lo2, double side) {
+    int32_t *__restrict__ status_word, int64_t n, int32_t nsets,
+    const int64_t *__restrict__ set_off_in, int64_t *__restrict__ set_off,
+    const tb_box *__restrict__ boxes_in, double *__restrict__ box, int host_box, double lo0,
+    double lo1, double lo2, double side) {
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < n_status0; i += stride) status0[i] = 0;
   if (tid < 64) counters[tid] = 0;
+  for (int64_t b = tid; b <= nsets; b += stride)
+    set_off[b] = set_off_in ? set_off_in[b] : (b == 0 ? 0 : n);
+  if (boxes_in) {
+    for (int64_t b = tid; b < nsets; b += stride) {
+      box[4 * b + 0] = boxes_in[b].lo[0];
+      box[4 * b + 1] = boxes_in[b].lo[1];
+      box[4 * b + 2] = boxes_in[b].lo[2];
+      box[4 * b + 3] = boxes_in[b].side;
+    }
+  }
   if (tid == 0) {
     *status_word = 0;
-    if (box_given) {
+    if (host_box) {
       box[0] = lo0;
       box[1] = lo1;
       box[2] = lo2;
@@ -40,29 +59,151 @@ __global__ __launch_bounds__(kInitThreads) void k_init(
   }
 }
 
-hipError_t launch_init(const Plan &p, const Work &w, const tb_box *box, const tb_tree &out,
+hipError_t launch_init(const Plan &p, const Work &w, const BatchIn &in, const tb_tree &out,
                        hipStream_t s) {
   const int64_t n0 = p.sort_tiles * (int64_t)p.sort.radix();
-  int blocks = (int)((n0 + kInitThreads - 1) / kInitThreads);
+  int64_t work = n0 > p.nsets ? n0 : p.nsets;
+  int blocks = (int)((work + kInitThreads - 1) / kInitThreads);
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  k_init<<<blocks, kInitThreads, 0, s>>>(w.status0, n0, w.counters, out.status, w.box, box ? 1 : 0, box ? box->lo[0] : 0.0,
-                                         box ? box->lo[1] : 0.0, box ? box->lo[2] : 0.0,
-                                         box ? box->side : 1.0);
+  const tb_box *hb = in.host_box;
+  k_init<<<blocks, kInitThreads, 0, s>>>(w.status0, n0, w.counters, out.status, p.n, p.nsets,
+                                         in.set_off, w.set_off, in.dev_boxes, w.box, hb ? 1 : 0,
+                                         hb ? hb->lo[0] : 0.0, hb ? hb->lo[1] : 0.0,
+                                         hb ? hb->lo[2] : 0.0, hb ? hb->side : 1.0);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// root box (FP64 min / max, then the power-of-two side)
+// per-set tables (one workgroup)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBboxThreads) void k_bbox_partial(const float *__restrict__ pos,
-                                                               int64_t n,
-                                                               double *__restrict__ part) {
+// lo finite and side a positive, finite, normal power of two
+__device__ __forceinline__ bool box_valid(const double *b) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(b[3]);
+  const uint32_t ex = (uint32_t)(bits >> 52) & 0x7ffu;
+  return isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]) && (bits >> 63) == 0 &&
+         (bits & ((1ull << 52) - 1)) == 0 && ex != 0 && ex != 0x7ffu;
+}
+
+__global__ __launch_bounds__(kSetupThreads) void k_setup(
+    int64_t *__restrict__ set_off, int32_t nsets, int64_t n, int64_t *__restrict__ tile_start,
+    int32_t *__restrict__ tile_set, int64_t *__restrict__ chunk_start,
+    int32_t *__restrict__ chunk_set, uint32_t *__restrict__ set_hist, int set_passes, int bits,
+    int with_chunks, double *__restrict__ box, int check_boxes,
+    int32_t *__restrict__ status_word) {
+  __shared__ uint32_t s_w[2][kSetupThreads / 64];
+  __shared__ uint64_t s_carry[2];
+  __shared__ int s_bad;
+  const int R = 1 << bits;
+  // The offsets must start at 0, end at n and never decrease.  Anything else is
+  // reported and replaced by {0, ..., 0, n}, so no kernel indexes outside [0, n).
+  if (threadIdx.x == 0) s_bad = (set_off[0] != 0 || set_off[nsets] != n) ? 1 : 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < nsets; b += kSetupThreads)
+    if (set_off[b] > set_off[b + 1] || set_off[b] < 0) s_bad = 1;
+  __syncthreads();
+  if (s_bad) {
+    for (int b = threadIdx.x; b <= nsets; b += kSetupThreads) set_off[b] = b == nsets ? n : 0;
+    if (threadIdx.x == 0) atomicOr(status_word, TB_STATUS_SETS);
+  }
+  // a caller-given box that is not usable is reported and replaced by the unit
+  // cube, so that the key arithmetic stays finite
+  if (check_boxes) {
+    bool bad_box = false;
+    for (int b = threadIdx.x; b < nsets; b += kSetupThreads) {
+      if (!box_valid(box + 4 * b)) {
+        bad_box = true;
+        box[4 * b + 0] = box[4 * b + 1] = box[4 * b + 2] = 0.0;
+        box[4 * b + 3] = 1.0;
+      }
+    }
+    if (bad_box) atomicOr(status_word, TB_STATUS_BOX);
+  }
+  __syncthreads();
+  // digit counts of the set-id passes: set b contributes its size to digit k of b
+  for (int i = threadIdx.x; i < set_passes * R; i += kSetupThreads) set_hist[i] = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < nsets; b += kSetupThreads) {
+    const uint32_t nb = (uint32_t)(set_off[b + 1] - set_off[b]);
+    for (int k = 0; k < set_passes; ++k)
+      if (nb) atomicAdd(&set_hist[k * R + ((b >> (k * bits)) & (R - 1))], nb);
+  }
+  // exclusive scans over sets of the tile and chunk counts, in rounds
+  if (threadIdx.x == 0) s_carry[0] = s_carry[1] = 0;
+  __syncthreads();
+  const int wv = threadIdx.x / 64;
+  for (int r0 = 0; r0 < nsets; r0 += kSetupThreads) {
+    const int b = r0 + threadIdx.x;
+    int64_t nb = 0;
+    if (b < nsets) nb = set_off[b + 1] - set_off[b];
+    const uint32_t nt = (uint32_t)((nb + kCellTile - 1) / kCellTile);
+    const uint32_t nc = with_chunks ? (uint32_t)((nb + kBboxChunk - 1) / kBboxChunk) : 0u;
+    const uint32_t it = wave_inclusive_scan(nt), ic = wave_inclusive_scan(nc);
+    if (lane_id() == 63) {
+      s_w[0][wv] = it;
+      s_w[1][wv] = ic;
+    }
+    __syncthreads();
+    uint64_t ot = s_carry[0], oc = s_carry[1], tt = 0, tc = 0;
+    for (int q = 0; q < kSetupThreads / 64; ++q) {
+      if (q < wv) {
+        ot += s_w[0][q];
+        oc += s_w[1][q];
+      }
+      tt += s_w[0][q];
+      tc += s_w[1][q];
+    }
+    ot += it - nt;
+    oc += ic - nc;
+    if (b < nsets) {
+      tile_start[b] = (int64_t)ot;
+      for (uint32_t k = 0; k < nt; ++k) tile_set[ot + k] = b;
+      if (with_chunks) {
+        chunk_start[b] = (int64_t)oc;
+        for (uint32_t k = 0; k < nc; ++k) chunk_set[oc + k] = b;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_carry[0] += tt;
+      s_carry[1] += tc;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    tile_start[nsets] = (int64_t)s_carry[0];
+    if (with_chunks) chunk_start[nsets] = (int64_t)s_carry[1];
+  }
+}
+
+hipError_t launch_setup(const Plan &p, const Work &w, bool with_chunks, bool check_boxes,
+                        int32_t *status, hipStream_t s) {
+  k_setup<<<1, kSetupThreads, 0, s>>>(w.set_off, p.nsets, p.n, w.tile_start, w.tile_set,
+                                      w.chunk_start, w.chunk_set,
+                                      w.hist + (size_t)p.key_passes * p.sort.radix(),
+                                      p.set_passes, p.sort.bits, with_chunks ? 1 : 0, w.box,
+                                      check_boxes ? 1 : 0, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// root boxes (FP64 min / max per set, then the power-of-two side)
+// ---------------------------------------------------------------------------
+constexpr int kBboxThreads = 256;
+
+__global__ __launch_bounds__(kBboxThreads) void k_bbox_partial(
+    const float *__restrict__ pos, const int64_t *__restrict__ set_off,
+    const int64_t *__restrict__ chunk_start, const int32_t *__restrict__ chunk_set,
+    int32_t nsets, double *__restrict__ part) {
   __shared__ double red[6][kBboxThreads / 64];
+  const int64_t c = blockIdx.x;
+  if (c >= chunk_start[nsets]) return;
+  const int b = chunk_set[c];
+  const int64_t i0 = set_off[b] + (c - chunk_start[b]) * (int64_t)kBboxChunk;
+  const int64_t i1 = min(i0 + (int64_t)kBboxChunk, set_off[b + 1]);
   double mn[3] = {INFINITY, INFINITY, INFINITY};
   double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBboxThreads) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       double v = (double)pos[3 * i + a];
@@ -87,58 +228,60 @@ __global__ __launch_bounds__(kBboxThreads) void k_bbox_partial(const float *__re
   }
   __syncthreads();
   if (threadIdx.x < 6) {
-    const int c = threadIdx.x;
-    double r = red[c][0];
-    for (int k = 1; k < kBboxThreads / 64; ++k) r = (c < 3) ? fmin(r, red[c][k]) : fmax(r, red[c][k]);
-    part[blockIdx.x * 6 + c] = r;
+    const int k = threadIdx.x;
+    double r = red[k][0];
+    for (int q = 1; q < kBboxThreads / 64; ++q) r = (k < 3) ? fmin(r, red[k][q]) : fmax(r, red[k][q]);
+    part[c * 6 + k] = r;
   }
 }
 
-__global__ __launch_bounds__(64) void k_bbox_final(const double *__restrict__ part, int nblocks,
-                                                   double *__restrict__ box) {
-  double mn[3] = {INFINITY, INFINITY, INFINITY};
-  double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = threadIdx.x; b < nblocks; b += 64) {
+__global__ __launch_bounds__(64) void k_bbox_final(const double *__restrict__ part,
+                                                   const int64_t *__restrict__ chunk_start,
+                                                   int32_t nsets, double *__restrict__ box) {
+  for (int b = blockIdx.x; b < nsets; b += gridDim.x) {
+    double mn[3] = {INFINITY, INFINITY, INFINITY};
+    double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t c = chunk_start[b] + threadIdx.x; c < chunk_start[b + 1]; c += 64) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        mn[a] = fmin(mn[a], part[c * 6 + a]);
+        mx[a] = fmax(mx[a], part[c * 6 + 3 + a]);
+      }
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      mn[a] = fmin(mn[a], part[b * 6 + a]);
-      mx[a] = fmax(mx[a], part[b * 6 + 3 + a]);
+      for (int o = 32; o > 0; o >>= 1) {
+        mn[a] = fmin(mn[a], __shfl_xor(mn[a], o, 64));
+        mx[a] = fmax(mx[a], __shfl_xor(mx[a], o, 64));
+      }
     }
-  }
+    if (threadIdx.x == 0) {
+      double ext = 0.0;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    for (int o = 32; o > 0; o >>= 1) {
-      mn[a] = fmin(mn[a], __shfl_xor(mn[a], o, 64));
-      mx[a] = fmax(mx[a], __shfl_xor(mx[a], o, 64));
+      for (int a = 0; a < 3; ++a) {
+        const double e = mx[a] - mn[a];
+        ext = e > ext ? e : ext;
+      }
+      // smallest power of two strictly above ext: ext = f * 2^e with f in [0.5, 1)
+      double side = 1.0;
+      if (ext > 0.0 && isfinite(ext)) {
+        int e;
+        (void)frexp(ext, &e);
+        side = ldexp(1.0, e);
+      }
+      box[4 * b + 0] = isfinite(mn[0]) ? mn[0] : 0.0;
+      box[4 * b + 1] = isfinite(mn[1]) ? mn[1] : 0.0;
+      box[4 * b + 2] = isfinite(mn[2]) ? mn[2] : 0.0;
+      box[4 * b + 3] = side;
     }
-  }
-  if (threadIdx.x == 0) {
-    double ext = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double e = mx[a] - mn[a];
-      ext = e > ext ? e : ext;
-    }
-    // smallest power of two strictly above ext: ext = f * 2^e with f in [0.5, 1)
-    double side = 1.0;
-    if (ext > 0.0 && isfinite(ext)) {
-      int e;
-      (void)frexp(ext, &e);
-      side = ldexp(1.0, e);
-    }
-    box[0] = isfinite(mn[0]) ? mn[0] : 0.0;
-    box[1] = isfinite(mn[1]) ? mn[1] : 0.0;
-    box[2] = isfinite(mn[2]) ? mn[2] : 0.0;
-    box[3] = side;
   }
 }
 
 hipError_t launch_bbox(const Plan &p, const Work &w, const float *pos, hipStream_t s) {
-  int blocks = (int)((p.n + kBboxThreads - 1) / kBboxThreads);
-  if (blocks > kBboxBlocks) blocks = kBboxBlocks;
-  if (blocks < 1) blocks = 1;
-  k_bbox_partial<<<blocks, kBboxThreads, 0, s>>>(pos, p.n, w.bbox_part);
-  k_bbox_final<<<1, 64, 0, s>>>(w.bbox_part, blocks, w.box);
+  k_bbox_partial<<<(unsigned)p.bbox_chunks, kBboxThreads, 0, s>>>(
+      pos, w.set_off, w.chunk_start, w.chunk_set, p.nsets, w.bbox_part);
+  const int blocks = p.nsets < 4096 ? p.nsets : 4096;
+  k_bbox_final<<<blocks, 64, 0, s>>>(w.bbox_part, w.chunk_start, p.nsets, w.box);
   return hipGetLastError();
 }
 
@@ -169,41 +312,50 @@ __device__ __forceinline__ uint32_t quantise(float x, double lo, double scale) {
 
 template <int BITS>
 __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
-    const float *__restrict__ pos, int64_t n, const double *__restrict__ box,
-    uint64_t *__restrict__ keys, uint32_t *__restrict__ hist_part, int passes,
-    int32_t *__restrict__ status_word) {
+    const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
+    const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
+    uint64_t *__restrict__ keys, float4 *__restrict__ packed, uint32_t *__restrict__ hist_part,
+    int passes, int32_t *__restrict__ status_word) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
   __shared__ uint32_t h[MAXP * R];
+  extern __shared__ uint32_t s_off[];  // [nsets + 1] set offsets (positions < 2^31)
   for (int i = threadIdx.x; i < passes * R; i += blockDim.x) h[i] = 0;
+  for (int i = threadIdx.x; i <= nsets; i += blockDim.x) s_off[i] = (uint32_t)set_off[i];
   __syncthreads();
 
-  const double lo0 = box[0], lo1 = box[1], lo2 = box[2];
-  const double scale = 2097152.0 / box[3];
   bool bad = false;
   // each step a thread handles kKeygenIpt particles whose loads are all issued
   // before any is used (indices past the end are clamped and masked)
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kKeygenIpt;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kKeygenIpt + threadIdx.x; i0 < n;
        i0 += step) {
-    float x[kKeygenIpt], y[kKeygenIpt], z[kKeygenIpt];
+    float x[kKeygenIpt], y[kKeygenIpt], z[kKeygenIpt], m[kKeygenIpt];
 #pragma unroll
     for (int r = 0; r < kKeygenIpt; ++r) {
       const int64_t i = min(i0 + (int64_t)r * blockDim.x, n - 1);
       x[r] = pos[3 * i + 0];
       y[r] = pos[3 * i + 1];
       z[r] = pos[3 * i + 2];
+      m[r] = mass[i];
     }
 #pragma unroll
     for (int r = 0; r < kKeygenIpt; ++r) {
       const int64_t i = i0 + (int64_t)r * blockDim.x;
       const bool valid = i < n;
+      const int b = nsets == 1 ? 0 : upper_index(s_off, nsets + 1, i);
+      const double lo0 = box[4 * b + 0], lo1 = box[4 * b + 1], lo2 = box[4 * b + 2];
+      const double scale = 2097152.0 / box[4 * b + 3];
       bad |= valid && !(isfinite(x[r]) && isfinite(y[r]) && isfinite(z[r]));
       const uint64_t qx = quantise(x[r], lo0, scale);
       const uint64_t qy = quantise(y[r], lo1, scale);
       const uint64_t qz = quantise(z[r], lo2, scale);
       const uint64_t key = (1ull << 63) | (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
-      if (valid) keys[i] = key;
+      if (valid) {
+        keys[i] = key;
+        // (x, y, z, m) in one 16-byte record: the reorder step gathers one line each
+        packed[i] = make_float4(x[r], y[r], z[r], m[r]);
+      }
       // digit histograms of every radix pass; a wave whose lanes all share the
       // digit adds once (the upper digits of clustered data are mostly uniform)
       const uint64_t active = __ballot(valid);
@@ -259,50 +411,76 @@ int keygen_blocks(int64_t n) {
   return (int)b;
 }
 
-hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const tb_tree &out,
-                         hipStream_t s) {
+hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const float *mass,
+                         const tb_tree &out, hipStream_t s) {
   const int blocks = keygen_blocks(p.n);
-  const int passes = p.sort.passes();
+  const int passes = p.key_passes;
+  const size_t lds = 4 * (size_t)(p.nsets + 1);
+#define TB_KEYGEN(B)                                                                          \
+  k_keygen<B><<<blocks, kKeygenThreads, lds, s>>>(pos, mass, p.n, w.set_off, p.nsets, w.box, \
+                                                  w.keys0, w.packed, w.hist_part, passes,    \
+                                                  out.status)
   switch (p.sort.bits) {
-    case 8: k_keygen<8><<<blocks, kKeygenThreads, 0, s>>>(pos, p.n, w.box, w.keys0, w.hist_part, passes, out.status); break;
-    case 9: k_keygen<9><<<blocks, kKeygenThreads, 0, s>>>(pos, p.n, w.box, w.keys0, w.hist_part, passes, out.status); break;
-    case 10: k_keygen<10><<<blocks, kKeygenThreads, 0, s>>>(pos, p.n, w.box, w.keys0, w.hist_part, passes, out.status); break;
-    case 11: k_keygen<11><<<blocks, kKeygenThreads, 0, s>>>(pos, p.n, w.box, w.keys0, w.hist_part, passes, out.status); break;
+    case 8: TB_KEYGEN(8); break;
+    case 9: TB_KEYGEN(9); break;
     default: return hipErrorInvalidValue;
   }
+#undef TB_KEYGEN
   return hipGetLastError();
 }
 
 hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s) {
-  const int cols = p.sort.passes() * p.sort.radix();
+  const int cols = p.key_passes * p.sort.radix();
   k_hist_reduce<<<(cols + 15) / 16, 256, 0, s>>>(w.hist_part, keygen_blocks(p.n), cols, w.hist);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// optional sorted-key output (a copy kernel keeps captured graphs simple)
+// ---------------------------------------------------------------------------
+__global__ void k_copy_u64(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy_keys(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
+  int64_t blocks = (p.n + 1023) / 1024;
+  if (blocks > 2048) blocks = 2048;
+  k_copy_u64<<<(unsigned)blocks, 256, 0, s>>>(sorted_keys(p, w), out.key_sorted, p.n);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // N == 0: only the scalar outputs are written
 // ---------------------------------------------------------------------------
-__global__ void k_empty(int64_t *level_offset, int64_t *n_cells, int32_t *status_word,
-                        double *box_out, int box_given, double lo0, double lo1, double lo2,
+__global__ void k_empty(int64_t *level_offset, int32_t nsets, int64_t *n_cells,
+                        int64_t *cell_offsets, int32_t *status_word, double *box_out,
+                        const tb_box *boxes_in, int host_box, double lo0, double lo1, double lo2,
                         double side) {
-  const int t = threadIdx.x;
-  if (t < kLevels + 1) level_offset[t] = 0;
-  if (t == 0) {
+  for (int64_t i = threadIdx.x; i < (int64_t)nsets * (kLevels + 1); i += blockDim.x)
+    level_offset[i] = 0;
+  if (cell_offsets)
+    for (int64_t i = threadIdx.x; i <= nsets; i += blockDim.x) cell_offsets[i] = 0;
+  if (box_out) {
+    for (int64_t b = threadIdx.x; b < nsets; b += blockDim.x) {
+      box_out[4 * b + 0] = boxes_in ? boxes_in[b].lo[0] : (host_box ? lo0 : 0.0);
+      box_out[4 * b + 1] = boxes_in ? boxes_in[b].lo[1] : (host_box ? lo1 : 0.0);
+      box_out[4 * b + 2] = boxes_in ? boxes_in[b].lo[2] : (host_box ? lo2 : 0.0);
+      box_out[4 * b + 3] = boxes_in ? boxes_in[b].side : (host_box ? side : 1.0);
+    }
+  }
+  if (threadIdx.x == 0) {
     *n_cells = 0;
     *status_word = 0;
-    if (box_out) {
-      box_out[0] = box_given ? lo0 : 0.0;
-      box_out[1] = box_given ? lo1 : 0.0;
-      box_out[2] = box_given ? lo2 : 0.0;
-      box_out[3] = box_given ? side : 1.0;
-    }
   }
 }
 
-hipError_t launch_empty(const tb_tree &out, const tb_box *box, hipStream_t s) {
-  k_empty<<<1, 64, 0, s>>>(out.level_offset, out.n_cells, out.status, out.box_out, box ? 1 : 0,
-                           box ? box->lo[0] : 0.0, box ? box->lo[1] : 0.0,
-                           box ? box->lo[2] : 0.0, box ? box->side : 1.0);
+hipError_t launch_empty(const tb_tree &out, int32_t nsets, const BatchIn &in,
+                        int64_t *cell_offsets, hipStream_t s) {
+  const tb_box *hb = in.host_box;
+  k_empty<<<1, 256, 0, s>>>(out.level_offset, nsets, out.n_cells, cell_offsets, out.status,
+                            out.box_out, in.dev_boxes, hb ? 1 : 0, hb ? hb->lo[0] : 0.0,
+                            hb ? hb->lo[1] : 0.0, hb ? hb->lo[2] : 0.0, hb ? hb->side : 1.0);
   return hipGetLastError();
 }
 

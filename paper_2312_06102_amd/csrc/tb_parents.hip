@@ -31,18 +31,27 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
     int depth, const int64_t *__restrict__ level_offset, const uint64_t *__restrict__ cell_key,
     int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr,
     double *__restrict__ com, double *__restrict__ quad, const int32_t *__restrict__ head_parent,
-    const double *__restrict__ box, int32_t *__restrict__ status_word) {
+    const double *__restrict__ box, int32_t *__restrict__ status_word, int32_t nsets,
+    const int64_t *__restrict__ par_start) {
   __shared__ uint64_t s_key[kChunk + kHalo + 1];  // keys of [base - 1, base + kChunk + kHalo)
   __shared__ int32_t s_cnt[kChunk + kHalo];
   __shared__ __align__(16) double s_com[(kChunk + kHalo) * 4];
   __shared__ __align__(16) double s_quad[(kChunk + kHalo) * 6];
 
-  const int64_t P0 = level_offset[depth], P1 = level_offset[depth + 1];
-  const int64_t L1 = P1, L2 = level_offset[depth + 2];  // the children at depth + 1
-  const double q = ldexp(box[3], -(depth + 2));          // a quarter of the parent side
+  __shared__ int s_set;
+  const int64_t *row = par_start + depth * (nsets + 1);
+  const int64_t n_chunks = row[nsets];
   bool internal = false;
-  for (int64_t base = L1 + (int64_t)blockIdx.x * kChunk; base < L2;
-       base += (int64_t)gridDim.x * kChunk) {
+  for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+    // the chunk's set, then the set's parents [P0, P1) and children [L1, L2)
+    if (threadIdx.x == 0) s_set = upper_index(row, nsets + 1, ch);
+    __syncthreads();
+    const int b = s_set;
+    const int64_t *lo_b = level_offset + b * (kLevels + 1);
+    const int64_t P0 = lo_b[depth], P1 = lo_b[depth + 1];
+    const int64_t L1 = P1, L2 = lo_b[depth + 2];
+    const double q = ldexp(box[4 * b + 3], -(depth + 2));  // a quarter of the parent side
+    const int64_t base = L1 + (ch - row[b]) * (int64_t)kChunk;
     // stage the chunk: every load is issued before the first LDS store
     const int64_t lim = min((int64_t)(kChunk + kHalo), L2 - base);
     constexpr int KN = (kChunk + kHalo + 1 + kParentThreads - 1) / kParentThreads;
@@ -172,21 +181,28 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
     int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr,
     float *__restrict__ com, float *__restrict__ quad, float *__restrict__ m_lo,
     const int32_t *__restrict__ head_parent, const double *__restrict__ box,
-    int32_t *__restrict__ status_word) {
+    int32_t *__restrict__ status_word, int32_t nsets, const int64_t *__restrict__ par_start) {
   __shared__ uint64_t s_key[kChunk + kHalo + 1];
   __shared__ int32_t s_cnt[kChunk + kHalo];
   __shared__ float4 s_com[kChunk + kHalo];
   __shared__ __align__(16) float s_quad[(kChunk + kHalo) * 6];
   __shared__ float s_mlo[kChunk + kHalo];
 
-  const int64_t P0 = level_offset[depth], P1 = level_offset[depth + 1];
-  const int64_t L1 = P1, L2 = level_offset[depth + 2];
-  const float lc = ldexpf((float)box[3], -(depth + 1));  // child side
-  const float lp = 2.0f * lc;                            // parent side
-  const float inv_lc = 1.0f / lc, inv_lc2 = inv_lc * inv_lc;
+  __shared__ int s_set;
+  const int64_t *row = par_start + depth * (nsets + 1);
+  const int64_t n_chunks = row[nsets];
   bool internal = false;
-  for (int64_t base = L1 + (int64_t)blockIdx.x * kChunk; base < L2;
-       base += (int64_t)gridDim.x * kChunk) {
+  for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+    if (threadIdx.x == 0) s_set = upper_index(row, nsets + 1, ch);
+    __syncthreads();
+    const int b = s_set;
+    const int64_t *lo_b = level_offset + b * (kLevels + 1);
+    const int64_t P0 = lo_b[depth], P1 = lo_b[depth + 1];
+    const int64_t L1 = P1, L2 = lo_b[depth + 2];
+    const float lc = ldexpf((float)box[4 * b + 3], -(depth + 1));  // child side
+    const float lp = 2.0f * lc;                                    // parent side
+    const float inv_lc = 1.0f / lc, inv_lc2 = inv_lc * inv_lc;
+    const int64_t base = L1 + (ch - row[b]) * (int64_t)kChunk;
     const int64_t lim = min((int64_t)(kChunk + kHalo), L2 - base);
     constexpr int KN = (kChunk + kHalo + 1 + kParentThreads - 1) / kParentThreads;
     constexpr int CN = (kChunk + kHalo + kParentThreads - 1) / kParentThreads;
@@ -299,25 +315,25 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
 
 hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
                           hipStream_t s) {
-  // at most 8^(depth+1) children one depth down
+  // at most 8^(depth+1) children per set one depth down, in chunks of kChunk
   int64_t bound = p.c_max;
   if (depth + 1 < 10) {
-    const int64_t b8 = int64_t(1) << (3 * (depth + 1));
+    const int64_t b8 = (int64_t(1) << (3 * (depth + 1))) * p.nsets;
     if (b8 < bound) bound = b8;
   }
-  int64_t blocks = (bound + kChunk - 1) / kChunk;
+  int64_t blocks = (bound + kChunk - 1) / kChunk + p.nsets;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
   if ((p.flags & 0xffu) == TB_MIXED)
     k_parents_mixed<<<(unsigned)blocks, kParentThreads, 0, s>>>(
-        depth, out.level_offset, out.cell_key, out.cell_count, out.child_ptr,
+        depth, w.lvl_off, out.cell_key, out.cell_count, out.child_ptr,
         static_cast<float *>(out.com), static_cast<float *>(out.quad), w.m_lo, w.head_parent,
-        w.box, out.status);
+        w.box, out.status, p.nsets, w.par_start);
   else
     k_parents_fp64<<<(unsigned)blocks, kParentThreads, 0, s>>>(
-        depth, out.level_offset, out.cell_key, out.cell_count, out.child_ptr,
+        depth, w.lvl_off, out.cell_key, out.cell_count, out.child_ptr,
         static_cast<double *>(out.com), static_cast<double *>(out.quad), w.head_parent, w.box,
-        out.status);
+        out.status, p.nsets, w.par_start);
   return hipGetLastError();
 }
 

@@ -48,13 +48,18 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
   return w & ((1u << BITS) - 1u);
 }
 
-template <int BITS, int IPT, int THREADS>
+// SETID = false: the digit is taken from the key.  SETID = true (batches):
+// the digit is taken from the set that holds the payload's original index, and
+// the keys travel as payload, so that after the key passes these passes group
+// the particles by set without disturbing the key order inside a set.
+template <int BITS, int IPT, int THREADS, bool SETID>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const uint64_t *__restrict__ kin, uint64_t *__restrict__ kout,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
     const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
-    int32_t *__restrict__ status_word, uint32_t n_tiles) {
+    int32_t *__restrict__ status_word, uint32_t n_tiles, const int64_t *__restrict__ set_off,
+    int32_t nsets) {
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
   constexpr int TILE = THREADS * IPT;
@@ -67,6 +72,17 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   __shared__ int32_t s_goff[R];            // global position minus tile-local position
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
+  extern __shared__ uint32_t s_soff[];  // SETID: [nsets + 1] set offsets
+  if constexpr (SETID) {
+    for (int i = threadIdx.x; i <= nsets; i += THREADS) s_soff[i] = (uint32_t)set_off[i];
+  }
+  auto digit = [&](uint64_t kk, uint32_t vv) -> uint32_t {
+    if constexpr (SETID) {
+      return ((uint32_t)upper_index(s_soff, nsets + 1, (int64_t)vv) >> shift) & ((1u << BITS) - 1u);
+    } else {
+      return digit_of<BITS>(kk, shift);
+    }
+  };
 
   if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
   // the global digit counts do not depend on the tile: fetch them meanwhile
@@ -113,7 +129,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const bool valid = wbase + j * 64 < n;
-    const uint32_t d = digit_of<BITS>(k[j], shift);
+    const uint32_t d = digit(k[j], v[j]);
     const uint64_t vmask = __ballot(valid);
     uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
 #pragma unroll
@@ -188,7 +204,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     if (wbase + j * 64 < n) {
-      const uint32_t d = digit_of<BITS>(k[j], shift);
+      const uint32_t d = digit(k[j], v[j]);
       const uint32_t p = s_tstart[d] + wc[d] + rk[j];
       s_keys[p] = k[j];
       s_vals[p] = v[j];
@@ -203,7 +219,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   bool bad = false;
   for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
     const uint64_t key = s_keys[i];
-    const uint32_t d = digit_of<BITS>(key, shift);
+    const uint32_t d = digit(key, s_vals[i]);
     const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
     if (gp >= n) {  // cannot happen with consistent histograms
       bad = true;
@@ -218,7 +234,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 template <int BITS, int IPT, int THREADS>
 static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
-  const int P = p.sort.passes();
+  const int P = p.key_passes + p.set_passes;
   uint64_t *K[2] = {w.keys0, w.keys1};
   // the last pass must write its payload into out.perm
   uint32_t *V[2];
@@ -227,10 +243,14 @@ static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb
   uint64_t *S[2] = {w.status0, w.status1};
   const uint32_t *vin = pass == 0 ? nullptr : V[pass % 2];
   const int R = 1 << BITS;
-  k_onesweep<BITS, IPT, THREADS><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
-      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, pass * BITS,
+  const bool setid = pass >= p.key_passes;
+  const int shift = setid ? (pass - p.key_passes) * BITS : pass * BITS;
+  auto k = setid ? k_onesweep<BITS, IPT, THREADS, true> : k_onesweep<BITS, IPT, THREADS, false>;
+  const size_t lds = setid ? 4 * (size_t)(p.nsets + 1) : 0;
+  k<<<(unsigned)p.sort_tiles, THREADS, lds, s>>>(
+      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift,
       w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, out.status,
-      (uint32_t)p.sort_tiles);
+      (uint32_t)p.sort_tiles, w.set_off, p.nsets);
   return hipGetLastError();
 }
 

@@ -174,6 +174,8 @@ def batched_plummer(sizes, seed: int = 4):
     pos = np.empty((int(offsets[-1]), 3), dtype=np.float32)
     mass = np.empty(int(offsets[-1]), dtype=np.float32)
     for b, (nb, ss) in enumerate(zip(sizes, children)):
+        if nb == 0:
+            continue
         rng = np.random.Generator(np.random.PCG64(ss))
         r = plummer_radii(rng, int(nb))
         x = r[:, None] * _isotropic(rng, int(nb))

@@ -5,11 +5,15 @@ Argument marshalling only: every step of a build runs in the HIP kernels of
 no CPU fallback: without the native library, or with tensors that are not on a
 GPU, every call raises.
 
-The functions ``tb_max_cells``, ``tb_workspace_bytes``, ``tb_build``,
-``tb_build_sync``, ``tb_trace_enable``, ``tb_trace_read``, ``tb_sort_configs``
-and ``tb_version`` mirror the C entry points of the same names.  ``Builder``
-keeps a workspace and output buffers for repeated builds; ``build`` is the
-one-shot convenience form.
+The functions ``tb_max_cells``, ``tb_workspace_bytes``,
+``tb_workspace_bytes_batched``, ``tb_build``, ``tb_build_sync``,
+``tb_build_batched``, ``tb_build_batched_sync``, ``tb_trace_enable``,
+``tb_trace_read``, ``tb_sort_configs`` and ``tb_version`` mirror the C entry
+points of the same names.  ``Builder`` keeps a workspace and output buffers for
+repeated builds of one set, ``BatchBuilder`` the same for batches of sets
+stored back to back; ``build`` and ``build_batched`` are the one-shot forms.
+Both builders can record their build into a HIP graph (``capture``) and replay
+it (``replay``).
 """
 from __future__ import annotations
 
@@ -34,12 +38,16 @@ TB_ERR_INTERNAL = -7
 TB_STATUS_NONFINITE = 1
 TB_STATUS_MASS = 2
 TB_STATUS_INTERNAL = 4
+TB_STATUS_SETS = 8
+TB_STATUS_BOX = 16
 TB_FP64 = 0
 TB_MIXED = 1
 TB_MAX_DEPTH = 21
 TB_MAX_NLEAF = 1024
+TB_MAX_SETS = 16383
 
-EXPORTS = ("tb_max_cells", "tb_workspace_bytes", "tb_build", "tb_build_sync", "tb_trace_enable",
+EXPORTS = ("tb_max_cells", "tb_workspace_bytes", "tb_workspace_bytes_batched", "tb_build",
+           "tb_build_sync", "tb_build_batched", "tb_build_batched_sync", "tb_trace_enable",
            "tb_trace_read", "tb_sort_configs", "tb_version")
 
 _ERRNAMES = {TB_ERR_ARG: "TB_ERR_ARG", TB_ERR_BOX: "TB_ERR_BOX", TB_ERR_WORKSPACE: "TB_ERR_WORKSPACE",
@@ -101,6 +109,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
            ctypes.POINTER(TbTree), P]
     lib.tb_build.argtypes = sig
     lib.tb_build_sync.argtypes = sig
+    lib.tb_workspace_bytes_batched.argtypes = [i64, i32, i32, ctypes.c_uint32,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+    bsig = [P, P, i64, i32, P, i32, P, ctypes.c_uint32, P, ctypes.c_size_t,
+            ctypes.POINTER(TbTree), P, P]
+    lib.tb_build_batched.argtypes = bsig
+    lib.tb_build_batched_sync.argtypes = bsig
     lib.tb_trace_enable.argtypes = [ctypes.c_int]
     lib.tb_trace_read.argtypes = [ctypes.POINTER(TbTraceEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.tb_sort_configs.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
@@ -146,6 +160,37 @@ def tb_build_sync(pos_ptr: int, mass_ptr: int, n: int, n_leaf: int, box: Optiona
                                         int(n_leaf), ctypes.byref(box) if box is not None else None,
                                         int(flags), ctypes.c_void_p(ws_ptr), int(ws_bytes),
                                         ctypes.byref(out), ctypes.c_void_p(stream))
+
+
+def tb_workspace_bytes_batched(n_total: int, nsets: int, n_leaf: int, flags: int = TB_FP64) -> int:
+    out = ctypes.c_size_t(0)
+    rc = load_library().tb_workspace_bytes_batched(int(n_total), int(nsets), int(n_leaf), int(flags),
+                                                   ctypes.byref(out))
+    if rc:
+        _raise(rc, "tb_workspace_bytes_batched")
+    return out.value
+
+
+def tb_build_batched(pos_ptr: int, mass_ptr: int, n_total: int, nsets: int, offsets_ptr: int,
+                     n_leaf: int, boxes_ptr: Optional[int], flags: int, ws_ptr: int, ws_bytes: int,
+                     out: TbTree, cell_offsets_ptr: Optional[int], stream: int) -> int:
+    """Raw call: device pointers as ints (boxes / cell_offsets may be None)."""
+    return load_library().tb_build_batched(
+        ctypes.c_void_p(pos_ptr), ctypes.c_void_p(mass_ptr), int(n_total), int(nsets),
+        ctypes.c_void_p(offsets_ptr), int(n_leaf), ctypes.c_void_p(boxes_ptr), int(flags),
+        ctypes.c_void_p(ws_ptr), int(ws_bytes), ctypes.byref(out),
+        ctypes.c_void_p(cell_offsets_ptr), ctypes.c_void_p(stream))
+
+
+def tb_build_batched_sync(pos_ptr: int, mass_ptr: int, n_total: int, nsets: int, offsets_ptr: int,
+                          n_leaf: int, boxes_ptr: Optional[int], flags: int, ws_ptr: int,
+                          ws_bytes: int, out: TbTree, cell_offsets_ptr: Optional[int],
+                          stream: int) -> int:
+    return load_library().tb_build_batched_sync(
+        ctypes.c_void_p(pos_ptr), ctypes.c_void_p(mass_ptr), int(n_total), int(nsets),
+        ctypes.c_void_p(offsets_ptr), int(n_leaf), ctypes.c_void_p(boxes_ptr), int(flags),
+        ctypes.c_void_p(ws_ptr), int(ws_bytes), ctypes.byref(out),
+        ctypes.c_void_p(cell_offsets_ptr), ctypes.c_void_p(stream))
 
 
 def tb_trace_enable(on: bool = True) -> None:
@@ -220,7 +265,8 @@ class TreeBuffers:
 
     @staticmethod
     def allocate(n: int, n_leaf: int, precision: str = "fp64", device="cuda",
-                 sorted_particles: bool = False, sorted_keys: bool = False) -> "TreeBuffers":
+                 sorted_particles: bool = False, sorted_keys: bool = False,
+                 nsets: int = 1) -> "TreeBuffers":
         cmax = max(tb_max_cells(n, n_leaf), 1)
         fdt = torch.float64 if precision == "fp64" else torch.float32
         kw = dict(device=device)
@@ -234,10 +280,12 @@ class TreeBuffers:
             child_ptr=torch.empty((cmax, 2), dtype=torch.int32, **kw),
             com=torch.empty((cmax, 4), dtype=fdt, **kw),
             quad=torch.empty((cmax, 6), dtype=fdt, **kw),
-            level_offset=torch.empty(TB_MAX_DEPTH + 2, dtype=torch.int64, **kw),
+            level_offset=torch.empty(TB_MAX_DEPTH + 2, dtype=torch.int64, **kw) if nsets == 1
+            else torch.empty((nsets, TB_MAX_DEPTH + 2), dtype=torch.int64, **kw),
             n_cells=torch.empty(1, dtype=torch.int64, **kw),
             status=torch.empty(1, dtype=torch.int32, **kw),
-            box_out=torch.empty(4, dtype=torch.float64, **kw),
+            box_out=torch.empty(4, dtype=torch.float64, **kw) if nsets == 1
+            else torch.empty((nsets, 4), dtype=torch.float64, **kw),
             pos_sorted=torch.empty((nn, 3), dtype=torch.float32, **kw) if sorted_particles else None,
             mass_sorted=torch.empty(nn, dtype=torch.float32, **kw) if sorted_particles else None,
             key_sorted=torch.empty(nn, dtype=torch.int64, **kw) if sorted_keys else None,
@@ -262,7 +310,45 @@ def _box_struct(box) -> Optional[TbBox]:
     return b
 
 
-class Builder:
+def _check_status(st: int, what: str) -> None:
+    if st & TB_STATUS_NONFINITE:
+        _raise(TB_ERR_NONFINITE, what)
+    if st & TB_STATUS_MASS:
+        _raise(TB_ERR_MASS, what)
+    if st & TB_STATUS_SETS:
+        _raise(TB_ERR_ARG, what)
+    if st & TB_STATUS_BOX:
+        _raise(TB_ERR_BOX, what)
+    if st & TB_STATUS_INTERNAL:
+        _raise(TB_ERR_INTERNAL, what)
+
+
+class _Graphable:
+    """Records one launch() into a HIP graph (through torch's graph capture on a
+    side stream) and replays it.  A build holds no memset node and no host
+    synchronisation, so the captured graph is the plain kernel sequence."""
+
+    _graph = None
+
+    def capture(self, *args, **kwargs) -> None:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.launch(*args, **kwargs)  # resolves kernel attributes outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.launch(*args, **kwargs)
+        self._graph = g
+
+    def replay(self) -> None:
+        if self._graph is None:
+            raise RuntimeError("capture() first")
+        self._graph.replay()
+
+
+class Builder(_Graphable):
     """Reusable workspace + outputs for repeated builds of N particles."""
 
     def __init__(self, n: int, n_leaf: int = 16, precision: str = "fp64", sort_config: int = 0,
@@ -293,13 +379,7 @@ class Builder:
     def result(self) -> dict:
         """Synchronise and return the outputs trimmed to n_cells (device tensors)."""
         torch.cuda.synchronize()
-        st = int(self.out.status.item())
-        if st & TB_STATUS_NONFINITE:
-            _raise(TB_ERR_NONFINITE, "tb_build")
-        if st & TB_STATUS_MASS:
-            _raise(TB_ERR_MASS, "tb_build")
-        if st & TB_STATUS_INTERNAL:
-            _raise(TB_ERR_INTERNAL, "tb_build")
+        _check_status(int(self.out.status.item()), "tb_build")
         c = int(self.out.n_cells.item())
         o = self.out
         res = dict(perm=o.perm[:self.n], cell_key=o.cell_key[:c], cell_level=o.cell_level[:c],
@@ -324,4 +404,79 @@ def build(pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 16, box=None,
     b = Builder(pos.shape[0], n_leaf, precision, sort_config, pos.device, sorted_particles,
                 sorted_keys)
     b.launch(pos, mass, box)
+    return b.result()
+
+
+class BatchBuilder(_Graphable):
+    """Reusable workspace + outputs for batches of `nsets` sets holding `n_total`
+    particles together, stored back to back (set b = particles
+    [set_offsets[b], set_offsets[b+1]))."""
+
+    def __init__(self, n_total: int, nsets: int, n_leaf: int = 16, precision: str = "fp64",
+                 sort_config: int = 0, device="cuda", sorted_particles: bool = False,
+                 sorted_keys: bool = False):
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        self.n, self.nsets, self.n_leaf, self.precision = int(n_total), int(nsets), int(n_leaf), precision
+        self.flags = (TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
+        self.ws_bytes = tb_workspace_bytes_batched(self.n, self.nsets, self.n_leaf, self.flags)
+        self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
+                                        sorted_keys, nsets=self.nsets)
+        if self.nsets == 1:  # keep the [B][23] / [B][4] shapes for one set too
+            self.out.level_offset = self.out.level_offset.view(1, -1)
+            self.out.box_out = self.out.box_out.view(1, -1)
+        self.cell_offsets = torch.empty(self.nsets + 1, dtype=torch.int64, device=device)
+        self._struct = self.out.struct()
+
+    def launch(self, pos: torch.Tensor, mass: torch.Tensor, set_offsets: torch.Tensor,
+               boxes: Optional[torch.Tensor] = None, stream=None) -> None:
+        """Asynchronous batched build.  set_offsets: int64 [B+1] on the GPU;
+        boxes: float64 [B][4] (lo, side) on the GPU, or None (boxes from data)."""
+        _check_device_tensor(pos, "pos", torch.float32, (3,))
+        _check_device_tensor(mass, "mass", torch.float32)
+        _check_device_tensor(set_offsets, "set_offsets", torch.int64)
+        if pos.shape[0] != self.n or mass.shape[0] != self.n:
+            raise ValueError(f"this BatchBuilder is sized for n_total={self.n}")
+        if set_offsets.shape[0] != self.nsets + 1:
+            raise ValueError(f"set_offsets must hold nsets + 1 = {self.nsets + 1} entries")
+        if boxes is not None:
+            _check_device_tensor(boxes, "boxes", torch.float64, (4,))
+            if boxes.shape[0] != self.nsets:
+                raise ValueError("boxes must be [nsets][4]")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = tb_build_batched(pos.data_ptr(), mass.data_ptr(), self.n, self.nsets,
+                              set_offsets.data_ptr(), self.n_leaf, _ptr(boxes), self.flags,
+                              self.workspace.data_ptr(), self.ws_bytes, self._struct,
+                              self.cell_offsets.data_ptr(), s.cuda_stream)
+        if rc:
+            _raise(rc, "tb_build_batched")
+
+    def result(self) -> dict:
+        """Synchronise and return the outputs trimmed to n_cells (device tensors)."""
+        torch.cuda.synchronize()
+        _check_status(int(self.out.status.item()), "tb_build_batched")
+        c = int(self.out.n_cells.item())
+        o = self.out
+        res = dict(perm=o.perm[:self.n], cell_key=o.cell_key[:c], cell_level=o.cell_level[:c],
+                   cell_first=o.cell_first[:c], cell_count=o.cell_count[:c],
+                   child_ptr=o.child_ptr[:c], com=o.com[:c], quad=o.quad[:c],
+                   level_offset=o.level_offset.clone(), n_cells=c, box=o.box_out.clone(),
+                   cell_offsets=self.cell_offsets.clone())
+        if o.pos_sorted is not None:
+            res["pos_sorted"] = o.pos_sorted[:self.n]
+            res["mass_sorted"] = o.mass_sorted[:self.n]
+        if o.key_sorted is not None:
+            res["key_sorted"] = o.key_sorted[:self.n]
+        return res
+
+
+def build_batched(pos: torch.Tensor, mass: torch.Tensor, set_offsets: torch.Tensor,
+                  n_leaf: int = 16, boxes: Optional[torch.Tensor] = None,
+                  precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
+                  sorted_keys: bool = False) -> dict:
+    """One-shot batched build; returns device tensors trimmed to n_cells."""
+    b = BatchBuilder(pos.shape[0], set_offsets.shape[0] - 1, n_leaf, precision, sort_config,
+                     pos.device, sorted_particles, sorted_keys)
+    b.launch(pos, mass, set_offsets, boxes)
     return b.result()

@@ -135,3 +135,35 @@ def test_no_oracle_in_product_path():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text and "tb_oracle" not in text, f
+
+
+def test_batched_workspace_and_validation():
+    one = tb.tb_workspace_bytes_batched(100000, 1, 16)
+    assert one == tb.tb_workspace_bytes(100000, 16)
+    many = tb.tb_workspace_bytes_batched(100000, 4096, 16)
+    assert many > one
+    assert tb.tb_workspace_bytes_batched(0, 7, 16) == 0
+    for bad in [(100, 0, 16), (100, tb.TB_MAX_SETS + 1, 16), (100, 4, 0), (-1, 4, 16)]:
+        with pytest.raises(tb.TreeBuildArgError):
+            tb.tb_workspace_bytes_batched(*bad)
+    t = _fake_tree()
+    ws = 1 << 40
+    call = lambda n, B, offs, nl=16, flags=0, wsb=ws: tb.tb_build_batched(
+        0x10, 0x20, n, B, offs, nl, None, flags, 0x30, wsb, t, 0x40, 0)
+    assert call(100, 0, 0x50) == tb.TB_ERR_ARG
+    assert call(100, tb.TB_MAX_SETS + 1, 0x50) == tb.TB_ERR_ARG
+    assert call(100, 4, None) == tb.TB_ERR_ARG
+    assert call(100, 4, 0x50, nl=0) == tb.TB_ERR_ARG
+    assert call(100, 4, 0x50, flags=77) == tb.TB_ERR_ARG
+    assert call(100, 4, 0x50, wsb=16) == tb.TB_ERR_WORKSPACE
+
+
+def test_status_bits_distinct():
+    text = open(HEADER).read()
+    bits = [int(re.search(rf"#define {n} (\d+)", text).group(1)) for n in
+            ("TB_STATUS_NONFINITE", "TB_STATUS_MASS", "TB_STATUS_INTERNAL", "TB_STATUS_SETS",
+             "TB_STATUS_BOX")]
+    assert bits == [tb.TB_STATUS_NONFINITE, tb.TB_STATUS_MASS, tb.TB_STATUS_INTERNAL,
+                    tb.TB_STATUS_SETS, tb.TB_STATUS_BOX]
+    assert len(set(bits)) == 5 and all(b & (b - 1) == 0 for b in bits)
+    assert int(re.search(r"#define TB_MAX_SETS (\d+)", text).group(1)) == tb.TB_MAX_SETS

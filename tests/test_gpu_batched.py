@@ -1,0 +1,325 @@
+"""Batched builds through the C ABI: B independent sets in one launch sequence.
+
+Every set's tree must equal, bit for bit, the tree a standalone build of that
+set gives (the batch changes where the outputs sit, not what they are), and the
+oracle's tree of that set: structure bit-exact, FP64 moments within 1e-12 in the
+per-cell relative measures of test_gpu_parity.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2312_06102_amd import datagen as dg
+from paper_2312_06102_amd import treebuild as tb
+from test_gpu_parity import FP64_TOL, MIXED_TOL, compare_structure, gpu_build, moment_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _to_np(res):
+    out = {}
+    for k, v in res.items():
+        out[k] = v.cpu().numpy() if torch.is_tensor(v) else v
+    out["cell_key"] = out["cell_key"].view(np.uint64)
+    if "key_sorted" in out:
+        out["key_sorted"] = out["key_sorted"].view(np.uint64)
+    return out
+
+
+def batch_build(pos, mass, offsets, n_leaf, boxes=None, **kw):
+    """boxes: None (from data) or an array [B][4] of (lo, side)."""
+    print(f"[batch_build] N={pos.shape[0]} B={len(offsets) - 1} n_leaf={n_leaf} "
+          f"boxes={'data' if boxes is None else 'given'} {kw}", flush=True)
+    p = torch.from_numpy(np.ascontiguousarray(pos, np.float32)).cuda()
+    m = torch.from_numpy(np.ascontiguousarray(mass, np.float32)).cuda()
+    off = torch.from_numpy(np.asarray(offsets, np.int64)).cuda()
+    bx = None if boxes is None else torch.from_numpy(np.asarray(boxes, np.float64)).cuda()
+    return _to_np(tb.build_batched(p, m, off, n_leaf, bx, sorted_keys=True, **kw))
+
+
+def set_view(g, offsets, b):
+    """Set b's tree cut out of a batched result, in the indexing of a
+    standalone build of that set."""
+    S, E = int(offsets[b]), int(offsets[b + 1])
+    c0, c1 = int(g["cell_offsets"][b]), int(g["cell_offsets"][b + 1])
+    cp = g["child_ptr"][c0:c1].copy()
+    cp[cp[:, 0] >= 0, 0] -= c0
+    return {
+        "n_cells": c1 - c0,
+        "perm": g["perm"][S:E] - S,
+        "cell_key": g["cell_key"][c0:c1],
+        "cell_level": g["cell_level"][c0:c1],
+        "cell_first": g["cell_first"][c0:c1] - S,
+        "cell_count": g["cell_count"][c0:c1],
+        "child_ptr": cp,
+        "com": g["com"][c0:c1],
+        "quad": g["quad"][c0:c1],
+        "level_offset": g["level_offset"][b] - c0,
+        "box": g["box"][b],
+        "key_sorted": g["key_sorted"][S:E],
+    }
+
+
+def check_offsets(g, offsets):
+    B = len(offsets) - 1
+    co = g["cell_offsets"]
+    assert co.shape == (B + 1,) and co[0] == 0 and co[-1] == g["n_cells"]
+    assert np.all(np.diff(co) >= 0)
+    assert np.array_equal(g["level_offset"][:, 0], co[:-1])
+    assert np.array_equal(g["level_offset"][:, -1], co[1:])
+    # every set's particles stay in its own range of the permutation
+    for b in range(B):
+        S, E = int(offsets[b]), int(offsets[b + 1])
+        assert np.array_equal(np.sort(g["perm"][S:E]), np.arange(S, E))
+
+
+def oracle_set(pos, mass, n_leaf, box):
+    lo, side = (float(box[0]), float(box[1]), float(box[2])), float(box[3])
+    return oracle.build(pos, mass, n_leaf, lo=lo, side=side)
+
+
+def check_against_oracle(pos, mass, offsets, n_leaf, g, sets, tol=FP64_TOL):
+    worst = [0.0, 0.0, 0.0]
+    for b in sets:
+        S, E = int(offsets[b]), int(offsets[b + 1])
+        v = set_view(g, offsets, b)
+        if E == S:
+            assert v["n_cells"] == 0
+            continue
+        o = oracle_set(pos[S:E], mass[S:E], n_leaf, v["box"])
+        compare_structure(v, o)
+        _, keys = oracle.keys(pos[S:E], tuple(v["box"][:3]), float(v["box"][3]))
+        assert np.array_equal(v["key_sorted"], keys[o["perm"]])
+        errs = moment_errors(v["com"].astype(np.float64), v["quad"].astype(np.float64), o["com"],
+                             o["quad"], o["cell_level"], float(v["box"][3]))
+        worst = [max(a, e) for a, e in zip(worst, errs)]
+        assert max(errs) <= tol, (b, errs)
+    return worst
+
+
+def uneven_sizes():
+    # empty sets, single particles, tile edges (2048) and a few larger sets
+    return np.array([0, 1, 2, 16, 17, 0, 2047, 2048, 2049, 4096, 5, 0, 30000, 333, 12345, 1,
+                     65536, 7, 0, 100003, 3000], np.int64)
+
+
+def plummer_batch(sizes, seed):
+    pos, mass, offsets = dg.batched_plummer(sizes, seed=seed)
+    return pos, mass, offsets
+
+
+# --------------------------------------------------------------------------
+# parity per set
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("boxes", ["data", "given"])
+def test_uneven_sets_vs_oracle_and_standalone(boxes):
+    sizes = uneven_sizes()
+    pos, mass, offsets = plummer_batch(sizes, seed=31)
+    B = len(sizes)
+    bx = None
+    if boxes == "given":
+        # non-unit boxes that hold each set (sets are normalised into the unit cube)
+        bx = np.tile(np.array([-1.0, -1.0, -1.0, 4.0]), (B, 1))
+        bx[1::3] = [0.0, 0.0, 0.0, 1.0]
+    g = batch_build(pos, mass, offsets, 16, bx)
+    check_offsets(g, offsets)
+    check_against_oracle(pos, mass, offsets, 16, g, range(B))
+    # bit-identical to standalone builds of each set (moments included)
+    for b in range(B):
+        S, E = int(offsets[b]), int(offsets[b + 1])
+        if E == S:
+            continue
+        v = set_view(g, offsets, b)
+        box = None if bx is None else ((bx[b, 0], bx[b, 1], bx[b, 2]), bx[b, 3])
+        s = gpu_build(pos[S:E], mass[S:E], 16, box=box)
+        compare_structure(v, s)
+        assert np.array_equal(v["com"], s["com"]) and np.array_equal(v["quad"], s["quad"]), b
+        assert np.array_equal(v["box"], s["box"])
+
+
+def test_one_set_batch_equals_single_build():
+    pos, mass = dg.plummer(70000, seed=32)
+    g = batch_build(pos, mass, [0, 70000], 16, [[0.0, 0.0, 0.0, 1.0]])
+    s = gpu_build(pos, mass, 16)
+    v = set_view(g, [0, 70000], 0)
+    compare_structure(v, s)
+    assert np.array_equal(v["com"], s["com"]) and np.array_equal(v["quad"], s["quad"])
+
+
+@pytest.mark.parametrize("sort_config", [0, 2])
+def test_many_small_sets_two_set_digits(sort_config):
+    """600 sets: two 8-bit set-id digits (config 0) or one 9-bit digit (config 2)."""
+    rng = _rng(33)
+    sizes = rng.integers(0, 300, 600)
+    sizes[::50] = 0
+    pos, mass, offsets = plummer_batch(sizes, seed=33)
+    g = batch_build(pos, mass, offsets, 8, sort_config=sort_config)
+    check_offsets(g, offsets)
+    check_against_oracle(pos, mass, offsets, 8, g, range(len(sizes)))
+
+
+def test_thousands_of_sets():
+    """4096 sets of 0..96 particles (the set-count of the batched workload at a
+    size the oracle checks completely)."""
+    rng = _rng(34)
+    sizes = rng.integers(0, 97, 4096)
+    pos, mass, offsets = plummer_batch(sizes, seed=34)
+    g = batch_build(pos, mass, offsets, 16)
+    check_offsets(g, offsets)
+    check_against_oracle(pos, mass, offsets, 16, g, range(4096))
+
+
+def test_max_sets():
+    rng = _rng(35)
+    B = tb.TB_MAX_SETS
+    sizes = rng.integers(0, 9, B)
+    pos, mass, offsets = plummer_batch(sizes, seed=35)
+    g = batch_build(pos, mass, offsets, 4)
+    check_offsets(g, offsets)
+    check_against_oracle(pos, mass, offsets, 4, g, rng.integers(0, B, 400))
+    with pytest.raises(tb.TreeBuildArgError):
+        tb.tb_workspace_bytes_batched(100, B + 1, 16)
+
+
+def test_mixed_precision_batch():
+    sizes = uneven_sizes()
+    pos, mass, offsets = plummer_batch(sizes, seed=36)
+    rng = _rng(36)
+    mass = (mass * np.exp(rng.standard_normal(mass.shape[0]))).astype(np.float32)
+    g = batch_build(pos, mass, offsets, 16, precision="mixed")
+    check_offsets(g, offsets)
+    worst = check_against_oracle(pos, mass, offsets, 16, g, range(len(sizes)), tol=MIXED_TOL)
+    print(f"[mixed batch] max rel err M={worst[0]:.2e} com={worst[1]:.2e} Q={worst[2]:.2e}",
+          flush=True)
+
+
+def test_all_empty_and_zero_total():
+    g = batch_build(np.zeros((0, 3), np.float32), np.zeros(0, np.float32), [0, 0, 0, 0], 16)
+    assert g["n_cells"] == 0
+    assert np.all(g["cell_offsets"] == 0) and np.all(g["level_offset"] == 0)
+
+
+def test_duplicate_heavy_sets():
+    """Sets of coincident points (saturated depth-21 leaves) next to normal sets."""
+    rng = _rng(37)
+    parts, sizes = [], []
+    for b in range(12):
+        n = int(rng.integers(1, 3000))
+        if b % 3 == 0:
+            p = np.tile(rng.random((1, 3), dtype=np.float32), (n, 1))
+        else:
+            base = rng.random((max(n // 10, 1), 3), dtype=np.float32)
+            p = base[rng.integers(0, base.shape[0], n)]
+        parts.append(p)
+        sizes.append(n)
+    pos = np.concatenate(parts)
+    mass = (rng.random(pos.shape[0]) + 0.5).astype(np.float32)
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    g = batch_build(pos, mass, offsets, 8)
+    check_offsets(g, offsets)
+    check_against_oracle(pos, mass, offsets, 8, g, range(12))
+
+
+# --------------------------------------------------------------------------
+# errors found on the device
+# --------------------------------------------------------------------------
+
+def _raw_batched_sync(pos, mass, offsets, boxes, n_leaf=16):
+    p = torch.from_numpy(pos).cuda()
+    m = torch.from_numpy(mass).cuda()
+    off = torch.tensor(offsets, dtype=torch.int64, device="cuda")
+    B = len(offsets) - 1
+    bx = None if boxes is None else torch.tensor(boxes, dtype=torch.float64, device="cuda")
+    bb = tb.BatchBuilder(pos.shape[0], B, n_leaf)
+    rc = tb.tb_build_batched_sync(p.data_ptr(), m.data_ptr(), pos.shape[0], B, off.data_ptr(),
+                                  n_leaf, None if bx is None else bx.data_ptr(), bb.flags,
+                                  bb.workspace.data_ptr(), bb.ws_bytes, bb._struct,
+                                  bb.cell_offsets.data_ptr(), 0)
+    torch.cuda.synchronize()
+    return rc, bb
+
+
+def test_bad_offsets_reported():
+    rng = _rng(38)
+    pos = rng.random((5000, 3), dtype=np.float32)
+    mass = np.ones(5000, np.float32)
+    for offsets in ([0, 3000, 2000, 5000], [0, 100, 200, 4999], [5, 100, 200, 5000],
+                    [0, -7, 200, 5000]):
+        print(f"[bad offsets] {offsets}", flush=True)
+        rc, bb = _raw_batched_sync(pos, mass, offsets, None)
+        assert rc == tb.TB_ERR_ARG, offsets
+        # the build went on as one set holding every particle
+        assert int(bb.cell_offsets[-1].item()) == int(bb.out.n_cells.item()) > 0
+    rc, _ = _raw_batched_sync(pos, mass, [0, 2000, 2000, 5000], None)
+    assert rc == tb.TB_OK
+
+
+def test_bad_device_box_reported():
+    rng = _rng(39)
+    pos = rng.random((3000, 3), dtype=np.float32)
+    mass = np.ones(3000, np.float32)
+    good = [0.0, 0.0, 0.0, 1.0]
+    for bad in ([0.0, 0.0, 0.0, 3.0], [0.0, np.nan, 0.0, 1.0], [0.0, 0.0, 0.0, -2.0],
+                [0.0, 0.0, 0.0, np.inf], [0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 5e-324]):
+        print(f"[bad box] {bad}", flush=True)
+        rc, _ = _raw_batched_sync(pos, mass, [0, 1000, 3000], [good, bad])
+        assert rc == tb.TB_ERR_BOX, bad
+    rc, _ = _raw_batched_sync(pos, mass, [0, 1000, 3000], [good, [-2.0, -2.0, -2.0, 8.0]])
+    assert rc == tb.TB_OK
+
+
+# --------------------------------------------------------------------------
+# graph capture
+# --------------------------------------------------------------------------
+
+def test_graph_replay_matches_eager():
+    """The whole batch recorded once into a HIP graph and replayed: each replay
+    (with eager work and synchronisation between replays, and new particle data
+    in the same buffers) equals an eager build of the same data."""
+    sizes = uneven_sizes()
+    pos, mass, offsets = plummer_batch(sizes, seed=40)
+    N, B = pos.shape[0], len(sizes)
+    p = torch.from_numpy(pos).cuda()
+    m = torch.from_numpy(mass).cuda()
+    off = torch.from_numpy(offsets).cuda()
+    gb = tb.BatchBuilder(N, B, 16)
+    eb = tb.BatchBuilder(N, B, 16)
+    print("[graph] capture", flush=True)
+    gb.capture(p, m, off)
+    rng = _rng(40)
+    for rep in range(4):
+        if rep:
+            # new data in the captured buffers: jitter positions, change masses
+            p.copy_(torch.from_numpy((pos + rng.uniform(-1e-3, 1e-3, pos.shape)).clip(0, 0.999)
+                                     .astype(np.float32)).cuda())
+            m.copy_(torch.from_numpy((mass * rng.uniform(0.5, 2.0, N)).astype(np.float32)).cuda())
+        torch.cuda.synchronize()
+        print(f"[graph] replay {rep}", flush=True)
+        gb.replay()
+        gr = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in gb.result().items()}
+        eb.launch(p, m, off)
+        er = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in eb.result().items()}
+        for k in er:
+            assert np.array_equal(np.asarray(gr[k]), np.asarray(er[k])), (rep, k)
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+
+
+def test_single_build_graph_replay():
+    pos, mass = dg.plummer(50000, seed=41)
+    p = torch.from_numpy(pos).cuda()
+    m = torch.from_numpy(mass).cuda()
+    b = tb.Builder(50000, 16)
+    b.capture(p, m, ((0.0, 0.0, 0.0), 1.0))
+    o = oracle.build(pos, mass, 16)
+    for rep in range(3):
+        b.replay()
+        r = _to_np(b.result())
+        compare_structure(r, o)
+        errs = moment_errors(r["com"], r["quad"], o["com"], o["quad"], o["cell_level"])
+        assert max(errs) <= FP64_TOL, (rep, errs)
