@@ -4,11 +4,25 @@ and the achieved HBM bandwidth of the dominant kernel against the MI355X peak.
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|mixed]
 
 One step = one complete build (keys, sort, leaves, parents, moments) of a
-resident synthetic particle set.  Prints one JSON line.
+resident synthetic particle set; for the batched workload one step = one build
+of all 4,096 sets.  Prints one JSON line.
+
+Workloads
+  plummer16m    N = 2^24 Plummer, n_leaf 16, FP64 (default: the headline line)
+  uniform64k    N = 65,536 uniform, n_leaf 16 (latency-bound; parity size)
+  clustered64m  N = 2^26 clustered halos, n_leaf 8
+  mixed16m      N = 2^24 clustered, log-normal masses, n_leaf 8: the mixed-precision
+                path timed, beside the FP64 path on the same data, with the
+                per-moment error of mixed against FP64
+  batched4096   4,096 Plummer sets, sizes log-uniform in [256, 262144], n_leaf 16:
+                one graph-captured batch per step, beside eager batches and 4,096
+                sequential single-set builds; the sort shape comes from the autotuner
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import platform
@@ -28,9 +42,18 @@ WORKLOADS = {
     "uniform64k": "N=65,536 uniform in the unit cube, equal masses, n_leaf=16",
     "clustered64m": "N=2^26 clustered (70% in 2000 NFW halos, 30% uniform), periodic unit box, "
                     "n_leaf=8",
-    "mixed16m": "N=2^24 clustered set with log-normal masses, n_leaf=8",
+    "mixed16m": "N=2^24 clustered set (2000 NFW halos + 30% uniform) with log-normal masses, "
+                "n_leaf=8, mixed-precision moments vs FP64",
+    "batched4096": "4096 independent Plummer sets, sizes floor(exp(U(ln 256, ln 262144))), each in "
+                   "its own unit cube, masses 1/n_b, n_leaf=16, one graph-captured batch",
 }
 
+# profiles/pmc_<workload>.json holds per-launch HBM counter bytes measured with
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by a copy-kernel calibration,
+# together with a hash of the kernel sources they were taken on.
+PROFILES = os.path.join(ROOT, "profiles")
+SOURCES = sorted(glob.glob(os.path.join(ROOT, "paper_2312_06102_amd", "csrc", "*"))) + \
+    [os.path.join(ROOT, "include", "treebuild.h")]
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -38,9 +61,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer16m", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--sort-config", type=int, default=0)
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: mixed for mixed16m, fp64 otherwise")
+    ap.add_argument("--sort-config", type=int, default=None,
+                    help="sort shape index (default: 0; the autotuner's choice for batched4096)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched4096: skip the 4096 sequential single-set builds")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="mixed16m: skip the FP64 build on the same data")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22,
                     help="particles of the workload the oracle builds for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -62,26 +91,323 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_launch": 1 << 28, "launches": 5}))
 
 
-def algorithmic_bytes(n: int, cells: int, leaves: int, passes: int, precision: str) -> dict:
-    """Bytes each stage must move (reads + writes), not counter traffic.
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in SOURCES:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
-    keygen      read pos 12 + write key 8 per particle
-    sort_pass   read key 8 (+ payload 4 after the first pass) + write key 8 + payload 4
-    cell_count  read sorted key 8
-    cell_emit   read sorted key 8 + perm 4 + gathered pos/mass 16 per particle; write
-                key 8 + depth 1 + first 4 + child 8 per cell and count 4 + moments per leaf
-    parents     per internal cell: read its children's key 8 + count 4 + moments,
-                write its own count 4 + child count 4 + moments
+
+def counter_traffic(workload: str) -> dict | None:
+    """Per-launch HBM bytes by kernel from the committed counter profile, or None
+    when there is none or the kernels changed since it was taken."""
+    path = os.path.join(PROFILES, f"pmc_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    if prof.get("source_sha256") != source_hash():
+        return None
+    return prof
+
+
+def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: int,
+                 precision: str) -> dict:
+    """Bytes each traced stage must read + write for what it computes (its
+    compulsory traffic), per build.
+
+    keygen      read pos 12 + mass 4; write key 8 + packed (x, y, z, m) record 16
+    sort_pass   pass 0 reads keys 8 (the payload is generated), later passes key 8 +
+                payload 4; every pass writes key 8 + payload 4
+    set_pass    as a later key pass
+    cell_count  read sorted keys 8
+    reorder     read perm 4 + gathered record 16; write the record in key order 16
+    cell_emit   read sorted keys 8 + sorted records 16 per particle; write key 8, depth 1,
+                first 4, child link 8, head_parent 4 per cell, count 4 + moments per leaf
+    parents     per child cell read key 8 + count 4 + moments; per parent read head 4,
+                write count 4 + child count 4 + moments
+    moments: FP64 80 B (com 32 + quad 48); mixed 44 B (com 16 + quad 24 + mass term 4)
     """
-    mom = 80 if precision == "fp64" else 40
+    mom = 80 if precision == "fp64" else 44
     inner = cells - leaves
     return {
-        "keygen": 20 * n,
-        "sort_pass": (20 + 24 * (passes - 1)) * n,
+        "keygen": 40 * n,
+        "sort_pass": (20 + 24 * (key_passes - 1)) * n,
+        "set_pass": 24 * n * set_passes,
         "cell_count": 8 * n,
-        "cell_emit": 28 * n + 21 * cells + (4 + mom) * leaves,
-        "parents": (12 + mom) * max(cells - 1, 0) + (8 + mom) * inner,
+        "reorder": 36 * n,
+        "cell_emit": 24 * n + 25 * cells + (4 + mom) * leaves,
+        "parents": (12 + mom) * max(cells - 1, 0) + (12 + mom) * inner,
     }
+
+
+def method_bytes(n: int, cells: int, key_passes: int, precision: str) -> float:
+    """What the method must move per build (the whole-build algorithmic bytes):
+    keys 20 B, sort 8 + 24 P, gather 20, structure 8 + 25 c, moments 2 x 80 c
+    (FP64) or 2 x 40 c (mixed) per particle, with c = cells / N."""
+    c = cells / max(n, 1)
+    mom = 160 if precision == "fp64" else 80
+    return n * (56 + 24 * key_passes + (25 + mom) * c)
+
+
+def traced_kernels(run, steps, tb):
+    """Per-stage durations from HIP events recorded on the build stream."""
+    import torch
+    tb.tb_trace_enable(True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    trace = tb.tb_trace_read()
+    tb.tb_trace_enable(False)
+    return trace
+
+
+def kernels_table(trace, steps, alg):
+    out = {}
+    for name, (launches, total_ms) in sorted(trace.items()):
+        per_build_ms = total_ms / steps
+        k = {"ms_per_build": round(per_build_ms, 4), "launches_per_build": launches // steps,
+             "avg_launch_ms": round(total_ms / max(launches, 1), 5)}
+        if alg.get(name):
+            k["alg_bytes_per_build"] = alg[name]
+            k["alg_GBps"] = round(alg[name] / (per_build_ms * 1e-3) / 1e9, 1)
+        out[name] = k
+    return out
+
+
+def roofline(trace, alg, key_passes, workload):
+    """Roofline entry of the dominant kernel (the sort's key passes)."""
+    launches, total_ms = trace["sort_pass"]
+    avg_ms = total_ms / launches
+    per_launch = alg["sort_pass"] / key_passes
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    r = {"kernel": "k_onesweep (radix scatter pass over the key bits, one launch per digit)",
+         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+         "alg_bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 5)}
+    prof = counter_traffic(workload)
+    if prof is not None:
+        k = prof["kernels"].get("sort_pass")
+        if k:
+            r["traffic"] = k["bytes_per_launch"]
+            r["traffic_source"] = prof["file"]
+    return r
+
+
+def counter_summary(workload, ms_per_step):
+    prof = counter_traffic(workload)
+    if prof is None:
+        return None
+    tot = sum(k["bytes_per_launch"] * k["launches_per_build"] for k in prof["kernels"].values())
+    return {"bytes_per_build": tot, "GBps": round(tot / (ms_per_step * 1e-3) / 1e9, 1),
+            "frac": round(tot / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "source": prof["file"]}
+
+
+def time_steps(run, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def moment_error_vs(res, ref, side=1.0):
+    """Max per-cell relative errors of res against ref (same tree): |dM|/M,
+    max|d com|/l, max|dQ|/(M l^2), l the cell side."""
+    import torch
+    lvl = ref["cell_level"].to(torch.float64)
+    l = side * torch.pow(2.0, -lvl)
+    M = ref["com"][:, 3].to(torch.float64)
+    gc, gq = res["com"].to(torch.float64), res["quad"].to(torch.float64)
+    rc, rq = ref["com"].to(torch.float64), ref["quad"].to(torch.float64)
+    e_m = ((gc[:, 3] - M).abs() / M).max().item()
+    e_c = ((gc[:, :3] - rc[:, :3]).abs().amax(1) / l).max().item()
+    e_q = ((gq - rq).abs().amax(1) / (M * l * l)).max().item()
+    return {"M": e_m, "com": e_c, "quad": e_q}
+
+
+def run_single(args, tb, dg, torch, np):
+    t_gen = time.time()
+    pos_np, mass_np, n_leaf = dg.workload(args.workload)
+    n = pos_np.shape[0]
+    print(f"[bench] generated {args.workload} N={n} in {time.time() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    precision = args.precision or ("mixed" if args.workload == "mixed16m" else "fp64")
+    k = args.sort_config or 0
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(pos_np).to(dev)
+    mass = torch.from_numpy(mass_np).to(dev)
+    box = ((0.0, 0.0, 0.0), 1.0)
+    b = tb.Builder(n, n_leaf, precision, k, dev)
+    run = lambda: b.launch(pos, mass, box)
+    sec = time_steps(run, args.steps, args.warmup)
+    print(f"[bench] {args.steps} builds, {sec * 1e3:.3f} ms/build", file=sys.stderr, flush=True)
+    res = b.result()
+    cells = res["n_cells"]
+    leaves = int((res["child_ptr"][:, 0] < 0).sum().item())
+    key_passes = (63 + tb.tb_sort_configs()[k][0] - 1) // tb.tb_sort_configs()[k][0]
+    trace = traced_kernels(run, args.steps, tb)
+    alg = kernel_bytes(n, cells, leaves, key_passes, 0, precision)
+    total_method = method_bytes(n, cells, key_passes, precision)
+    line = {
+        "metric": METRIC, "value": n / sec, "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 keys + f64 moments" if precision == "fp64" else "u64 keys + f32 moments",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "N": n,
+                   "n_leaf": n_leaf, "precision": precision, "box": "unit cube",
+                   "sort_config": list(tb.tb_sort_configs()[k]), "cells": cells,
+                   "leaves": leaves},
+        "roofline": roofline(trace, alg, key_passes, args.workload),
+        "build_method_bytes": total_method,
+        "build_alg_GBps": round(total_method / sec / 1e9, 1),
+        "build_alg_frac": round(total_method / sec / 1e9 / HBM_PEAK_GBPS, 4),
+        "build_counter_traffic": counter_summary(args.workload, sec * 1e3),
+        "traced_ms_per_build": round(sum(v[1] for v in trace.values()) / args.steps, 4),
+        "kernels": kernels_table(trace, args.steps, alg),
+    }
+    if args.workload == "mixed16m" and not args.no_compare:
+        # the FP64 path on the same data and the mixed path's error against it
+        # (the FP64 path matches the FP64 oracle to 1e-12 in the parity tests)
+        ref_b = tb.Builder(n, n_leaf, "fp64", k, dev)
+        ref_run = lambda: ref_b.launch(pos, mass, box)
+        sec64 = time_steps(ref_run, args.steps, args.warmup)
+        ref = ref_b.result()
+        same = all(torch.equal(res[f], ref[f]) for f in
+                   ("perm", "cell_key", "cell_level", "cell_first", "cell_count", "child_ptr"))
+        line["fp64_comparison"] = {
+            "fp64_ms_per_step": sec64 * 1e3, "fp64_particles_per_s": n / sec64,
+            "mixed_speedup": sec64 / sec, "tree_identical": bool(same),
+            "max_rel_error_vs_fp64": moment_error_vs(res, ref),
+            "error_measures": "per cell: |dM|/M, max|d com|/l, max|dQ|/(M l^2), l = cell side; "
+                              "max over all cells"}
+    return line, (pos_np, mass_np, n_leaf, None)
+
+
+def run_batched(args, tb, dg, torch, np):
+    from paper_2312_06102_amd import autotune
+    t_gen = time.time()
+    sizes = dg.batched_sizes(4096, 256, 262144, seed=4)
+    pos_np, mass_np, offsets_np = dg.batched_plummer(sizes, seed=4)
+    n, B, n_leaf = pos_np.shape[0], len(sizes), 16
+    print(f"[bench] generated batched4096 N={n} in {time.time() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    precision = args.precision or "fp64"
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(pos_np).to(dev)
+    mass = torch.from_numpy(mass_np).to(dev)
+    off = torch.from_numpy(offsets_np).to(dev)
+    boxes = torch.tensor([[0.0, 0.0, 0.0, 1.0]] * B, dtype=torch.float64, device=dev)
+    # sort shape: the autotuner's choice on this batch (timed outside the steps)
+    t_tune = time.time()
+    if args.sort_config is None:
+        k = autotune.tune(pos, mass, n_leaf, precision, set_offsets=off, boxes=boxes,
+                          use_cache=False, verbose=True)
+    else:
+        k = args.sort_config
+    tune_s = time.time() - t_tune
+    bb = tb.BatchBuilder(n, B, n_leaf, precision, k, dev)
+    bb.capture(pos, mass, off, boxes)
+    sec = time_steps(bb.replay, args.steps, args.warmup)
+    print(f"[bench] {args.steps} graph replays, {sec * 1e3:.3f} ms/batch", file=sys.stderr,
+          flush=True)
+    res = bb.result()
+    cells = res["n_cells"]
+    leaves = int((res["child_ptr"][:, 0] < 0).sum().item())
+    eager = lambda: bb.launch(pos, mass, off, boxes)
+    sec_eager = time_steps(eager, args.steps, 1)
+    trace = traced_kernels(eager, args.steps, tb)
+    bits = tb.tb_sort_configs()[k][0]
+    key_passes = (63 + bits - 1) // bits
+    set_passes = 0
+    span = 1
+    while span < B:
+        span <<= bits
+        set_passes += 1
+    alg = kernel_bytes(n, cells, leaves, key_passes, set_passes, precision)
+    total_method = method_bytes(n, cells, key_passes, precision)
+    line = {
+        "metric": METRIC, "value": n / sec, "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 keys + f64 moments" if precision == "fp64" else "u64 keys + f32 moments",
+        "data": "synthetic",
+        "config": {"workload": "batched4096", "description": WORKLOADS["batched4096"], "N": n,
+                   "sets": B, "set_size_min": int(sizes.min()), "set_size_max": int(sizes.max()),
+                   "n_leaf": n_leaf, "precision": precision, "box": "unit cube per set",
+                   "sort_config": list(tb.tb_sort_configs()[k]), "autotune_s": round(tune_s, 2),
+                   "cells": cells, "leaves": leaves, "launch": "one HIP graph per batch"},
+        "roofline": roofline(trace, alg, key_passes, "batched4096"),
+        "build_method_bytes": total_method,
+        "build_alg_GBps": round(total_method / sec / 1e9, 1),
+        "build_alg_frac": round(total_method / sec / 1e9 / HBM_PEAK_GBPS, 4),
+        "build_counter_traffic": counter_summary("batched4096", sec * 1e3),
+        "eager_batch_ms": sec_eager * 1e3,
+        "traced_ms_per_build": round(sum(v[1] for v in trace.values()) / args.steps, 4),
+        "kernels": kernels_table(trace, args.steps, alg),
+    }
+    del bb
+    torch.cuda.empty_cache()
+    if not args.no_sequential:
+        # the same sets as 4096 sequential single-set builds on one stream, one
+        # workspace and one set of outputs sized for the largest set
+        nmax = int(sizes.max())
+        ws_bytes = tb.tb_workspace_bytes(nmax, n_leaf, tb.TB_FP64 if precision == "fp64" else tb.TB_MIXED)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        outb = tb.TreeBuffers.allocate(nmax, n_leaf, precision, dev)
+        st = outb.struct()
+        flags = tb.TB_FP64 if precision == "fp64" else tb.TB_MIXED
+        box = tb._box_struct(((0.0, 0.0, 0.0), 1.0))
+        stream = torch.cuda.current_stream().cuda_stream
+        pp, mp = pos.data_ptr(), mass.data_ptr()
+
+        def sequential():
+            for bi in range(B):
+                s0, s1 = int(offsets_np[bi]), int(offsets_np[bi + 1])
+                rc = tb.tb_build(pp + 12 * s0, mp + 4 * s0, s1 - s0, n_leaf, box, flags,
+                                 ws.data_ptr(), ws_bytes, st, stream)
+                if rc:
+                    raise RuntimeError(f"tb_build failed: {rc}")
+        seq_steps = max(1, min(3, args.steps))
+        sec_seq = time_steps(sequential, seq_steps, 1)
+        line["sequential"] = {"ms_per_batch": sec_seq * 1e3, "particles_per_s": n / sec_seq,
+                              "steps": seq_steps, "graph_speedup": sec_seq / sec,
+                              "what": "4096 tb_build calls on one stream, sort config 0"}
+    return line, (pos_np, mass_np, n_leaf, offsets_np)
+
+
+def cpu_baseline(args, data, np):
+    import oracle
+    pos_np, mass_np, n_leaf, offsets = data
+    oracle.load()
+    if offsets is None:
+        m = min(args.cpu_sample, pos_np.shape[0])
+        tc0 = time.perf_counter()
+        oracle.build(np.ascontiguousarray(pos_np[:m]), np.ascontiguousarray(mass_np[:m]), n_leaf)
+        tc1 = time.perf_counter()
+        what = f"first {m} particles of the same workload"
+    else:
+        # whole sets from the start of the batch, about cpu_sample particles
+        nb = int(np.searchsorted(offsets, args.cpu_sample)) or 1
+        m = int(offsets[nb])
+        tc0 = time.perf_counter()
+        for b in range(nb):
+            s0, s1 = int(offsets[b]), int(offsets[b + 1])
+            oracle.build(pos_np[s0:s1], mass_np[s0:s1], n_leaf)
+        tc1 = time.perf_counter()
+        what = f"first {nb} sets ({m} particles) of the same batch, one oracle build per set"
+    return {"value": m / (tc1 - tc0), "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what}, full oracle build (keys, top-down insertion, perm, canonical "
+                      f"order, direct FP64 moments), {tc1 - tc0:.2f} s on "
+                      f"{platform.processor() or platform.machine()} (host nproc={os.cpu_count()})"}
 
 
 def main():
@@ -100,103 +426,12 @@ def main():
     from paper_2312_06102_amd import datagen as dg
     from paper_2312_06102_amd import treebuild as tb
 
-    t_gen = time.time()
-    pos_np, mass_np, n_leaf = dg.workload(args.workload)
-    n = pos_np.shape[0]
-    print(f"[bench] generated {args.workload} N={n} in {time.time() - t_gen:.1f}s", file=sys.stderr,
-          flush=True)
-    dev = torch.device("cuda:0")
-    pos = torch.from_numpy(pos_np).to(dev)
-    mass = torch.from_numpy(mass_np).to(dev)
-    box = ((0.0, 0.0, 0.0), 1.0)
-    b = tb.Builder(n, n_leaf, args.precision, args.sort_config, dev)
-    passes = (63 + tb.tb_sort_configs()[args.sort_config][0] - 1) // tb.tb_sort_configs()[args.sort_config][0]
-
-    for _ in range(args.warmup):
-        b.launch(pos, mass, box)
-    res = b.result()
-    cells = res["n_cells"]
-    leaves = int((res["child_ptr"][:, 0] < 0).sum().item())
-
-    # timed region: K complete builds
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.launch(pos, mass, box)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = (t1 - t0) / args.steps
-    print(f"[bench] {args.steps} builds, {sec * 1e3:.3f} ms/build", file=sys.stderr, flush=True)
-
-    # per-kernel durations from HIP events recorded on the build stream
-    tb.tb_trace_enable(True)
-    for _ in range(args.steps):
-        b.launch(pos, mass, box)
-    torch.cuda.synchronize()
-    trace = tb.tb_trace_read()
-    tb.tb_trace_enable(False)
-
-    alg = algorithmic_bytes(n, cells, leaves, passes, args.precision)
-    kernels = {}
-    for name, (launches, total_ms) in sorted(trace.items()):
-        per_build_ms = total_ms / args.steps
-        k = {"ms_per_build": round(per_build_ms, 4), "launches_per_build": launches // args.steps,
-             "avg_launch_ms": round(total_ms / max(launches, 1), 5)}
-        if name in alg:
-            k["alg_bytes_per_build"] = alg[name]
-            k["alg_GBps"] = round(alg[name] / (per_build_ms * 1e-3) / 1e9, 1)
-        kernels[name] = k
-    sp = trace["sort_pass"]
-    sort_avg_ms = sp[1] / sp[0]
-    sort_bytes_per_launch = alg["sort_pass"] / passes
-    achieved = sort_bytes_per_launch / (sort_avg_ms * 1e-3) / 1e9
-    total_alg = sum(alg.values())
-    traced_ms = sum(v[1] for v in trace.values()) / args.steps
-
-    line = {
-        "metric": METRIC,
-        "value": n / sec,
-        "unit": "particles/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64 keys + f64 moments" if args.precision == "fp64" else "u64 keys + f32 moments",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "N": n,
-                   "n_leaf": n_leaf, "precision": args.precision, "box": "unit cube",
-                   "sort_config": list(tb.tb_sort_configs()[args.sort_config]),
-                   "cells": cells, "leaves": leaves},
-        "roofline": {"kernel": "sort_pass (radix scatter pass, one launch per digit)",
-                     "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None,
-                     "alg_bytes_per_launch": sort_bytes_per_launch,
-                     "avg_launch_ms": round(sort_avg_ms, 5)},
-        "build_alg_GBps": round(total_alg / sec / 1e9, 1),
-        "build_alg_frac": round(total_alg / sec / 1e9 / HBM_PEAK_GBPS, 4),
-        "traced_ms_per_build": round(traced_ms, 4),
-        "kernels": kernels,
-    }
-
+    if args.workload == "batched4096":
+        line, data = run_batched(args, tb, dg, torch, np)
+    else:
+        line, data = run_single(args, tb, dg, torch, np)
     if not args.no_cpu_baseline:
-        import oracle
-        m = min(args.cpu_sample, n)
-        sub_p = np.ascontiguousarray(pos_np[:m])
-        sub_m = np.ascontiguousarray(mass_np[:m])
-        oracle.load()
-        tc0 = time.perf_counter()
-        oracle.build(sub_p, sub_m, n_leaf)
-        tc1 = time.perf_counter()
-        line["cpu_baseline"] = {
-            "value": m / (tc1 - tc0), "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} particles of the same workload, full oracle build "
-                      f"(keys, top-down insertion, perm, canonical order, direct FP64 moments), "
-                      f"{tc1 - tc0:.2f} s on {platform.processor() or platform.machine()} "
-                      f"(host nproc={os.cpu_count()})"}
+        line["cpu_baseline"] = cpu_baseline(args, data, np)
     print(json.dumps(line))
 
 

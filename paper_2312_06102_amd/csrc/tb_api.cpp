@@ -225,7 +225,7 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
     if (e == hipSuccess) e = traced(name, s, f);
   };
   run("init", [&] { return launch_init(p, w, in, *out, s); });
-  run("setup", [&] { return launch_setup(p, w, in.auto_box, in.dev_boxes != nullptr, out->status, s); });
+  run("setup", [&] { return launch_setup(p, w, in, out->status, s); });
   if (in.auto_box) run("bbox", [&] { return launch_bbox(p, w, pos, s); });
   run("keygen", [&] { return launch_keygen(p, w, pos, mass, *out, s); });
   run("hist_reduce", [&] { return launch_hist_reduce(p, w, s); });

@@ -268,15 +268,16 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_count(
 
 // Exclusive prefix of the per-tile counts over the earlier tiles of the same
 // set, one workgroup per (depth, set); the set's total per depth goes to
-// set_tot[b][d].
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 4;
+// set_tot[b][d].  A single set uses 1024-thread workgroups (8192 tiles, i.e.
+// 2^24 particles, per round), batches 256-thread ones (their sets are small).
+constexpr int kScanItems = 8;
 
-__global__ __launch_bounds__(kScanThreads) void k_cell_scan(
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_cell_scan(
     const uint32_t *__restrict__ tile_cnt, int64_t cell_tiles,
     const int64_t *__restrict__ tile_start, int32_t nsets, uint32_t *__restrict__ excl,
     uint32_t *__restrict__ set_tot) {
-  __shared__ uint32_t s_w[kScanThreads / 64];
+  __shared__ uint32_t s_w[THREADS / 64];
   const int d = blockIdx.x;
   const uint32_t *row = tile_cnt + d * cell_tiles;
   uint32_t *out = excl + d * cell_tiles;
@@ -284,20 +285,19 @@ __global__ __launch_bounds__(kScanThreads) void k_cell_scan(
   for (int b = blockIdx.y; b < nsets; b += gridDim.y) {
     const int64_t ts = tile_start[b], te = tile_start[b + 1];
     uint32_t carry = 0;
-    for (int64_t c0 = ts; c0 < te; c0 += (int64_t)kScanThreads * kScanItems) {
+    for (int64_t c0 = ts; c0 < te; c0 += (int64_t)THREADS * kScanItems) {
       const int64_t q = c0 + (int64_t)threadIdx.x * kScanItems;
       uint32_t v[kScanItems], sum = 0;
 #pragma unroll
-      for (int r = 0; r < kScanItems; ++r) {
-        v[r] = (q + r < te) ? row[q + r] : 0u;
-        sum += v[r];
-      }
+      for (int r = 0; r < kScanItems; ++r) v[r] = (q + r < te) ? row[q + r] : 0u;
+#pragma unroll
+      for (int r = 0; r < kScanItems; ++r) sum += v[r];
       const uint32_t inc = wave_inclusive_scan(sum);
       if (lane_id() == 63) s_w[wv] = inc;
       __syncthreads();
       uint32_t off = 0, tot = 0;
 #pragma unroll
-      for (int k = 0; k < kScanThreads / 64; ++k) {
+      for (int k = 0; k < THREADS / 64; ++k) {
         const uint32_t t = s_w[k];
         off += (k < wv) ? t : 0u;
         tot += t;
@@ -315,10 +315,12 @@ __global__ __launch_bounds__(kScanThreads) void k_cell_scan(
   }
 }
 
-// One workgroup over all sets: the first cell of every set and of every depth
-// of every set, the outputs level_offset [B][23], cell_offsets [B+1] and
-// n_cells, the parent-pass chunk tables, and the boxes used.
+// One workgroup over all sets, 1024 sets per round and every row of a round at
+// once: the first cell of every set and of every depth of every set, the
+// outputs level_offset [B][23], cell_offsets [B+1] and n_cells, the
+// parent-pass chunk tables, and the boxes used.
 constexpr int kSetScanThreads = 1024;
+constexpr int kSetScanWaves = kSetScanThreads / 64;
 
 __global__ __launch_bounds__(kSetScanThreads) void k_set_scan(
     const uint32_t *__restrict__ set_tot, int32_t nsets, int64_t *__restrict__ set_cells,
@@ -326,64 +328,72 @@ __global__ __launch_bounds__(kSetScanThreads) void k_set_scan(
     int64_t *__restrict__ cell_offsets, int64_t *__restrict__ n_cells,
     int64_t *__restrict__ par_start, const double *__restrict__ box,
     double *__restrict__ box_out) {
-  __shared__ uint32_t s_w[kSetScanThreads / 64];
-  __shared__ int64_t s_carry;
+  // rows: 0 = cells per set, r = 1..21 = parent chunks at depth r - 1 (children at depth r)
+  __shared__ uint32_t s_w[kLevels][kSetScanWaves];
+  __shared__ int64_t s_carry[kLevels];
   const int wv = threadIdx.x / 64;
-  // rows: 0 = cells per set, 1 + d = parent chunks at depth d (children at d + 1)
-  for (int row = 0; row < kLevels; ++row) {
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (int r0 = 0; r0 < nsets; r0 += kSetScanThreads) {
-      const int b = r0 + threadIdx.x;
-      uint32_t v = 0;
-      if (b < nsets) {
-        if (row == 0) {
-          for (int d = 0; d < kLevels; ++d) v += set_tot[b * kLevels + d];
-        } else {
-          v = (set_tot[b * kLevels + row] + kParentChunk - 1) / kParentChunk;
-        }
-      }
-      const uint32_t inc = wave_inclusive_scan(v);
-      if (lane_id() == 63) s_w[wv] = inc;
-      __syncthreads();
-      int64_t off = s_carry, tot = 0;
-      for (int q = 0; q < kSetScanThreads / 64; ++q) {
-        off += (q < wv) ? s_w[q] : 0u;
-        tot += s_w[q];
-      }
-      off += inc - v;
-      if (b < nsets) {
-        if (row == 0) {
-          set_cells[b] = off;
-          if (cell_offsets) cell_offsets[b] = off;
-          int64_t run = off;
-          for (int d = 0; d < kLevels; ++d) {
-            lvl_off[b * (kLevels + 1) + d] = run;
-            level_offset[b * (kLevels + 1) + d] = run;
-            run += set_tot[b * kLevels + d];
-          }
-          lvl_off[b * (kLevels + 1) + kLevels] = run;
-          level_offset[b * (kLevels + 1) + kLevels] = run;
-          if (box_out)
-            for (int k = 0; k < 4; ++k) box_out[4 * b + k] = box[4 * b + k];
-        } else {
-          par_start[(row - 1) * (nsets + 1) + b] = off;
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) s_carry += tot;
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      if (row == 0) {
-        set_cells[nsets] = s_carry;
-        if (cell_offsets) cell_offsets[nsets] = s_carry;
-        *n_cells = s_carry;
-      } else {
-        par_start[(row - 1) * (nsets + 1) + nsets] = s_carry;
-      }
+  if (threadIdx.x < kLevels) s_carry[threadIdx.x] = 0;
+  __syncthreads();
+  for (int r0 = 0; r0 < nsets; r0 += kSetScanThreads) {
+    const int b = r0 + threadIdx.x;
+    uint32_t t[kLevels];
+#pragma unroll
+    for (int d = 0; d < kLevels; ++d) t[d] = (b < nsets) ? set_tot[b * kLevels + d] : 0u;
+    uint32_t v[kLevels], inc[kLevels];
+    v[0] = 0;
+#pragma unroll
+    for (int d = 0; d < kLevels; ++d) v[0] += t[d];
+#pragma unroll
+    for (int r = 1; r < kLevels; ++r) v[r] = (t[r] + kParentChunk - 1) / kParentChunk;
+#pragma unroll
+    for (int r = 0; r < kLevels; ++r) inc[r] = wave_inclusive_scan(v[r]);
+    if (lane_id() == 63) {
+#pragma unroll
+      for (int r = 0; r < kLevels; ++r) s_w[r][wv] = inc[r];
     }
     __syncthreads();
+    int64_t off[kLevels];
+#pragma unroll
+    for (int r = 0; r < kLevels; ++r) {
+      int64_t o = s_carry[r];
+      for (int q = 0; q < wv; ++q) o += s_w[r][q];
+      off[r] = o + (int64_t)(inc[r] - v[r]);
+    }
+    if (b < nsets) {
+      set_cells[b] = off[0];
+      if (cell_offsets) cell_offsets[b] = off[0];
+      int64_t run = off[0];
+#pragma unroll
+      for (int d = 0; d < kLevels; ++d) {
+        lvl_off[b * (kLevels + 1) + d] = run;
+        level_offset[b * (kLevels + 1) + d] = run;
+        run += t[d];
+      }
+      lvl_off[b * (kLevels + 1) + kLevels] = run;
+      level_offset[b * (kLevels + 1) + kLevels] = run;
+      if (box_out)
+        for (int k = 0; k < 4; ++k) box_out[4 * b + k] = box[4 * b + k];
+#pragma unroll
+      for (int r = 1; r < kLevels; ++r) par_start[(r - 1) * (nsets + 1) + b] = off[r];
+    }
+    __syncthreads();
+    if (threadIdx.x < kLevels) {
+      int64_t tot = 0;
+      for (int q = 0; q < kSetScanWaves; ++q) tot += s_w[threadIdx.x][q];
+      s_carry[threadIdx.x] += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kLevels) {
+    const int r = threadIdx.x;
+    const int64_t total = s_carry[r];
+    if (r == 0) {
+      set_cells[nsets] = total;
+      if (cell_offsets) cell_offsets[nsets] = total;
+      *n_cells = total;
+    } else {
+      par_start[(r - 1) * (nsets + 1) + nsets] = total;
+    }
   }
 }
 
@@ -749,8 +759,12 @@ hipError_t launch_cell_count(const Plan &p, const Work &w, hipStream_t s) {
 hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
                             int64_t *cell_offsets, hipStream_t s) {
   const int gy = p.nsets < 65535 ? p.nsets : 65535;
-  k_cell_scan<<<dim3(kLevels, gy), kScanThreads, 0, s>>>(w.cell_cnt, p.cell_tiles, w.tile_start,
-                                                         p.nsets, w.cell_excl, w.set_tot);
+  if (p.nsets == 1)
+    k_cell_scan<1024><<<dim3(kLevels, 1), 1024, 0, s>>>(w.cell_cnt, p.cell_tiles, w.tile_start,
+                                                       p.nsets, w.cell_excl, w.set_tot);
+  else
+    k_cell_scan<256><<<dim3(kLevels, gy), 256, 0, s>>>(w.cell_cnt, p.cell_tiles, w.tile_start,
+                                                      p.nsets, w.cell_excl, w.set_tot);
   k_set_scan<<<1, kSetScanThreads, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
                                            out.level_offset, cell_offsets, out.n_cells,
                                            w.par_start, w.box, out.box_out);

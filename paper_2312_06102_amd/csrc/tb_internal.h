@@ -140,8 +140,8 @@ struct BatchIn {
 // tb_keys.hip
 hipError_t launch_init(const Plan &p, const Work &w, const BatchIn &in, const tb_tree &out,
                        hipStream_t s);
-hipError_t launch_setup(const Plan &p, const Work &w, bool with_chunks, bool check_boxes,
-                        int32_t *status, hipStream_t s);
+hipError_t launch_setup(const Plan &p, const Work &w, const BatchIn &in, int32_t *status,
+                        hipStream_t s);
 hipError_t launch_bbox(const Plan &p, const Work &w, const float *pos, hipStream_t s);
 hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const float *mass,
                          const tb_tree &out, hipStream_t s);

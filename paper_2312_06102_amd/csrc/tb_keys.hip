@@ -33,10 +33,29 @@ __global__ __launch_bounds__(kInitThreads) void k_init(
     int32_t *__restrict__ status_word, int64_t n, int32_t nsets,
     const int64_t *__restrict__ set_off_in, int64_t *__restrict__ set_off,
     const tb_box *__restrict__ boxes_in, double *__restrict__ box, int host_box, double lo0,
-    double lo1, double lo2, double side) {
+    double lo1, double lo2, double side, int single, int with_chunks,
+    int64_t *__restrict__ tile_start,
+    int32_t *__restrict__ tile_set, int64_t *__restrict__ chunk_start,
+    int32_t *__restrict__ chunk_set) {
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < n_status0; i += stride) status0[i] = 0;
+  if (single) {
+    // one set given by the host: its tables need no validation or scan (the
+    // chunk table exists only when the box comes from the data)
+    const int64_t nt = (n + kCellTile - 1) / kCellTile;
+    const int64_t nc = with_chunks ? (n + kBboxChunk - 1) / kBboxChunk : 0;
+    for (int64_t t = tid; t < nt; t += stride) tile_set[t] = 0;
+    for (int64_t c = tid; c < nc; c += stride) chunk_set[c] = 0;
+    if (tid == 0) {
+      tile_start[0] = 0;
+      tile_start[1] = nt;
+      if (with_chunks) {
+        chunk_start[0] = 0;
+        chunk_start[1] = nc;
+      }
+    }
+  }
   if (tid < 64) counters[tid] = 0;
   for (int64_t b = tid; b <= nsets; b += stride)
     set_off[b] = set_off_in ? set_off_in[b] : (b == 0 ? 0 : n);
@@ -59,6 +78,12 @@ __global__ __launch_bounds__(kInitThreads) void k_init(
   }
 }
 
+// A single set described by the host (tb_build): k_init writes its tables and
+// k_setup is skipped.
+static bool single_set(const Plan &p, const BatchIn &in) {
+  return p.nsets == 1 && !in.set_off && !in.dev_boxes;
+}
+
 hipError_t launch_init(const Plan &p, const Work &w, const BatchIn &in, const tb_tree &out,
                        hipStream_t s) {
   const int64_t n0 = p.sort_tiles * (int64_t)p.sort.radix();
@@ -70,7 +95,10 @@ hipError_t launch_init(const Plan &p, const Work &w, const BatchIn &in, const tb
   k_init<<<blocks, kInitThreads, 0, s>>>(w.status0, n0, w.counters, out.status, p.n, p.nsets,
                                          in.set_off, w.set_off, in.dev_boxes, w.box, hb ? 1 : 0,
                                          hb ? hb->lo[0] : 0.0, hb ? hb->lo[1] : 0.0,
-                                         hb ? hb->lo[2] : 0.0, hb ? hb->side : 1.0);
+                                         hb ? hb->lo[2] : 0.0, hb ? hb->side : 1.0,
+                                         single_set(p, in) ? 1 : 0, in.auto_box ? 1 : 0,
+                                         w.tile_start, w.tile_set,
+                                         w.chunk_start, w.chunk_set);
   return hipGetLastError();
 }
 
@@ -87,8 +115,7 @@ __device__ __forceinline__ bool box_valid(const double *b) {
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(
     int64_t *__restrict__ set_off, int32_t nsets, int64_t n, int64_t *__restrict__ tile_start,
-    int32_t *__restrict__ tile_set, int64_t *__restrict__ chunk_start,
-    int32_t *__restrict__ chunk_set, uint32_t *__restrict__ set_hist, int set_passes, int bits,
+    int64_t *__restrict__ chunk_start, uint32_t *__restrict__ set_hist, int set_passes, int bits,
     int with_chunks, double *__restrict__ box, int check_boxes,
     int32_t *__restrict__ status_word) {
   __shared__ uint32_t s_w[2][kSetupThreads / 64];
@@ -157,11 +184,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(
     oc += ic - nc;
     if (b < nsets) {
       tile_start[b] = (int64_t)ot;
-      for (uint32_t k = 0; k < nt; ++k) tile_set[ot + k] = b;
-      if (with_chunks) {
-        chunk_start[b] = (int64_t)oc;
-        for (uint32_t k = 0; k < nc; ++k) chunk_set[oc + k] = b;
-      }
+      if (with_chunks) chunk_start[b] = (int64_t)oc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -176,13 +199,37 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(
   }
 }
 
-hipError_t launch_setup(const Plan &p, const Work &w, bool with_chunks, bool check_boxes,
-                        int32_t *status, hipStream_t s) {
-  k_setup<<<1, kSetupThreads, 0, s>>>(w.set_off, p.nsets, p.n, w.tile_start, w.tile_set,
-                                      w.chunk_start, w.chunk_set,
+// The set of every cell tile and bounding-box chunk: one thread per entry,
+// binary search over the first-tile / first-chunk tables.
+__global__ __launch_bounds__(256) void k_tile_map(const int64_t *__restrict__ tile_start,
+                                                  int32_t *__restrict__ tile_set,
+                                                  int64_t cell_tiles,
+                                                  const int64_t *__restrict__ chunk_start,
+                                                  int32_t *__restrict__ chunk_set,
+                                                  int64_t bbox_chunks, int with_chunks,
+                                                  int32_t nsets) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < cell_tiles) {
+    if (i < tile_start[nsets]) tile_set[i] = upper_index(tile_start, nsets + 1, i);
+  } else if (with_chunks) {
+    const int64_t c = i - cell_tiles;
+    if (c < bbox_chunks && c < chunk_start[nsets])
+      chunk_set[c] = upper_index(chunk_start, nsets + 1, c);
+  }
+}
+
+hipError_t launch_setup(const Plan &p, const Work &w, const BatchIn &in, int32_t *status,
+                        hipStream_t s) {
+  if (single_set(p, in)) return hipSuccess;  // written by k_init
+  const bool with_chunks = in.auto_box;
+  k_setup<<<1, kSetupThreads, 0, s>>>(w.set_off, p.nsets, p.n, w.tile_start, w.chunk_start,
                                       w.hist + (size_t)p.key_passes * p.sort.radix(),
                                       p.set_passes, p.sort.bits, with_chunks ? 1 : 0, w.box,
-                                      check_boxes ? 1 : 0, status);
+                                      in.dev_boxes ? 1 : 0, status);
+  const int64_t entries = p.cell_tiles + (with_chunks ? p.bbox_chunks : 0);
+  k_tile_map<<<(unsigned)((entries + 255) / 256), 256, 0, s>>>(
+      w.tile_start, w.tile_set, p.cell_tiles, w.chunk_start, w.chunk_set, p.bbox_chunks,
+      with_chunks ? 1 : 0, p.nsets);
   return hipGetLastError();
 }
 
@@ -325,6 +372,9 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
   __syncthreads();
 
   bool bad = false;
+  // the box of set 0 (the only one of a single build) stays in registers
+  const double b_lo0 = box[0], b_lo1 = box[1], b_lo2 = box[2];
+  const double b_scale = 2097152.0 / box[3];
   // each step a thread handles kKeygenIpt particles whose loads are all issued
   // before any is used (indices past the end are clamped and masked)
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kKeygenIpt;
@@ -343,9 +393,14 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
     for (int r = 0; r < kKeygenIpt; ++r) {
       const int64_t i = i0 + (int64_t)r * blockDim.x;
       const bool valid = i < n;
-      const int b = nsets == 1 ? 0 : upper_index(s_off, nsets + 1, i);
-      const double lo0 = box[4 * b + 0], lo1 = box[4 * b + 1], lo2 = box[4 * b + 2];
-      const double scale = 2097152.0 / box[4 * b + 3];
+      double lo0 = b_lo0, lo1 = b_lo1, lo2 = b_lo2, scale = b_scale;
+      if (nsets > 1) {
+        const int b = upper_index(s_off, nsets + 1, i);
+        lo0 = box[4 * b + 0];
+        lo1 = box[4 * b + 1];
+        lo2 = box[4 * b + 2];
+        scale = 2097152.0 / box[4 * b + 3];
+      }
       bad |= valid && !(isfinite(x[r]) && isfinite(y[r]) && isfinite(z[r]));
       const uint64_t qx = quantise(x[r], lo0, scale);
       const uint64_t qy = quantise(y[r], lo1, scale);
