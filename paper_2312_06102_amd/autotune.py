@@ -17,6 +17,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import sys
 from typing import Optional
 
 import torch
@@ -104,7 +105,7 @@ def tune(pos, mass, n_leaf: int, precision: str = "fp64", set_offsets=None, boxe
         results[k] = time_config(k, pos, mass, n_leaf, precision, set_offsets, boxes, box, reps)
         if verbose:
             print(f"[autotune] {key} config {k} {tb.tb_sort_configs()[k]}: {results[k]:.3f} ms",
-                  flush=True)
+                  file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     best = min(results, key=results.get)
     _store(path, key, {"sort_config": best, "shape": list(tb.tb_sort_configs()[best]),

@@ -15,8 +15,8 @@ namespace tb {
 
 // Table of sort shapes selectable through TB_SORT_CONFIG(k); entry 0 is the default.
 static const SortConfig kSortTable[] = {
-    {8, 8, 512},  {8, 16, 256}, {9, 16, 256}, {8, 12, 256},
-    {9, 12, 256}, {8, 8, 256},  {8, 12, 512},
+    {8, 12, 512}, {8, 16, 256}, {9, 16, 256}, {8, 12, 256},
+    {9, 12, 256}, {8, 8, 256},  {8, 8, 512},
 };
 static const int kSortTableSize = (int)(sizeof(kSortTable) / sizeof(kSortTable[0]));
 
@@ -232,13 +232,12 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
   for (int pass = 0; pass < p.key_passes + p.set_passes; ++pass)
     run(pass < p.key_passes ? "sort_pass" : "set_pass",
         [&] { return launch_sort_pass(p, w, pass, *out, s); });
+  run("reorder", [&] { return launch_reorder(p, w, *out, s); });
   run("cell_count", [&] { return launch_cell_count(p, w, s); });
   run("cell_scan", [&] { return launch_cell_scan(p, w, *out, cell_offsets, s); });
-  run("reorder", [&] { return launch_reorder(p, w, *out, s); });
   run("cell_emit", [&] { return launch_cell_emit(p, w, *out, s); });
   for (int d = kMaxDepth - 1; d >= 0; --d)
     run("parents", [&] { return launch_parents(p, w, d, *out, s); });
-  if (out->key_sorted) run("copy_keys", [&] { return launch_copy_keys(p, w, *out, s); });
   return e == hipSuccess ? TB_OK : TB_ERR_HIP;
 }
 

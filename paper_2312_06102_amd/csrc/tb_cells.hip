@@ -19,9 +19,9 @@
 // bottom-up pass below knows, before any parent exists, how many cells each
 // depth will hold and where each cell goes in the (depth, key) order.
 //
-// k_cell_count : per tile, per-depth cell counts (and packed particle records);
+// k_reorder    : particles in key order (the reorder step) and their keys;
+// k_cell_count : per tile, per-depth cell counts;
 // k_cell_scan  : per-depth prefix over tiles;
-// k_reorder    : particles in key order (the reorder step);
 // k_cell_emit  : writes key, depth, first particle and first-child slot of
 //                every cell, and count plus moments of every leaf.
 #include "tb_internal.h"
@@ -40,10 +40,18 @@ struct CellLds {
   uint32_t *lvl;   // [kLevels]       per-depth base of this tile
   uint16_t *off;   // [kLevels][kCellThreads] next cell slot per depth per thread (tile-relative)
   float4 *rec;     // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL)
-  uint32_t *leaf_ci;   // [T]         cell slot of each leaf starting in the tile
-  uint16_t *leaf_tag;  // [T]         local first particle | depth << 11
+  uint32_t *leaf;      // [T]         leaf starting in the tile: local first particle |
+                       //             depth << 11 | slot within its depth << 16
+  uint16_t *leaf_len;  // [T]         particles of the leaf (65535: recompute); aliases off
+  uint16_t *order;     // [T]         leaves by decreasing length; aliases off
+  uint32_t *bucket;    // [2][kLenClasses] leaves per length class, then fill cursors
+  uint8_t *heads;      // [T / 8]     bit li: particle t0 + li starts a leaf
   uint32_t *nleaf;     // [1]
 };
+
+// Leaves are processed one per lane; sorting a tile's leaves by length first
+// gives every wave leaves of similar length, so lanes do not idle.
+constexpr int kLenClasses = 64;
 
 __host__ __device__ inline size_t cell_lds_bytes(int nl, bool emit) {
   size_t b = (size_t)(kCellTile + 2 * nl + 1) * 8;
@@ -52,7 +60,8 @@ __host__ __device__ inline size_t cell_lds_bytes(int nl, bool emit) {
   if (emit) {
     b += (size_t)kLevels * kCellThreads * 2;
     b = (b + 15) & ~size_t(15);
-    b += (size_t)(kCellTile + nl) * 16 + (size_t)kCellTile * 6 + 16;
+    b += (size_t)(kCellTile + nl) * 16 + (size_t)kCellTile * 4 + 8 * kLenClasses + kCellTile / 8 +
+         16;
   }
   return b;
 }
@@ -72,8 +81,11 @@ __device__ inline CellLds carve_lds(unsigned char *base, int nl, bool emit) {
   base += kLevels * 4;
   s.off = nullptr;
   s.rec = nullptr;
-  s.leaf_ci = nullptr;
-  s.leaf_tag = nullptr;
+  s.leaf = nullptr;
+  s.leaf_len = nullptr;
+  s.order = nullptr;
+  s.bucket = nullptr;
+  s.heads = nullptr;
   s.nleaf = nullptr;
   if (emit) {
     s.off = reinterpret_cast<uint16_t *>(base);
@@ -81,10 +93,15 @@ __device__ inline CellLds carve_lds(unsigned char *base, int nl, bool emit) {
     base = reinterpret_cast<unsigned char *>((reinterpret_cast<uintptr_t>(base) + 15) & ~uintptr_t(15));
     s.rec = reinterpret_cast<float4 *>(base);
     base += (size_t)(kCellTile + nl) * 16;
-    s.leaf_ci = reinterpret_cast<uint32_t *>(base);
+    s.leaf = reinterpret_cast<uint32_t *>(base);
     base += (size_t)kCellTile * 4;
-    s.leaf_tag = reinterpret_cast<uint16_t *>(base);
-    base += (size_t)kCellTile * 2;
+    // the per-depth cursors are dead once the cells are placed
+    s.leaf_len = s.off;
+    s.order = s.off + kCellTile;
+    s.bucket = reinterpret_cast<uint32_t *>(base);
+    base += (size_t)8 * kLenClasses;
+    s.heads = base;
+    base += kCellTile / 8;
     s.nleaf = reinterpret_cast<uint32_t *>(base);
   }
   return s;
@@ -401,22 +418,34 @@ __global__ __launch_bounds__(kSetScanThreads) void k_set_scan(
 // reorder pass (Sec. 2.3, step iii)
 // ---------------------------------------------------------------------------
 // sorted[s] = packed[perm[s]]: the particles in key order, one 16-byte record
-// each.  Every thread issues all of its index loads, then all of its gathers,
-// so the random reads overlap.  Also fills the optional pos_sorted /
-// mass_sorted outputs and checks the masses.
+// each, and their keys recomputed from the gathered positions (the same FP64
+// arithmetic as the key pass, so the keys are identical).  One workgroup per
+// cell tile, so the whole tile shares one set and one root box.  Every thread
+// issues all of its index loads, then all of its gathers, so the random reads
+// overlap.  Also fills the optional pos_sorted / mass_sorted / key_sorted
+// outputs and checks the masses.
 constexpr int kReorderThreads = 256;
 constexpr int kReorderIpt = 8;
+static_assert(kReorderThreads * kReorderIpt == kCellTile, "reorder works on cell tiles");
 
 __global__ __launch_bounds__(kReorderThreads) void k_reorder(
     const int32_t *__restrict__ perm, const float4 *__restrict__ packed, int64_t n,
-    float4 *__restrict__ sorted, float *__restrict__ pos_sorted,
-    float *__restrict__ mass_sorted, int32_t *__restrict__ status_word) {
-  const int64_t base = (int64_t)blockIdx.x * kReorderThreads * kReorderIpt + threadIdx.x;
+    const int64_t *__restrict__ tile_start, const int32_t *__restrict__ tile_set,
+    const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
+    float4 *__restrict__ sorted, uint64_t *__restrict__ keys, uint64_t *__restrict__ key_out,
+    float *__restrict__ pos_sorted, float *__restrict__ mass_sorted,
+    int32_t *__restrict__ status_word) {
+  const int64_t tile = blockIdx.x;
+  if (tile >= tile_start[nsets]) return;
+  const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
+  const double lo0 = box[4 * tr.b + 0], lo1 = box[4 * tr.b + 1], lo2 = box[4 * tr.b + 2];
+  const double scale = 2097152.0 / box[4 * tr.b + 3];
+  const int64_t base = tr.t0 + threadIdx.x;
   int32_t p[kReorderIpt];
 #pragma unroll
   for (int r = 0; r < kReorderIpt; ++r) {
     const int64_t sp = base + r * kReorderThreads;
-    p[r] = perm[sp < n ? sp : n - 1];
+    p[r] = perm[sp < tr.t1 ? sp : tr.t1 - 1];
   }
   // branch-free gathers (out-of-range indices are clamped and reported) so
   // that all of them are in flight together
@@ -426,14 +455,17 @@ __global__ __launch_bounds__(kReorderThreads) void k_reorder(
   for (int r = 0; r < kReorderIpt; ++r) {
     const int64_t sp = base + r * kReorderThreads;
     const bool ok = p[r] >= 0 && p[r] < n;
-    internal |= (sp < n) && !ok;
+    internal |= (sp < tr.t1) && !ok;
     rec[r] = packed[ok ? p[r] : 0];
   }
 #pragma unroll
   for (int r = 0; r < kReorderIpt; ++r) {
     const int64_t sp = base + r * kReorderThreads;
-    if (sp < n) {
+    if (sp < tr.t1) {
       sorted[sp] = rec[r];
+      const uint64_t key = morton_key(rec[r].x, rec[r].y, rec[r].z, lo0, lo1, lo2, scale);
+      keys[sp] = key;
+      if (key_out) key_out[sp] = key;
       bad |= !(rec[r].w > 0.0f && isfinite(rec[r].w));
       if (pos_sorted) {
         pos_sorted[3 * sp + 0] = rec[r].x;
@@ -481,6 +513,26 @@ __device__ inline int64_t leaf_end(const CellLds &s, const uint64_t *__restrict_
       hi = mid;
   }
   return lo;
+}
+
+// The same leaf end from the tile's head mask: a leaf ends where the next leaf
+// starts (a particle inside the leaf shares the leaf's prefix with its
+// predecessor, so it starts no cell; the first particle past the leaf differs
+// from its predecessor at depth <= the leaf depth and starts its own leaf).
+// Only a leaf reaching past the tile falls back to the halo scan.
+__device__ inline int64_t leaf_end_fast(const CellLds &s, const uint64_t *__restrict__ keys,
+                                        int64_t n, int nl, int64_t t0, int T, int li, int dl) {
+  const uint64_t *hw = reinterpret_cast<const uint64_t *>(s.heads);
+  const int nw = (T + 63) >> 6;
+  int w = li >> 6;
+  const int b = li & 63;
+  uint64_t bits = b == 63 ? 0ull : (hw[w] >> (b + 1)) << (b + 1);
+  while (bits == 0 && ++w < nw) bits = hw[w];
+  if (bits != 0) {
+    const int p = (w << 6) + __ffsll((long long)bits) - 1;
+    if (p < T) return t0 + p;
+  }
+  return leaf_end(s, keys, n, nl, t0, t0 + li, dl);
 }
 
 // FP64 leaf moments in the leaf's frame: one pass of sums of m, m r and m r r
@@ -635,12 +687,19 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     }
   }
   if (threadIdx.x == 0) *s.nleaf = 0;
+  if (threadIdx.x < kLenClasses) s.bucket[threadIdx.x] = 0;
 
   uint8_t A[kCellIpt], D[kCellIpt];
   tile_depths(s, keys, tr.S, tr.E, nl, t0, t1, A, D);  // its barriers also publish s.lvl, s.rec
+  {
+    uint32_t hb = 0;
+#pragma unroll
+    for (int j = 0; j < kCellIpt; ++j) hb |= (A[j] <= D[j] ? 1u : 0u) << j;
+    s.heads[threadIdx.x] = (uint8_t)hb;  // items 8t .. 8t+7 (none past the tile end)
+  }
   uint32_t c[kLevelWords], tot[kLevelWords];
   thread_level_counts(A, D, c);
-  block_level_scan(s, c, tot);
+  block_level_scan(s, c, tot);  // its barriers also publish s.heads
 #pragma unroll
   for (int d = 0; d < kLevels; ++d) s.off[d * kCellThreads + threadIdx.x] = (uint16_t)unpack(c, d);
   // this thread's leaves go to a contiguous run of the leaf list
@@ -679,25 +738,48 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
         if ((int64_t)fc < c_max) head_parent[fc] = (int32_t)ci;
       } else {
         reinterpret_cast<int2 *>(child_ptr)[ci] = make_int2(-1, 0);
-        s.leaf_ci[leaf_slot] = ci;
-        s.leaf_tag[leaf_slot] = (uint16_t)(li | (dl << 11));
+        s.leaf[leaf_slot] = (uint32_t)li | ((uint32_t)dl << 11) | (rel << 16);
         ++leaf_slot;
       }
     }
   }
   __syncthreads();
 
+  // leaf lengths, then a counting sort of the leaves by decreasing length
+  // (class = min(length, 63))
+  const uint32_t nlv = *s.nleaf;
+  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
+    const uint32_t e = s.leaf[x];
+    const int li = e & 0x7ff, dl = (e >> 11) & 31;
+    const int64_t len = leaf_end_fast(s, keys, n, nl, t0, (int)(t1 - t0), li, dl) - (t0 + li);
+    s.leaf_len[x] = (uint16_t)min(len, (int64_t)65535);
+    atomicAdd(&s.bucket[kLenClasses - 1 - (int)min(len, (int64_t)kLenClasses - 1)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const uint32_t c = threadIdx.x < kLenClasses ? s.bucket[threadIdx.x] : 0u;
+    const uint32_t inc = wave_inclusive_scan(c);
+    if (threadIdx.x < kLenClasses) s.bucket[kLenClasses + threadIdx.x] = inc - c;
+  }
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
+    const int cls = kLenClasses - 1 - min((int)s.leaf_len[x], kLenClasses - 1);
+    s.order[atomicAdd(&s.bucket[kLenClasses + cls], 1u)] = (uint16_t)x;
+  }
+  __syncthreads();
+
   // leaf moments: one lane per leaf, particles read from LDS
   const double lo[3] = {box[4 * tr.b + 0], box[4 * tr.b + 1], box[4 * tr.b + 2]};
   const double side = box[4 * tr.b + 3];
-  const uint32_t nlv = *s.nleaf;
-  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
-    const uint32_t ci = s.leaf_ci[x];
-    const int li = s.leaf_tag[x] & 0x7ff;
-    const int dl = s.leaf_tag[x] >> 11;
+  for (uint32_t xo = threadIdx.x; xo < nlv; xo += kCellThreads) {
+    const uint32_t x = s.order[xo];
+    const uint32_t le = s.leaf[x];
+    const int li = le & 0x7ff;
+    const int dl = (le >> 11) & 31;
+    const uint32_t ci = s.lvl[dl] + (le >> 16);
     const int64_t i = t0 + li;
     const uint64_t key = s.keys[li + nl + 1];
-    const int64_t e = leaf_end(s, keys, n, nl, t0, i, dl);
+    const int64_t e = s.leaf_len[x] < 65535 ? i + s.leaf_len[x] : leaf_end(s, keys, n, nl, t0, i, dl);
     cell_count[ci] = (int32_t)(e - i);
     const int sh = kMaxDepth - dl;
     const uint32_t ijk[3] = {compact3(key >> 2) >> sh, compact3(key >> 1) >> sh, compact3(key) >> sh};
@@ -772,9 +854,9 @@ hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
 }
 
 hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
-  const int64_t per = (int64_t)kReorderThreads * kReorderIpt;
-  k_reorder<<<(unsigned)((p.n + per - 1) / per), kReorderThreads, 0, s>>>(
-      out.perm, w.packed, p.n, w.sorted, out.pos_sorted, out.mass_sorted, out.status);
+  k_reorder<<<(unsigned)p.cell_tiles, kReorderThreads, 0, s>>>(
+      out.perm, w.packed, p.n, w.tile_start, w.tile_set, w.set_off, p.nsets, w.box, w.sorted,
+      sorted_keys(p, w), out.key_sorted, out.pos_sorted, out.mass_sorted, out.status);
   return hipGetLastError();
 }
 

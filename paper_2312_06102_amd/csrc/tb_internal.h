@@ -146,7 +146,6 @@ hipError_t launch_bbox(const Plan &p, const Work &w, const float *pos, hipStream
 hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const float *mass,
                          const tb_tree &out, hipStream_t s);
 hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s);
-hipError_t launch_copy_keys(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
 int keygen_blocks(int64_t n);
 hipError_t launch_empty(const tb_tree &out, int32_t nsets, const BatchIn &in,
                         int64_t *cell_offsets, hipStream_t s);
@@ -166,10 +165,9 @@ size_t cell_lds_limit();
 hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
                           hipStream_t s);
 
-// Final sorted keys live in keys0 or keys1 depending on the number of passes.
-inline uint64_t *sorted_keys(const Plan &p, const Work &w) {
-  return ((p.key_passes + p.set_passes) % 2 == 0) ? w.keys0 : w.keys1;
-}
+// The sorted keys, recomputed from the sorted particles by the reorder pass (the
+// sort passes themselves stop carrying the key once its bits are consumed).
+inline uint64_t *sorted_keys(const Plan &, const Work &w) { return w.keys0; }
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -238,6 +236,38 @@ __device__ inline uint32_t lookback(const uint64_t *status, int64_t stride, int6
     q -= W;
   }
   return excl;
+}
+
+// Spread the low 21 bits of v so that bit b lands on bit 3b.
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x001f00000000ffffull;
+  v = (v | (v << 16)) & 0x001f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+// floor(fl64(x - lo) * scale) clamped to [0, 2^21 - 1]; scale = 2^21 / side is a
+// power of two, so the multiply is exact and only the subtraction rounds
+// (Sec. 2.2: each coordinate becomes a 21-bit integer inside the root cube).
+__device__ __forceinline__ uint32_t quantise(float x, double lo, double scale) {
+  const double u = __dsub_rn((double)x, lo);
+  const double t = __dmul_rn(u, scale);
+  if (!(t >= 0.0)) return 0u;
+  if (t >= 2097152.0) return 2097151u;
+  return (uint32_t)t;  // truncation == floor for t >= 0
+}
+
+// 64-bit key: a leading 1, then per depth the octant digit (x, y, z) with x the
+// most significant bit (Sec. 2.2).
+__device__ __forceinline__ uint64_t morton_key(float x, float y, float z, double lo0,
+                                               double lo1, double lo2, double scale) {
+  const uint64_t qx = quantise(x, lo0, scale);
+  const uint64_t qy = quantise(y, lo1, scale);
+  const uint64_t qz = quantise(z, lo2, scale);
+  return (1ull << 63) | (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
 }
 
 // Minimum distinguished depth of two particle keys (Sec. 2.3.1): leading zeros

@@ -336,27 +336,6 @@ hipError_t launch_bbox(const Plan &p, const Work &w, const float *pos, hipStream
 // Morton keys
 // ---------------------------------------------------------------------------
 
-// Spread the low 21 bits of v so that bit b lands on bit 3b.
-__device__ __forceinline__ uint64_t spread3(uint64_t v) {
-  v &= 0x1fffffull;
-  v = (v | (v << 32)) & 0x001f00000000ffffull;
-  v = (v | (v << 16)) & 0x001f0000ff0000ffull;
-  v = (v | (v << 8)) & 0x100f00f00f00f00full;
-  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
-  v = (v | (v << 2)) & 0x1249249249249249ull;
-  return v;
-}
-
-// floor(fl64(x - lo) * scale) clamped to [0, 2^21 - 1]; scale = 2^21 / side is a
-// power of two, so the multiply is exact and only the subtraction rounds.
-__device__ __forceinline__ uint32_t quantise(float x, double lo, double scale) {
-  const double u = __dsub_rn((double)x, lo);
-  const double t = __dmul_rn(u, scale);
-  if (!(t >= 0.0)) return 0u;
-  if (t >= 2097152.0) return 2097151u;
-  return (uint32_t)t;  // truncation == floor for t >= 0
-}
-
 template <int BITS>
 __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
     const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
@@ -402,10 +381,7 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
         scale = 2097152.0 / box[4 * b + 3];
       }
       bad |= valid && !(isfinite(x[r]) && isfinite(y[r]) && isfinite(z[r]));
-      const uint64_t qx = quantise(x[r], lo0, scale);
-      const uint64_t qy = quantise(y[r], lo1, scale);
-      const uint64_t qz = quantise(z[r], lo2, scale);
-      const uint64_t key = (1ull << 63) | (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+      const uint64_t key = morton_key(x[r], y[r], z[r], lo0, lo1, lo2, scale);
       if (valid) {
         keys[i] = key;
         // (x, y, z, m) in one 16-byte record: the reorder step gathers one line each
@@ -487,21 +463,6 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const f
 hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s) {
   const int cols = p.key_passes * p.sort.radix();
   k_hist_reduce<<<(cols + 15) / 16, 256, 0, s>>>(w.hist_part, keygen_blocks(p.n), cols, w.hist);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// optional sorted-key output (a copy kernel keeps captured graphs simple)
-// ---------------------------------------------------------------------------
-__global__ void k_copy_u64(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
-}
-
-hipError_t launch_copy_keys(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
-  int64_t blocks = (p.n + 1023) / 1024;
-  if (blocks > 2048) blocks = 2048;
-  k_copy_u64<<<(unsigned)blocks, 256, 0, s>>>(sorted_keys(p, w), out.key_sorted, p.n);
   return hipGetLastError();
 }
 

@@ -15,6 +15,13 @@
 //     run.
 // The global digit counts come from the key-generation pass, so the keys are
 // read only once per pass.  The index payload of the last pass is `perm`.
+//
+// Key width shrinks as the passes go: a pass carries only the key bits later
+// passes still need.  Passes whose digit lies (partly) in the low 32 bits read
+// the 64-bit key; once those bits are consumed the key travels as its upper 32
+// bits; the last key pass writes no key at all, and the set-id passes of a batch
+// move only the payload.  The sorted keys themselves are recomputed from the
+// sorted particles in the reorder pass, which reads those particles anyway.
 #include "tb_internal.h"
 
 namespace tb {
@@ -39,7 +46,20 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *s_
   return off + inc - v;
 }
 
-// Digit of a 64-bit key at bit offset `shift` (uniform), from its two halves.
+// Key storage of a pass: the full 64-bit key, its upper 32 bits, or nothing.
+enum KeyWidth { kKeyNone = 0, kKey32 = 1, kKey64 = 2 };
+
+template <int W>
+struct KeyType {
+  using T = uint32_t;
+};
+template <>
+struct KeyType<kKey64> {
+  using T = uint64_t;
+};
+
+// Digit at bit offset `shift` (uniform) of a key stored with width W (for
+// kKey32 the shift is already relative to bit 32).
 template <int BITS>
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
   const uint32_t lo = (uint32_t)k, hi = (uint32_t)(k >> 32);
@@ -47,25 +67,35 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
                                 : (hi >> (shift - 32));
   return w & ((1u << BITS) - 1u);
 }
+template <int BITS>
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
+  return (k >> shift) & ((1u << BITS) - 1u);
+}
 
-// SETID = false: the digit is taken from the key.  SETID = true (batches):
-// the digit is taken from the set that holds the payload's original index, and
-// the keys travel as payload, so that after the key passes these passes group
-// the particles by set without disturbing the key order inside a set.
-template <int BITS, int IPT, int THREADS, bool SETID>
+// KIN / KOUT: key width read / written (kKeyNone in: a set-id pass).
+// SETID passes take the digit from the set that holds the payload's original
+// index, so that after the key passes they group the particles by set without
+// disturbing the key order inside a set.
+template <int BITS, int IPT, int THREADS, int KIN, int KOUT>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
-    const uint64_t *__restrict__ kin, uint64_t *__restrict__ kout,
+    const void *__restrict__ kin_v, void *__restrict__ kout_v,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
     const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
     int32_t *__restrict__ status_word, uint32_t n_tiles, const int64_t *__restrict__ set_off,
     int32_t nsets) {
+  constexpr bool SETID = KIN == kKeyNone;
+  using KI = typename KeyType<KIN == kKeyNone ? kKey32 : KIN>::T;
+  using KO = typename KeyType<KOUT == kKeyNone ? kKey32 : KOUT>::T;
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
   constexpr int TILE = THREADS * IPT;
   constexpr int DPT = (R + THREADS - 1) / THREADS;  // digits per thread
+  // the local sort keeps the input key (when a key is written), or else the
+  // digit of each slot
+  constexpr int SLOT_BYTES = KOUT == kKeyNone ? 2 : (int)sizeof(KI);
 
-  __shared__ uint64_t s_keys[TILE];
+  __shared__ __align__(16) unsigned char s_slot[TILE * SLOT_BYTES];
   __shared__ uint32_t s_vals[TILE];
   __shared__ uint32_t s_wc[WAVES * R];     // per-wave digit counters, then wave offsets
   __shared__ uint32_t s_tstart[R];         // tile-local start of each digit
@@ -73,10 +103,12 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
   extern __shared__ uint32_t s_soff[];  // SETID: [nsets + 1] set offsets
+  const KI *__restrict__ kin = static_cast<const KI *>(kin_v);
+  KO *__restrict__ kout = static_cast<KO *>(kout_v);
   if constexpr (SETID) {
     for (int i = threadIdx.x; i <= nsets; i += THREADS) s_soff[i] = (uint32_t)set_off[i];
   }
-  auto digit = [&](uint64_t kk, uint32_t vv) -> uint32_t {
+  auto digit = [&](KI kk, uint32_t vv) -> uint32_t {
     if constexpr (SETID) {
       return ((uint32_t)upper_index(s_soff, nsets + 1, (int64_t)vv) >> shift) & ((1u << BITS) - 1u);
     } else {
@@ -107,12 +139,18 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   // wave-striped load: item j of lane l is key base + wv*64*IPT + j*64 + l.
   // Loads are branch-free (indices past the end are clamped and the items
   // masked later) so that all of them are in flight together.
-  uint64_t k[IPT];
+  KI k[IPT];
   uint32_t v[IPT];
+  uint32_t dg[IPT];
   uint32_t rk[IPT];
   const uint32_t wbase = base + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
+  if constexpr (!SETID) {
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, n - 1u)];
+    for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, n - 1u)];
+  } else {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) k[j] = 0;
+  }
   if (vin) {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, n - 1u)];
@@ -120,6 +158,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
     for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
   }
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) dg[j] = digit(k[j], v[j]);
 
   // Stable wave-level ranking: for every digit bit a ballot; XOR-ing the
   // ballot with "all ones unless my bit is set" keeps exactly the lanes that
@@ -129,7 +169,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const bool valid = wbase + j * 64 < n;
-    const uint32_t d = digit(k[j], v[j]);
+    const uint32_t d = dg[j];
     const uint64_t vmask = __ballot(valid);
     uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
 #pragma unroll
@@ -200,13 +240,17 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   }
   __syncthreads();
 
-  // sort the tile by digit in LDS
+  // sort the tile by digit in LDS (the input key when a key is written, else
+  // the digit)
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     if (wbase + j * 64 < n) {
-      const uint32_t d = digit(k[j], v[j]);
+      const uint32_t d = dg[j];
       const uint32_t p = s_tstart[d] + wc[d] + rk[j];
-      s_keys[p] = k[j];
+      if constexpr (KOUT == kKeyNone)
+        reinterpret_cast<uint16_t *>(s_slot)[p] = (uint16_t)d;
+      else
+        reinterpret_cast<KI *>(s_slot)[p] = k[j];
       s_vals[p] = v[j];
     }
   }
@@ -218,24 +262,43 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   const uint32_t tile_n = (n - base) < (uint32_t)TILE ? (n - base) : (uint32_t)TILE;
   bool bad = false;
   for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
-    const uint64_t key = s_keys[i];
-    const uint32_t d = digit(key, s_vals[i]);
+    uint32_t d;
+    KO key = 0;
+    if constexpr (KOUT == kKeyNone) {
+      d = reinterpret_cast<const uint16_t *>(s_slot)[i];
+    } else {
+      const KI kk = reinterpret_cast<const KI *>(s_slot)[i];
+      d = digit_of<BITS>(kk, shift);
+      // a 64-bit key keeps only its upper half once its low bits are consumed
+      key = (KIN == kKey64 && KOUT == kKey32) ? (KO)((uint64_t)kk >> 32) : (KO)kk;
+    }
     const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
     if (gp >= n) {  // cannot happen with consistent histograms
       bad = true;
       continue;
     }
-    kout[gp] = key;
+    if constexpr (KOUT != kKeyNone) kout[gp] = key;
     vout[gp] = s_vals[i];
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
-template <int BITS, int IPT, int THREADS>
-static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb_tree &out,
+// Key widths of pass `pass`: a key pass whose digit starts below bit 32 reads
+// the 64-bit key; later key passes read the upper 32 bits; set-id passes read
+// no key.  A pass writes what the next pass reads.
+static int key_in(const Plan &p, int pass) {
+  if (pass >= p.key_passes) return kKeyNone;
+  return pass * p.sort.bits < 32 ? kKey64 : kKey32;
+}
+static int key_out(const Plan &p, int pass) {
+  return pass + 1 < p.key_passes ? key_in(p, pass + 1) : kKeyNone;
+}
+
+template <int BITS, int IPT, int THREADS, int KIN, int KOUT>
+static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
   const int P = p.key_passes + p.set_passes;
-  uint64_t *K[2] = {w.keys0, w.keys1};
+  void *K[2] = {w.keys0, w.keys1};
   // the last pass must write its payload into out.perm
   uint32_t *V[2];
   V[P % 2] = reinterpret_cast<uint32_t *>(out.perm);
@@ -243,15 +306,34 @@ static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb
   uint64_t *S[2] = {w.status0, w.status1};
   const uint32_t *vin = pass == 0 ? nullptr : V[pass % 2];
   const int R = 1 << BITS;
-  const bool setid = pass >= p.key_passes;
-  const int shift = setid ? (pass - p.key_passes) * BITS : pass * BITS;
-  auto k = setid ? k_onesweep<BITS, IPT, THREADS, true> : k_onesweep<BITS, IPT, THREADS, false>;
-  const size_t lds = setid ? 4 * (size_t)(p.nsets + 1) : 0;
-  k<<<(unsigned)p.sort_tiles, THREADS, lds, s>>>(
+  int shift;
+  if (KIN == kKeyNone)
+    shift = (pass - p.key_passes) * BITS;  // set-id digit
+  else
+    shift = pass * BITS - (KIN == kKey32 ? 32 : 0);
+  const size_t lds = KIN == kKeyNone ? 4 * (size_t)(p.nsets + 1) : 0;
+  k_onesweep<BITS, IPT, THREADS, KIN, KOUT><<<(unsigned)p.sort_tiles, THREADS, lds, s>>>(
       K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift,
       w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, out.status,
       (uint32_t)p.sort_tiles, w.set_off, p.nsets);
   return hipGetLastError();
+}
+
+template <int BITS, int IPT, int THREADS>
+static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb_tree &out,
+                                hipStream_t s) {
+  const int ki = key_in(p, pass), ko = key_out(p, pass);
+  if (ki == kKey64 && ko == kKey64)
+    return launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64>(p, w, pass, out, s);
+  if (ki == kKey64 && ko == kKey32)
+    return launch_pass_k<BITS, IPT, THREADS, kKey64, kKey32>(p, w, pass, out, s);
+  if (ki == kKey32 && ko == kKey32)
+    return launch_pass_k<BITS, IPT, THREADS, kKey32, kKey32>(p, w, pass, out, s);
+  if (ki == kKey32 && ko == kKeyNone)
+    return launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone>(p, w, pass, out, s);
+  if (ki == kKeyNone && ko == kKeyNone)
+    return launch_pass_k<BITS, IPT, THREADS, kKeyNone, kKeyNone>(p, w, pass, out, s);
+  return hipErrorInvalidValue;  // no other combination arises for 8- or 9-bit digits
 }
 
 hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tree &out,
