@@ -119,26 +119,35 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: i
     compulsory traffic), per build.
 
     keygen      read pos 12 + mass 4; write key 8 + packed (x, y, z, m) record 16
-    sort_pass   pass 0 reads keys 8 (the payload is generated), later passes key 8 +
-                payload 4; every pass writes key 8 + payload 4
+    sort_pass   pass 0 reads keys 8 (the payload is generated); a pass moves the key
+                as 8 bytes while its digit touches the low 32 bits, then as the upper
+                4 bytes; the last key pass writes no key; payload 4 read (after pass 0)
+                and written by every pass
     set_pass    as a later key pass
-    cell_count  read sorted keys 8
-    reorder     read perm 4 + gathered record 16; write the record in key order 16
-    cell_emit   read sorted keys 8 + sorted records 16 per particle; write key 8, depth 1,
-                first 4, child link 8, head_parent 4 per cell, count 4 + moments per leaf
+    reorder     read perm 4 + gathered record 16; write the record in key order 16, its
+                key 8 and its (a_i, D_i) 2
+    cell_emit   read sorted keys 8 + sorted records 16 + (a_i, D_i) 2 per particle; write
+                key 8, depth 1, first 4, child link 8, head_parent 4 per cell, count 4 +
+                moments per leaf
     parents     per child cell read key 8 + count 4 + moments; per parent read head 4,
                 write count 4 + child count 4 + moments
     moments: FP64 80 B (com 32 + quad 48); mixed 44 B (com 16 + quad 24 + mass term 4)
     """
     mom = 80 if precision == "fp64" else 44
     inner = cells - leaves
+    bits = -(-63 // key_passes)  # digit width of these passes
+    sort = 0
+    for p in range(key_passes):
+        kin = 8 if p * bits < 32 else 4
+        nxt = p + 1
+        kout = 0 if nxt >= key_passes else (8 if nxt * bits < 32 else 4)
+        sort += (kin + (4 if p else 0) + kout + 4) * n
     return {
         "keygen": 40 * n,
-        "sort_pass": (20 + 24 * (key_passes - 1)) * n,
-        "set_pass": 24 * n * set_passes,
-        "cell_count": 8 * n,
-        "reorder": 36 * n,
-        "cell_emit": 24 * n + 25 * cells + (4 + mom) * leaves,
+        "sort_pass": sort,
+        "set_pass": 8 * n * set_passes,
+        "reorder": 46 * n,
+        "cell_emit": 26 * n + 25 * cells + (4 + mom) * leaves,
         "parents": (12 + mom) * max(cells - 1, 0) + (12 + mom) * inner,
     }
 

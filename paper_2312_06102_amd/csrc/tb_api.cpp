@@ -79,6 +79,7 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->par_start = take(8 * (size_t)kLevels * B1);
   p->packed = take(16 * (size_t)n);
   p->sorted = take(16 * (size_t)n);
+  p->ad = take(2 * (size_t)n);
   p->head_parent = take(4 * (size_t)p->c_max);
   p->m_lo = take((flags & 0xffu) == TB_MIXED ? 4 * (size_t)p->c_max : 0);
   p->total = off;
@@ -111,6 +112,7 @@ Work carve(const Plan &p, void *base) {
   w.par_start = reinterpret_cast<int64_t *>(b + p.par_start);
   w.packed = reinterpret_cast<float4 *>(b + p.packed);
   w.sorted = reinterpret_cast<float4 *>(b + p.sorted);
+  w.ad = reinterpret_cast<uint16_t *>(b + p.ad);
   w.head_parent = reinterpret_cast<int32_t *>(b + p.head_parent);
   w.m_lo = reinterpret_cast<float *>(b + p.m_lo);
   return w;
@@ -233,7 +235,6 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
     run(pass < p.key_passes ? "sort_pass" : "set_pass",
         [&] { return launch_sort_pass(p, w, pass, *out, s); });
   run("reorder", [&] { return launch_reorder(p, w, *out, s); });
-  run("cell_count", [&] { return launch_cell_count(p, w, s); });
   run("cell_scan", [&] { return launch_cell_scan(p, w, *out, cell_offsets, s); });
   run("cell_emit", [&] { return launch_cell_emit(p, w, *out, s); });
   for (int d = kMaxDepth - 1; d >= 0; --d)

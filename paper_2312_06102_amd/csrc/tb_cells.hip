@@ -19,9 +19,11 @@
 // bottom-up pass below knows, before any parent exists, how many cells each
 // depth will hold and where each cell goes in the (depth, key) order.
 //
-// k_reorder    : particles in key order (the reorder step) and their keys;
-// k_cell_count : per tile, per-depth cell counts;
-// k_cell_scan  : per-depth prefix over tiles;
+// k_reorder    : particles in key order (the reorder step) and their keys; from
+//                the keys of its tile plus an n_leaf halo, a_i and D_i of every
+//                particle and the tile's per-depth cell counts;
+// k_cell_scan  : per-depth prefix over the tiles of each set;
+// k_set_scan   : first cell of every set and depth;
 // k_cell_emit  : writes key, depth, first particle and first-child slot of
 //                every cell, and count plus moments of every leaf.
 #include "tb_internal.h"
@@ -30,111 +32,96 @@ namespace tb {
 
 constexpr int kWaves = kCellThreads / 64;
 constexpr int kMaxSpan = (kCellTile + TB_MAX_NLEAF + kCellThreads - 1) / kCellThreads;
-
-// Shared layout (dynamic LDS), sized for the actual n_leaf.
-struct CellLds {
-  uint64_t *keys;  // [T + 2 NL + 1]  keys of [t0 - NL - 1, t1 + NL)
-  uint8_t *m;      // [T + NL]        w_j, then the sparse max table, j in [t0 - NL, t1)
-  uint8_t *a;      // [T + NL]        a_i, i in [t0, t1 + NL)
-  uint32_t *wtot;  // [kWaves][kLevelWords]
-  uint32_t *lvl;   // [kLevels]       per-depth base of this tile
-  uint16_t *off;   // [kLevels][kCellThreads] next cell slot per depth per thread (tile-relative)
-  float4 *rec;     // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL)
-  uint32_t *leaf;      // [T]         leaf starting in the tile: local first particle |
-                       //             depth << 11 | slot within its depth << 16
-  uint16_t *leaf_len;  // [T]         particles of the leaf (65535: recompute); aliases off
-  uint16_t *order;     // [T]         leaves by decreasing length; aliases off
-  uint32_t *bucket;    // [2][kLenClasses] leaves per length class, then fill cursors
-  uint8_t *heads;      // [T / 8]     bit li: particle t0 + li starts a leaf
-  uint32_t *nleaf;     // [1]
-};
-
 // Leaves are processed one per lane; sorting a tile's leaves by length first
 // gives every wave leaves of similar length, so lanes do not idle.
 constexpr int kLenClasses = 64;
 
-__host__ __device__ inline size_t cell_lds_bytes(int nl, bool emit) {
-  size_t b = (size_t)(kCellTile + 2 * nl + 1) * 8;
-  b += 2 * (size_t)((kCellTile + nl + 15) & ~15);
-  b += (size_t)kWaves * kLevelWords * 4 + kLevels * 4;
-  if (emit) {
-    b += (size_t)kLevels * kCellThreads * 2;
-    b = (b + 15) & ~size_t(15);
-    b += (size_t)(kCellTile + nl) * 16 + (size_t)kCellTile * 4 + 8 * kLenClasses + kCellTile / 8 +
-         16;
-  }
-  return b;
+__host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// Shared layout of the reorder pass (dynamic LDS, sized for the actual n_leaf).
+struct WindowLds {
+  uint64_t *keys;  // [T + 2 NL + 1]  keys of [t0 - NL - 1, t1 + NL)
+  uint8_t *m;      // [T + NL]        w_j, then the sparse max table, j in [t0 - NL, t1)
+  uint8_t *a;      // [T + NL]        a_i, i in [t0, t1 + NL)
+  uint32_t *wtot;  // [kWaves][kLevelWords]
+};
+
+__host__ __device__ inline size_t window_lds_bytes(int nl) {
+  return round16((size_t)(kCellTile + 2 * nl + 1) * 8) + 2 * round16(kCellTile + nl) +
+         (size_t)kWaves * kLevelWords * 4;
 }
 
-__device__ inline CellLds carve_lds(unsigned char *base, int nl, bool emit) {
-  CellLds s;
+__device__ inline WindowLds carve_window(unsigned char *base, int nl) {
+  WindowLds s;
   s.keys = reinterpret_cast<uint64_t *>(base);
-  base += (size_t)(kCellTile + 2 * nl + 1) * 8;
-  const size_t span = (size_t)((kCellTile + nl + 15) & ~15);
+  base += round16((size_t)(kCellTile + 2 * nl + 1) * 8);
   s.m = base;
-  base += span;
+  base += round16(kCellTile + nl);
   s.a = base;
-  base += span;
+  base += round16(kCellTile + nl);
   s.wtot = reinterpret_cast<uint32_t *>(base);
-  base += kWaves * kLevelWords * 4;
-  s.lvl = reinterpret_cast<uint32_t *>(base);
-  base += kLevels * 4;
-  s.off = nullptr;
-  s.rec = nullptr;
-  s.leaf = nullptr;
-  s.leaf_len = nullptr;
-  s.order = nullptr;
-  s.bucket = nullptr;
-  s.heads = nullptr;
-  s.nleaf = nullptr;
-  if (emit) {
-    s.off = reinterpret_cast<uint16_t *>(base);
-    base += kLevels * kCellThreads * 2;
-    base = reinterpret_cast<unsigned char *>((reinterpret_cast<uintptr_t>(base) + 15) & ~uintptr_t(15));
-    s.rec = reinterpret_cast<float4 *>(base);
-    base += (size_t)(kCellTile + nl) * 16;
-    s.leaf = reinterpret_cast<uint32_t *>(base);
-    base += (size_t)kCellTile * 4;
-    // the per-depth cursors are dead once the cells are placed
-    s.leaf_len = s.off;
-    s.order = s.off + kCellTile;
-    s.bucket = reinterpret_cast<uint32_t *>(base);
-    base += (size_t)8 * kLenClasses;
-    s.heads = base;
-    base += kCellTile / 8;
-    s.nleaf = reinterpret_cast<uint32_t *>(base);
-  }
   return s;
 }
 
-// Loads the key window, computes a_i and the windowed maximum, and returns
-// (in D[]) the leaf depth of this thread's IPT consecutive particles.  The
-// tile [t0, t1) lies inside one set [S, E): the set's first particle starts a
-// root (a = 0) and windows never reach across the set's ends.
-__device__ inline void tile_depths(const CellLds &s, const uint64_t *__restrict__ keys, int64_t S,
-                                   int64_t E, int nl, int64_t t0, int64_t t1, uint8_t A[kCellIpt],
-                                   uint8_t D[kCellIpt]) {
+// Shared layout of the emit pass.
+struct EmitLds {
+  uint8_t *a;          // [T + NL]        a_i, i in [t0, t1 + NL)
+  uint8_t *d;          // [T]             D_i, i in [t0, t1)
+  uint32_t *wtot;      // [kWaves][kLevelWords]
+  uint32_t *lvl;       // [kLevels]       per-depth base of this tile
+  uint16_t *off;       // [kLevels][kCellThreads] next cell slot per depth per thread
+  float4 *rec;         // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL)
+  uint32_t *leaf;      // [T]             leaf starting in the tile: local first particle |
+                       //                 depth << 11 | slot within its depth << 16
+  uint16_t *leaf_len;  // [T]             particles of the leaf (65535: recompute); aliases off
+  uint16_t *order;     // [T]             leaves by decreasing length; aliases off
+  uint32_t *bucket;    // [2][kLenClasses] leaves per length class, then fill cursors
+  uint8_t *heads;      // [T / 8]         bit li: particle t0 + li starts a leaf
+  uint32_t *nleaf;     // [1]
+};
+
+__host__ __device__ inline size_t emit_lds_bytes(int nl) {
+  return round16(kCellTile + nl) + round16(kCellTile) + round16((size_t)kWaves * kLevelWords * 4) +
+         round16(kLevels * 4) + round16((size_t)kLevels * kCellThreads * 2) +
+         (size_t)(kCellTile + nl) * 16 + (size_t)kCellTile * 4 + 8 * kLenClasses + kCellTile / 8 +
+         16;
+}
+
+__device__ inline EmitLds carve_emit(unsigned char *base, int nl) {
+  EmitLds s;
+  s.a = base;
+  base += round16(kCellTile + nl);
+  s.d = base;
+  base += round16(kCellTile);
+  s.wtot = reinterpret_cast<uint32_t *>(base);
+  base += round16((size_t)kWaves * kLevelWords * 4);
+  s.lvl = reinterpret_cast<uint32_t *>(base);
+  base += round16(kLevels * 4);
+  s.off = reinterpret_cast<uint16_t *>(base);
+  base += round16((size_t)kLevels * kCellThreads * 2);
+  s.rec = reinterpret_cast<float4 *>(base);
+  base += (size_t)(kCellTile + nl) * 16;
+  s.leaf = reinterpret_cast<uint32_t *>(base);
+  base += (size_t)kCellTile * 4;
+  // the per-depth cursors are dead once the cells are placed
+  s.leaf_len = s.off;
+  s.order = s.off + kCellTile;
+  s.bucket = reinterpret_cast<uint32_t *>(base);
+  base += (size_t)8 * kLenClasses;
+  s.heads = base;
+  base += kCellTile / 8;
+  s.nleaf = reinterpret_cast<uint32_t *>(base);
+  return s;
+}
+
+// From the key window in LDS (positions [t0 - nl - 1, t1 + nl), zero outside
+// the set [S, E)): a_i and the windowed maximum, and (in A[], D[]) a_i and the
+// leaf depth of this thread's IPT consecutive particles.  The set's first
+// particle starts a root (a = 0) and windows never reach across the set's ends.
+__device__ inline void depths_from_window(const WindowLds &s, int64_t S, int64_t E, int nl,
+                                          int64_t t0, int64_t t1, uint8_t A[kCellIpt],
+                                          uint8_t D[kCellIpt]) {
   const int T = (int)(t1 - t0);
-  const int64_t ws = t0 - nl - 1;  // window start (may be negative)
-  const int wn = T + 2 * nl + 1;
-  // all loads of a batch are issued before any is stored, so a tile waits for
-  // one or two memory round trips instead of one per key
-  constexpr int kBatch = 8;
-  for (int i0 = 0; i0 < wn; i0 += kBatch * kCellThreads) {
-    uint64_t v[kBatch];
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      const int i = i0 + r * kCellThreads + threadIdx.x;
-      const int64_t g = ws + i;
-      v[r] = (i < wn && g >= S && g < E) ? keys[g] : 0ull;
-    }
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      const int i = i0 + r * kCellThreads + threadIdx.x;
-      if (i < wn) s.keys[i] = v[r];
-    }
-  }
-  __syncthreads();
   // a_i for i in [t0, t1 + nl)
   for (int i = threadIdx.x; i < T + nl; i += kCellThreads) {
     const int64_t g = t0 + i;
@@ -207,7 +194,7 @@ __device__ inline void thread_level_counts(const uint8_t A[kCellIpt], const uint
 }
 
 // Block-wide exclusive scan of the packed counters; also returns the totals.
-__device__ inline void block_level_scan(const CellLds &s, uint32_t c[kLevelWords],
+__device__ inline void block_level_scan(uint32_t *wtot, uint32_t c[kLevelWords],
                                         uint32_t tot[kLevelWords]) {
   const int wv = threadIdx.x / 64;
   uint32_t inc[kLevelWords];
@@ -215,7 +202,7 @@ __device__ inline void block_level_scan(const CellLds &s, uint32_t c[kLevelWords
   for (int wi = 0; wi < kLevelWords; ++wi) inc[wi] = wave_inclusive_scan(c[wi]);
   if (lane_id() == 63) {
 #pragma unroll
-    for (int wi = 0; wi < kLevelWords; ++wi) s.wtot[wv * kLevelWords + wi] = inc[wi];
+    for (int wi = 0; wi < kLevelWords; ++wi) wtot[wv * kLevelWords + wi] = inc[wi];
   }
   __syncthreads();
 #pragma unroll
@@ -223,7 +210,7 @@ __device__ inline void block_level_scan(const CellLds &s, uint32_t c[kLevelWords
     uint32_t off = 0, t = 0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) {
-      const uint32_t v = s.wtot[q * kLevelWords + wi];
+      const uint32_t v = wtot[q * kLevelWords + wi];
       off += (q < wv) ? v : 0u;
       t += v;
     }
@@ -236,9 +223,6 @@ __device__ __forceinline__ uint32_t unpack(const uint32_t w[kLevelWords], int d)
   return (w[d >> 1] >> ((d & 1) * 16)) & 0xffffu;
 }
 
-// ---------------------------------------------------------------------------
-// count pass
-// ---------------------------------------------------------------------------
 // Tile t of set b covers [t0, t1) inside the set's range [S, E).
 struct TileRange {
   int b;
@@ -257,22 +241,95 @@ __device__ __forceinline__ TileRange tile_range(int64_t t, const int64_t *__rest
   return r;
 }
 
-// Per tile, the number of cells each depth will hold whose first particle lies
-// in the tile (stored depth-major: cnt[d][tile]).
-__global__ __launch_bounds__(kCellThreads) void k_cell_count(
-    const uint64_t *__restrict__ keys, int nl, int64_t cell_tiles,
+// ---------------------------------------------------------------------------
+// reorder pass (Sec. 2.3, step iii) with the leaf depths
+// ---------------------------------------------------------------------------
+// sorted[s] = packed[perm[s]]: the particles in key order, one 16-byte record
+// each, and their keys recomputed from the gathered positions (the same FP64
+// arithmetic as the key pass, so the keys are identical).  One workgroup per
+// cell tile, so the whole tile shares one set and one root box.  The workgroup
+// also gathers the n_leaf + 1 particles on either side of its tile (inside the
+// set), which gives it the key window of the leaf-depth formula: it stores
+// a_i | D_i << 8 for every particle of the tile and the tile's cell count per
+// depth.  Every thread issues all of a batch's index loads, then all of its
+// gathers, so the random reads overlap.  Also fills the optional pos_sorted /
+// mass_sorted / key_sorted outputs and checks the masses.
+__global__ __launch_bounds__(kCellThreads) void k_reorder(
+    const int32_t *__restrict__ perm, const float4 *__restrict__ packed, int64_t n, int nl,
     const int64_t *__restrict__ tile_start, const int32_t *__restrict__ tile_set,
-    const int64_t *__restrict__ set_off, int32_t nsets, uint32_t *__restrict__ tile_cnt) {
+    const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
+    int64_t cell_tiles, float4 *__restrict__ sorted, uint64_t *__restrict__ keys,
+    uint64_t *__restrict__ key_out, float *__restrict__ pos_sorted,
+    float *__restrict__ mass_sorted, uint16_t *__restrict__ ad, uint32_t *__restrict__ tile_cnt,
+    int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const CellLds s = carve_lds(lds, nl, false);
+  const WindowLds s = carve_window(lds, nl);
   const int64_t tile = blockIdx.x;
   if (tile >= tile_start[nsets]) return;
   const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
+  const int64_t t0 = tr.t0, t1 = tr.t1;
+  const double lo0 = box[4 * tr.b + 0], lo1 = box[4 * tr.b + 1], lo2 = box[4 * tr.b + 2];
+  const double scale = 2097152.0 / box[4 * tr.b + 3];
+  const int T = (int)(t1 - t0);
+  const int64_t ws = t0 - nl - 1;  // window start (may be negative)
+  const int wn = T + 2 * nl + 1;
+  bool internal = false, bad = false;
+  constexpr int kBatch = 8;
+  for (int i0 = 0; i0 < wn; i0 += kBatch * kCellThreads) {
+    int32_t p[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int i = i0 + r * kCellThreads + threadIdx.x;
+      const int64_t g = ws + i;
+      const bool in = i < wn && g >= tr.S && g < tr.E;
+      p[r] = perm[in ? g : t0];
+    }
+    float4 rec[kBatch];
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int i = i0 + r * kCellThreads + threadIdx.x;
+      const int64_t g = ws + i;
+      const bool in = i < wn && g >= tr.S && g < tr.E;
+      const bool ok = p[r] >= 0 && p[r] < n;
+      internal |= in && !ok;
+      rec[r] = packed[ok ? p[r] : 0];
+    }
+#pragma unroll
+    for (int r = 0; r < kBatch; ++r) {
+      const int i = i0 + r * kCellThreads + threadIdx.x;
+      const int64_t g = ws + i;
+      const bool in = i < wn && g >= tr.S && g < tr.E;
+      const uint64_t key =
+          in ? morton_key(rec[r].x, rec[r].y, rec[r].z, lo0, lo1, lo2, scale) : 0ull;
+      if (i < wn) s.keys[i] = key;
+      if (g >= t0 && g < t1 && i < wn) {
+        sorted[g] = rec[r];
+        keys[g] = key;
+        if (key_out) key_out[g] = key;
+        bad |= !(rec[r].w > 0.0f && isfinite(rec[r].w));
+        if (pos_sorted) {
+          pos_sorted[3 * g + 0] = rec[r].x;
+          pos_sorted[3 * g + 1] = rec[r].y;
+          pos_sorted[3 * g + 2] = rec[r].z;
+        }
+        if (mass_sorted) mass_sorted[g] = rec[r].w;
+      }
+    }
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_MASS);
+  if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
+  __syncthreads();
+
   uint8_t A[kCellIpt], D[kCellIpt];
-  tile_depths(s, keys, tr.S, tr.E, nl, tr.t0, tr.t1, A, D);
+  depths_from_window(s, tr.S, tr.E, nl, t0, t1, A, D);
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) {
+    const int li = threadIdx.x * kCellIpt + j;
+    if (li < T) ad[t0 + li] = (uint16_t)(A[j] | (D[j] << 8));
+  }
   uint32_t c[kLevelWords], tot[kLevelWords];
   thread_level_counts(A, D, c);
-  block_level_scan(s, c, tot);
+  block_level_scan(s.wtot, c, tot);
   const int d = threadIdx.x;
   if (d < kLevels) {
     uint32_t cnt = 0;
@@ -415,72 +472,7 @@ __global__ __launch_bounds__(kSetScanThreads) void k_set_scan(
 }
 
 // ---------------------------------------------------------------------------
-// reorder pass (Sec. 2.3, step iii)
-// ---------------------------------------------------------------------------
-// sorted[s] = packed[perm[s]]: the particles in key order, one 16-byte record
-// each, and their keys recomputed from the gathered positions (the same FP64
-// arithmetic as the key pass, so the keys are identical).  One workgroup per
-// cell tile, so the whole tile shares one set and one root box.  Every thread
-// issues all of its index loads, then all of its gathers, so the random reads
-// overlap.  Also fills the optional pos_sorted / mass_sorted / key_sorted
-// outputs and checks the masses.
-constexpr int kReorderThreads = 256;
-constexpr int kReorderIpt = 8;
-static_assert(kReorderThreads * kReorderIpt == kCellTile, "reorder works on cell tiles");
-
-__global__ __launch_bounds__(kReorderThreads) void k_reorder(
-    const int32_t *__restrict__ perm, const float4 *__restrict__ packed, int64_t n,
-    const int64_t *__restrict__ tile_start, const int32_t *__restrict__ tile_set,
-    const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
-    float4 *__restrict__ sorted, uint64_t *__restrict__ keys, uint64_t *__restrict__ key_out,
-    float *__restrict__ pos_sorted, float *__restrict__ mass_sorted,
-    int32_t *__restrict__ status_word) {
-  const int64_t tile = blockIdx.x;
-  if (tile >= tile_start[nsets]) return;
-  const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
-  const double lo0 = box[4 * tr.b + 0], lo1 = box[4 * tr.b + 1], lo2 = box[4 * tr.b + 2];
-  const double scale = 2097152.0 / box[4 * tr.b + 3];
-  const int64_t base = tr.t0 + threadIdx.x;
-  int32_t p[kReorderIpt];
-#pragma unroll
-  for (int r = 0; r < kReorderIpt; ++r) {
-    const int64_t sp = base + r * kReorderThreads;
-    p[r] = perm[sp < tr.t1 ? sp : tr.t1 - 1];
-  }
-  // branch-free gathers (out-of-range indices are clamped and reported) so
-  // that all of them are in flight together
-  float4 rec[kReorderIpt];
-  bool internal = false, bad = false;
-#pragma unroll
-  for (int r = 0; r < kReorderIpt; ++r) {
-    const int64_t sp = base + r * kReorderThreads;
-    const bool ok = p[r] >= 0 && p[r] < n;
-    internal |= (sp < tr.t1) && !ok;
-    rec[r] = packed[ok ? p[r] : 0];
-  }
-#pragma unroll
-  for (int r = 0; r < kReorderIpt; ++r) {
-    const int64_t sp = base + r * kReorderThreads;
-    if (sp < tr.t1) {
-      sorted[sp] = rec[r];
-      const uint64_t key = morton_key(rec[r].x, rec[r].y, rec[r].z, lo0, lo1, lo2, scale);
-      keys[sp] = key;
-      if (key_out) key_out[sp] = key;
-      bad |= !(rec[r].w > 0.0f && isfinite(rec[r].w));
-      if (pos_sorted) {
-        pos_sorted[3 * sp + 0] = rec[r].x;
-        pos_sorted[3 * sp + 1] = rec[r].y;
-        pos_sorted[3 * sp + 2] = rec[r].z;
-      }
-      if (mass_sorted) mass_sorted[sp] = rec[r].w;
-    }
-  }
-  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_MASS);
-  if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
-}
-
-// ---------------------------------------------------------------------------
-// emit pass
+// leaf moments
 // ---------------------------------------------------------------------------
 
 // Inverse of the 3-way bit spread: gathers bits 0, 3, 6, ... into bits 0, 1, 2, ...
@@ -494,13 +486,15 @@ __device__ __forceinline__ uint32_t compact3(uint64_t v) {
   return (uint32_t)v;
 }
 
-// End (exclusive) of the leaf that starts at particle i with depth dl.
-__device__ inline int64_t leaf_end(const CellLds &s, const uint64_t *__restrict__ keys, int64_t n,
+
+// End (exclusive) of the leaf that starts at particle i with depth dl, from
+// the a_i of the particles after it (a: [t0, t1 + nl) relative to t0).
+__device__ inline int64_t leaf_end(const uint8_t *a, const uint64_t *__restrict__ keys, int64_t n,
                                    int nl, int64_t t0, int64_t i, int dl) {
   // n is the end of the particle's set
   const int64_t lim = min(n, i + nl + 1);
   for (int64_t j = i + 1; j < lim; ++j)
-    if (s.a[j - t0] <= dl) return j;
+    if (a[j - t0] <= dl) return j;
   if (lim == n) return n;
   // only a depth-21 leaf of identical keys can be longer than n_leaf
   const uint64_t k = keys[i];
@@ -520,7 +514,7 @@ __device__ inline int64_t leaf_end(const CellLds &s, const uint64_t *__restrict_
 // predecessor, so it starts no cell; the first particle past the leaf differs
 // from its predecessor at depth <= the leaf depth and starts its own leaf).
 // Only a leaf reaching past the tile falls back to the halo scan.
-__device__ inline int64_t leaf_end_fast(const CellLds &s, const uint64_t *__restrict__ keys,
+__device__ inline int64_t leaf_end_fast(const EmitLds &s, const uint64_t *__restrict__ keys,
                                         int64_t n, int nl, int64_t t0, int T, int li, int dl) {
   const uint64_t *hw = reinterpret_cast<const uint64_t *>(s.heads);
   const int nw = (T + 63) >> 6;
@@ -532,7 +526,7 @@ __device__ inline int64_t leaf_end_fast(const CellLds &s, const uint64_t *__rest
     const int p = (w << 6) + __ffsll((long long)bits) - 1;
     if (p < T) return t0 + p;
   }
-  return leaf_end(s, keys, n, nl, t0, t0 + li, dl);
+  return leaf_end(s.a, keys, n, nl, t0, t0 + li, dl);
 }
 
 // FP64 leaf moments in the leaf's frame: one pass of sums of m, m r and m r r
@@ -644,10 +638,16 @@ __device__ __forceinline__ void leaf_finish_f(const LeafSumsF &a, float com[4], 
   quad[5] = 3.0f * zz - tr;
 }
 
+
+// ---------------------------------------------------------------------------
+// emit pass
+// ---------------------------------------------------------------------------
+// One workgroup per cell tile: a_i and D_i (from the reorder pass) give every
+// cell whose first particle lies in the tile; the per-depth prefix places it.
 template <bool MIXED>
 __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
-    const uint64_t *__restrict__ keys, int nl, const uint32_t *__restrict__ excl,
-    int64_t cell_tiles, const int64_t *__restrict__ tile_start,
+    const uint64_t *__restrict__ keys, const uint16_t *__restrict__ ad, int nl,
+    const uint32_t *__restrict__ excl, int64_t cell_tiles, const int64_t *__restrict__ tile_start,
     const int32_t *__restrict__ tile_set, const int64_t *__restrict__ set_off, int32_t nsets,
     const int64_t *__restrict__ lvl_off, const double *__restrict__ box,
     const float4 *__restrict__ sorted, uint64_t *__restrict__ cell_key,
@@ -656,11 +656,12 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     void *__restrict__ quad_v, float *__restrict__ m_lo, int32_t *__restrict__ head_parent,
     int64_t c_max, int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const CellLds s = carve_lds(lds, nl, true);
+  const EmitLds s = carve_emit(lds, nl);
   const int64_t tile = blockIdx.x;
   if (tile >= tile_start[nsets]) return;
   const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
   const int64_t t0 = tr.t0, t1 = tr.t1, n = tr.E;  // n: end of this tile's set
+  const int T = (int)(t1 - t0);
 
   // per-depth base of this tile: the set's first cell of the depth plus the
   // cells of the set's earlier tiles
@@ -668,29 +669,49 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     const int d = threadIdx.x;
     s.lvl[d] = (uint32_t)(lvl_off[tr.b * (kLevels + 1) + d] + excl[d * cell_tiles + tile]);
   }
-  // the tile's particles in key order plus the n_leaf halo, one batched load
+  if (threadIdx.x == 0) *s.nleaf = 0;
+  if (threadIdx.x < kLenClasses) s.bucket[threadIdx.x] = 0;
+  // the tile's particles in key order plus the n_leaf halo, and their (a, D),
+  // in batched loads
   const int span = (int)(min(t1 + (int64_t)nl, n) - t0);
   {
     constexpr int kRecBatch = (kCellTile + 32 + kCellThreads - 1) / kCellThreads;
     for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
       float4 r[kRecBatch];
+      uint16_t v[kRecBatch];
 #pragma unroll
       for (int u = 0; u < kRecBatch; ++u) {
         const int x = x0 + u * kCellThreads + threadIdx.x;
-        r[u] = sorted[t0 + (x < span ? x : span - 1)];
+        const int xc = x < span ? x : span - 1;
+        r[u] = sorted[t0 + xc];
+        v[u] = ad[t0 + xc];
       }
 #pragma unroll
       for (int u = 0; u < kRecBatch; ++u) {
         const int x = x0 + u * kCellThreads + threadIdx.x;
-        if (x < span) s.rec[x] = r[u];
+        if (x < span) {
+          s.rec[x] = r[u];
+          s.a[x] = (uint8_t)(v[u] & 0xff);
+          if (x < T) s.d[x] = (uint8_t)(v[u] >> 8);
+        }
       }
     }
   }
-  if (threadIdx.x == 0) *s.nleaf = 0;
-  if (threadIdx.x < kLenClasses) s.bucket[threadIdx.x] = 0;
-
+  // this thread's particles t0 + 8t .. t0 + 8t + 7: their keys
+  uint64_t kk[kCellIpt];
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) {
+    const int li = threadIdx.x * kCellIpt + j;
+    kk[j] = keys[t0 + (li < T ? li : T - 1)];
+  }
+  __syncthreads();
   uint8_t A[kCellIpt], D[kCellIpt];
-  tile_depths(s, keys, tr.S, tr.E, nl, t0, t1, A, D);  // its barriers also publish s.lvl, s.rec
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) {
+    const int li = threadIdx.x * kCellIpt + j;
+    A[j] = li < T ? s.a[li] : 23;  // 23: starts no cell
+    D[j] = li < T ? s.d[li] : 0;
+  }
   {
     uint32_t hb = 0;
 #pragma unroll
@@ -699,7 +720,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   }
   uint32_t c[kLevelWords], tot[kLevelWords];
   thread_level_counts(A, D, c);
-  block_level_scan(s, c, tot);  // its barriers also publish s.heads
+  block_level_scan(s.wtot, c, tot);  // its barrier also publishes s.heads
 #pragma unroll
   for (int d = 0; d < kLevels; ++d) s.off[d * kCellThreads + threadIdx.x] = (uint16_t)unpack(c, d);
   // this thread's leaves go to a contiguous run of the leaf list
@@ -719,7 +740,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     if (a > dl) continue;
     const int li = threadIdx.x * kCellIpt + j;
     const int64_t i = t0 + li;
-    const uint64_t key = s.keys[li + nl + 1];
+    const uint64_t key = kk[j];
     for (int d = a; d <= dl; ++d) {
       const uint32_t rel = s.off[d * kCellThreads + threadIdx.x];
       s.off[d * kCellThreads + threadIdx.x] = (uint16_t)(rel + 1);
@@ -751,7 +772,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
     const uint32_t e = s.leaf[x];
     const int li = e & 0x7ff, dl = (e >> 11) & 31;
-    const int64_t len = leaf_end_fast(s, keys, n, nl, t0, (int)(t1 - t0), li, dl) - (t0 + li);
+    const int64_t len = leaf_end_fast(s, keys, n, nl, t0, T, li, dl) - (t0 + li);
     s.leaf_len[x] = (uint16_t)min(len, (int64_t)65535);
     atomicAdd(&s.bucket[kLenClasses - 1 - (int)min(len, (int64_t)kLenClasses - 1)], 1u);
   }
@@ -778,8 +799,9 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     const int dl = (le >> 11) & 31;
     const uint32_t ci = s.lvl[dl] + (le >> 16);
     const int64_t i = t0 + li;
-    const uint64_t key = s.keys[li + nl + 1];
-    const int64_t e = s.leaf_len[x] < 65535 ? i + s.leaf_len[x] : leaf_end(s, keys, n, nl, t0, i, dl);
+    const uint64_t key = keys[i];
+    const int64_t e =
+        s.leaf_len[x] < 65535 ? i + s.leaf_len[x] : leaf_end(s.a, keys, n, nl, t0, i, dl);
     cell_count[ci] = (int32_t)(e - i);
     const int sh = kMaxDepth - dl;
     const uint32_t ijk[3] = {compact3(key >> 2) >> sh, compact3(key >> 1) >> sh, compact3(key) >> sh};
@@ -830,14 +852,6 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
-hipError_t launch_cell_count(const Plan &p, const Work &w, hipStream_t s) {
-  const size_t lds = cell_lds_bytes(p.n_leaf, false);
-  k_cell_count<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
-      sorted_keys(p, w), p.n_leaf, p.cell_tiles, w.tile_start, w.tile_set, w.set_off, p.nsets,
-      w.cell_cnt);
-  return hipGetLastError();
-}
-
 hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
                             int64_t *cell_offsets, hipStream_t s) {
   const int gy = p.nsets < 65535 ? p.nsets : 65535;
@@ -854,9 +868,10 @@ hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
 }
 
 hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
-  k_reorder<<<(unsigned)p.cell_tiles, kReorderThreads, 0, s>>>(
-      out.perm, w.packed, p.n, w.tile_start, w.tile_set, w.set_off, p.nsets, w.box, w.sorted,
-      sorted_keys(p, w), out.key_sorted, out.pos_sorted, out.mass_sorted, out.status);
+  k_reorder<<<(unsigned)p.cell_tiles, kCellThreads, window_lds_bytes(p.n_leaf), s>>>(
+      out.perm, w.packed, p.n, p.n_leaf, w.tile_start, w.tile_set, w.set_off, p.nsets, w.box,
+      p.cell_tiles, w.sorted, sorted_keys(p, w), out.key_sorted, out.pos_sorted, out.mass_sorted,
+      w.ad, w.cell_cnt, out.status);
   return hipGetLastError();
 }
 
@@ -870,13 +885,13 @@ size_t cell_lds_limit() {
   if (dev != cached_dev) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
-    const int want = (int)cell_lds_bytes(TB_MAX_NLEAF, true);
+    const int want = (int)cell_emit_lds(TB_MAX_NLEAF);
     const int opt = v < want ? v : want;
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit<false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, opt);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, opt);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_count),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_reorder),
                               hipFuncAttributeMaxDynamicSharedMemorySize, opt);
     cached = (size_t)v;
     cached_dev = dev;
@@ -885,16 +900,20 @@ size_t cell_lds_limit() {
 }
 
 hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
-  const size_t lds = cell_lds_bytes(p.n_leaf, true);
+  const size_t lds = emit_lds_bytes(p.n_leaf);
   auto k = (p.flags & 0xffu) == TB_MIXED ? k_cell_emit<true> : k_cell_emit<false>;
   k<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
-      sorted_keys(p, w), p.n_leaf, w.cell_excl, p.cell_tiles, w.tile_start, w.tile_set,
+      sorted_keys(p, w), w.ad, p.n_leaf, w.cell_excl, p.cell_tiles, w.tile_start, w.tile_set,
       w.set_off, p.nsets, w.lvl_off, w.box, w.sorted, out.cell_key, out.cell_level,
       out.cell_first, out.cell_count, out.child_ptr, out.com, out.quad, w.m_lo, w.head_parent,
       p.c_max, out.status);
   return hipGetLastError();
 }
 
-size_t cell_emit_lds(int nl) { return cell_lds_bytes(nl, true); }
+// The larger of the two cell kernels' LDS needs for this n_leaf.
+size_t cell_emit_lds(int nl) {
+  const size_t a = emit_lds_bytes(nl), b = window_lds_bytes(nl);
+  return a > b ? a : b;
+}
 
 }  // namespace tb

@@ -89,6 +89,7 @@ struct Plan {
   size_t par_start;     // i64 [kLevels][B + 1] parent-pass chunks per depth and set
   size_t packed;        // f32x4 [n] (x, y, z, m) records in original order
   size_t sorted;        // f32x4 [n] the same records in key order
+  size_t ad;            // u16 [n] a_i | D_i << 8 of every particle in key order
   size_t head_parent;   // i32 [c_max] parent slot of every first child
   size_t m_lo;          // f32 [c_max] compensation of each cell mass (mixed precision)
   size_t total;
@@ -120,6 +121,7 @@ struct Work {
   int64_t *par_start;
   float4 *packed;
   float4 *sorted;
+  uint16_t *ad;
   int32_t *head_parent;
   float *m_lo;
 };
@@ -154,7 +156,6 @@ hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tre
                             hipStream_t s);
 bool sort_config_supported(const SortConfig &c);
 // tb_cells.hip
-hipError_t launch_cell_count(const Plan &p, const Work &w, hipStream_t s);
 hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
                             int64_t *cell_offsets, hipStream_t s);
 hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
