@@ -15,8 +15,8 @@ namespace tb {
 
 // Table of sort shapes selectable through TB_SORT_CONFIG(k); entry 0 is the default.
 static const SortConfig kSortTable[] = {
-    {8, 12, 512}, {8, 16, 256}, {9, 16, 256}, {8, 12, 256},
-    {9, 12, 256}, {8, 8, 256},  {8, 8, 512},
+    {8, 11, 512}, {8, 12, 512}, {8, 10, 512}, {8, 16, 256},
+    {9, 16, 256}, {8, 12, 256}, {8, 8, 512},
 };
 static const int kSortTableSize = (int)(sizeof(kSortTable) / sizeof(kSortTable[0]));
 

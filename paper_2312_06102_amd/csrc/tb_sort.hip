@@ -227,7 +227,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
       uint32_t excl = 0;
       if (tile > 0) {
         bool timed_out = false;
-        excl = lookback<4>(status, R, tile, d, timed_out);
+        excl = lookback<2>(status, R, tile, d, timed_out);
         if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
         atomic_store_agent(&status[(size_t)tile * R + d],
                            kFlagInclusive | (uint64_t)(excl + tcnt[t]));
@@ -342,20 +342,20 @@ hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tre
 #define TB_SORT_CASE(B, I, T)                                         \
   if (c.bits == B && c.ipt == I && c.threads == T)                    \
     return launch_pass_t<B, I, T>(p, w, pass, out, s);
+  TB_SORT_CASE(8, 11, 512)
+  TB_SORT_CASE(8, 12, 512)
+  TB_SORT_CASE(8, 10, 512)
   TB_SORT_CASE(8, 16, 256)
   TB_SORT_CASE(9, 16, 256)
   TB_SORT_CASE(8, 12, 256)
-  TB_SORT_CASE(9, 12, 256)
   TB_SORT_CASE(8, 8, 512)
-  TB_SORT_CASE(8, 8, 256)
-  TB_SORT_CASE(8, 12, 512)
 #undef TB_SORT_CASE
   return hipErrorInvalidValue;
 }
 
 bool sort_config_supported(const SortConfig &c) {
-  static const int table[][3] = {{8, 16, 256}, {9, 16, 256}, {8, 12, 256}, {9, 12, 256},
-                                 {8, 8, 512},  {8, 8, 256},  {8, 12, 512}};
+  static const int table[][3] = {{8, 11, 512}, {8, 12, 512}, {8, 10, 512}, {8, 16, 256},
+                                 {9, 16, 256}, {8, 12, 256}, {8, 8, 512}};
   for (const auto &r : table)
     if (r[0] == c.bits && r[1] == c.ipt && r[2] == c.threads) return true;
   return false;

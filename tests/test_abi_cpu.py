@@ -67,7 +67,7 @@ def test_workspace_bytes_grows_with_n():
 
 def test_sort_config_table():
     cfgs = tb.tb_sort_configs()
-    assert cfgs[0] == (8, 12, 512)
+    assert cfgs[0] == (8, 11, 512)
     for k, (bits, ipt, threads) in enumerate(cfgs):
         assert 8 <= bits <= 9 and threads % 64 == 0
         assert tb.tb_workspace_bytes(4096, 16, tb.TB_SORT_CONFIG(k)) > 0
