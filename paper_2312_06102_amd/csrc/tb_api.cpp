@@ -41,6 +41,8 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->key_passes = sc.passes();
   p->set_passes = 0;  // digits of the set id: 0 for a single set
   for (int64_t span = 1; span < nsets; span <<= sc.bits) ++p->set_passes;
+  p->coarse_shift = 0;
+  while (((n + (int64_t(1) << p->coarse_shift) - 1) >> p->coarse_shift) > kCoarse) ++p->coarse_shift;
   p->sort_tiles = (n + sc.tile() - 1) / sc.tile();
   // tiles never straddle two sets: at most one partial tile per set
   p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;
@@ -77,6 +79,7 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->set_cells = take(8 * B1);
   p->lvl_off = take(8 * (size_t)nsets * (kLevels + 1));
   p->par_start = take(8 * (size_t)kLevels * B1);
+  p->coarse = take(4 * (size_t)(kCoarse + 1));
   p->packed = take(16 * (size_t)n);
   p->sorted = take(16 * (size_t)n);
   p->ad = take(2 * (size_t)n);
@@ -110,6 +113,7 @@ Work carve(const Plan &p, void *base) {
   w.set_cells = reinterpret_cast<int64_t *>(b + p.set_cells);
   w.lvl_off = reinterpret_cast<int64_t *>(b + p.lvl_off);
   w.par_start = reinterpret_cast<int64_t *>(b + p.par_start);
+  w.coarse = reinterpret_cast<uint32_t *>(b + p.coarse);
   w.packed = reinterpret_cast<float4 *>(b + p.packed);
   w.sorted = reinterpret_cast<float4 *>(b + p.sorted);
   w.ad = reinterpret_cast<uint16_t *>(b + p.ad);

@@ -389,26 +389,25 @@ __global__ __launch_bounds__(THREADS) void k_cell_scan(
   }
 }
 
-// One workgroup over all sets, 1024 sets per round and every row of a round at
-// once: the first cell of every set and of every depth of every set, the
+// One workgroup over all sets, THREADS sets per round and every row of a round
+// at once: the first cell of every set and of every depth of every set, the
 // outputs level_offset [B][23], cell_offsets [B+1] and n_cells, the
-// parent-pass chunk tables, and the boxes used.
-constexpr int kSetScanThreads = 1024;
-constexpr int kSetScanWaves = kSetScanThreads / 64;
-
-__global__ __launch_bounds__(kSetScanThreads) void k_set_scan(
+// parent-pass chunk tables, and the boxes used.  Up to 64 sets take one wave.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_set_scan(
     const uint32_t *__restrict__ set_tot, int32_t nsets, int64_t *__restrict__ set_cells,
     int64_t *__restrict__ lvl_off, int64_t *__restrict__ level_offset,
     int64_t *__restrict__ cell_offsets, int64_t *__restrict__ n_cells,
     int64_t *__restrict__ par_start, const double *__restrict__ box,
     double *__restrict__ box_out) {
+  constexpr int kSetScanWaves = THREADS / 64;
   // rows: 0 = cells per set, r = 1..21 = parent chunks at depth r - 1 (children at depth r)
   __shared__ uint32_t s_w[kLevels][kSetScanWaves];
   __shared__ int64_t s_carry[kLevels];
   const int wv = threadIdx.x / 64;
   if (threadIdx.x < kLevels) s_carry[threadIdx.x] = 0;
   __syncthreads();
-  for (int r0 = 0; r0 < nsets; r0 += kSetScanThreads) {
+  for (int r0 = 0; r0 < nsets; r0 += THREADS) {
     const int b = r0 + threadIdx.x;
     uint32_t t[kLevels];
 #pragma unroll
@@ -713,6 +712,9 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     D[j] = li < T ? s.d[li] : 0;
   }
   {
+    // the head mask holds one byte per thread: bit j of byte t is particle 8t + j
+    static_assert(kCellIpt == 8 && kCellThreads * kCellIpt == kCellTile,
+                  "the head mask layout needs 8 particles per thread");
     uint32_t hb = 0;
 #pragma unroll
     for (int j = 0; j < kCellIpt; ++j) hb |= (A[j] <= D[j] ? 1u : 0u) << j;
@@ -797,7 +799,15 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     const uint32_t le = s.leaf[x];
     const int li = le & 0x7ff;
     const int dl = (le >> 11) & 31;
+    if (dl > kMaxDepth || li >= T) {  // cannot happen: entries come from the loop above
+      internal = true;
+      continue;
+    }
     const uint32_t ci = s.lvl[dl] + (le >> 16);
+    if ((int64_t)ci >= c_max) {
+      internal = true;
+      continue;
+    }
     const int64_t i = t0 + li;
     const uint64_t key = keys[i];
     const int64_t e =
@@ -861,9 +871,13 @@ hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
   else
     k_cell_scan<256><<<dim3(kLevels, gy), 256, 0, s>>>(w.cell_cnt, p.cell_tiles, w.tile_start,
                                                       p.nsets, w.cell_excl, w.set_tot);
-  k_set_scan<<<1, kSetScanThreads, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
-                                           out.level_offset, cell_offsets, out.n_cells,
-                                           w.par_start, w.box, out.box_out);
+  if (p.nsets <= 64)
+    k_set_scan<64><<<1, 64, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off, out.level_offset,
+                                    cell_offsets, out.n_cells, w.par_start, w.box, out.box_out);
+  else
+    k_set_scan<1024><<<1, 1024, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
+                                        out.level_offset, cell_offsets, out.n_cells, w.par_start,
+                                        w.box, out.box_out);
   return hipGetLastError();
 }
 

@@ -37,6 +37,9 @@ constexpr int kBboxChunk = 65536;
 
 // Sets whose offsets fit the LDS table of the set-id radix passes.
 constexpr int kMaxSetsLds = TB_MAX_SETS;
+// Coarse set table of the set-id passes: the set holding every 2^shift-th
+// position, at most kCoarse + 1 entries.
+constexpr int kCoarse = 4096;
 
 // Lookback status word: flag in bits 63:62, value in bits 31:0.
 constexpr uint64_t kFlagAggregate = 1ull << 62;
@@ -62,7 +65,8 @@ struct Plan {
   int32_t nsets;    // B
   SortConfig sort;
   int key_passes;   // radix passes over the 63 key bits
-  int set_passes;   // 8-bit radix passes over the set id (0 when B == 1)
+  int set_passes;   // radix passes over the set id (0 when B == 1)
+  int coarse_shift; // position >> coarse_shift indexes the coarse set table
   int64_t sort_tiles;
   int64_t cell_tiles;   // upper bound of the cell tiles of all sets
   int64_t bbox_chunks;  // upper bound of the bounding-box chunks of all sets
@@ -87,6 +91,7 @@ struct Plan {
   size_t set_cells;     // i64 [B + 1] first cell of each set; [B] = all cells
   size_t lvl_off;       // i64 [B][kLevels + 1] first cell of each depth of each set
   size_t par_start;     // i64 [kLevels][B + 1] parent-pass chunks per depth and set
+  size_t coarse;        // u32 [kCoarse + 1] set holding position k << coarse_shift
   size_t packed;        // f32x4 [n] (x, y, z, m) records in original order
   size_t sorted;        // f32x4 [n] the same records in key order
   size_t ad;            // u16 [n] a_i | D_i << 8 of every particle in key order
@@ -119,6 +124,7 @@ struct Work {
   int64_t *set_cells;
   int64_t *lvl_off;
   int64_t *par_start;
+  uint32_t *coarse;
   float4 *packed;
   float4 *sorted;
   uint16_t *ad;
@@ -288,6 +294,20 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
     if (l >= o) v += t;
   }
   return v;
+}
+
+// Index b of the last entry of the sorted table tab[lo..hi] with tab[b] <= x,
+// given tab[lo] <= x.
+template <typename T>
+__device__ __forceinline__ int upper_index_in(const T *tab, int lo, int hi, int64_t x) {
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)tab[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 // Index b of the last entry of the sorted table tab[0..count) with tab[b] <= x

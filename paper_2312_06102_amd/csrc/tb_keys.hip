@@ -116,8 +116,8 @@ __device__ __forceinline__ bool box_valid(const double *b) {
 __global__ __launch_bounds__(kSetupThreads) void k_setup(
     int64_t *__restrict__ set_off, int32_t nsets, int64_t n, int64_t *__restrict__ tile_start,
     int64_t *__restrict__ chunk_start, uint32_t *__restrict__ set_hist, int set_passes, int bits,
-    int with_chunks, double *__restrict__ box, int check_boxes,
-    int32_t *__restrict__ status_word) {
+    int with_chunks, double *__restrict__ box, int check_boxes, uint32_t *__restrict__ coarse,
+    int coarse_shift, int32_t *__restrict__ status_word) {
   __shared__ uint32_t s_w[2][kSetupThreads / 64];
   __shared__ uint64_t s_carry[2];
   __shared__ int s_bad;
@@ -149,6 +149,14 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(
   __syncthreads();
   // digit counts of the set-id passes: set b contributes its size to digit k of b
   for (int i = threadIdx.x; i < set_passes * R; i += kSetupThreads) set_hist[i] = 0;
+  // coarse table of the set-id passes: the set holding position k << shift
+  if (set_passes > 0 && n > 0) {
+    const int64_t K = ((n - 1) >> coarse_shift) + 1;
+    for (int64_t k = threadIdx.x; k <= K; k += kSetupThreads) {
+      const int64_t pos = min(k << coarse_shift, n - 1);
+      coarse[k] = (uint32_t)upper_index(set_off, nsets + 1, pos);
+    }
+  }
   __syncthreads();
   for (int b = threadIdx.x; b < nsets; b += kSetupThreads) {
     const uint32_t nb = (uint32_t)(set_off[b + 1] - set_off[b]);
@@ -225,7 +233,7 @@ hipError_t launch_setup(const Plan &p, const Work &w, const BatchIn &in, int32_t
   k_setup<<<1, kSetupThreads, 0, s>>>(w.set_off, p.nsets, p.n, w.tile_start, w.chunk_start,
                                       w.hist + (size_t)p.key_passes * p.sort.radix(),
                                       p.set_passes, p.sort.bits, with_chunks ? 1 : 0, w.box,
-                                      in.dev_boxes ? 1 : 0, status);
+                                      in.dev_boxes ? 1 : 0, w.coarse, p.coarse_shift, status);
   const int64_t entries = p.cell_tiles + (with_chunks ? p.bbox_chunks : 0);
   k_tile_map<<<(unsigned)((entries + 255) / 256), 256, 0, s>>>(
       w.tile_start, w.tile_set, p.cell_tiles, w.chunk_start, w.chunk_set, p.bbox_chunks,

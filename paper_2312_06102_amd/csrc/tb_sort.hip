@@ -83,7 +83,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
     int32_t *__restrict__ status_word, uint32_t n_tiles, const int64_t *__restrict__ set_off,
-    int32_t nsets) {
+    int32_t nsets, const uint32_t *__restrict__ coarse, int coarse_shift) {
   constexpr bool SETID = KIN == kKeyNone;
   using KI = typename KeyType<KIN == kKeyNone ? kKey32 : KIN>::T;
   using KO = typename KeyType<KOUT == kKeyNone ? kKey32 : KOUT>::T;
@@ -102,15 +102,23 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   __shared__ int32_t s_goff[R];            // global position minus tile-local position
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
-  extern __shared__ uint32_t s_soff[];  // SETID: [nsets + 1] set offsets
+  // SETID: [nsets + 1] set offsets, then the coarse table [K + 1]
+  extern __shared__ uint32_t s_soff[];
   const KI *__restrict__ kin = static_cast<const KI *>(kin_v);
   KO *__restrict__ kout = static_cast<KO *>(kout_v);
+  const int ncoarse = (int)(((int64_t)n - 1) >> coarse_shift) + 1;  // K
+  uint32_t *s_coarse = s_soff + nsets + 1;
   if constexpr (SETID) {
     for (int i = threadIdx.x; i <= nsets; i += THREADS) s_soff[i] = (uint32_t)set_off[i];
+    for (int i = threadIdx.x; i <= ncoarse; i += THREADS) s_coarse[i] = coarse[i];
   }
   auto digit = [&](KI kk, uint32_t vv) -> uint32_t {
     if constexpr (SETID) {
-      return ((uint32_t)upper_index(s_soff, nsets + 1, (int64_t)vv) >> shift) & ((1u << BITS) - 1u);
+      // the set holding original position vv lies between the sets holding the
+      // coarse positions around it
+      const int k = (int)(vv >> coarse_shift);
+      const int b = upper_index_in(s_soff, (int)s_coarse[k], (int)s_coarse[k + 1], (int64_t)vv);
+      return ((uint32_t)b >> shift) & ((1u << BITS) - 1u);
     } else {
       return digit_of<BITS>(kk, shift);
     }
@@ -311,11 +319,12 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
     shift = (pass - p.key_passes) * BITS;  // set-id digit
   else
     shift = pass * BITS - (KIN == kKey32 ? 32 : 0);
-  const size_t lds = KIN == kKeyNone ? 4 * (size_t)(p.nsets + 1) : 0;
+  const int64_t ncoarse = ((p.n - 1) >> p.coarse_shift) + 1;
+  const size_t lds = KIN == kKeyNone ? 4 * (size_t)(p.nsets + 1 + ncoarse + 1) : 0;
   k_onesweep<BITS, IPT, THREADS, KIN, KOUT><<<(unsigned)p.sort_tiles, THREADS, lds, s>>>(
       K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift,
       w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, out.status,
-      (uint32_t)p.sort_tiles, w.set_off, p.nsets);
+      (uint32_t)p.sort_tiles, w.set_off, p.nsets, w.coarse, p.coarse_shift);
   return hipGetLastError();
 }
 
