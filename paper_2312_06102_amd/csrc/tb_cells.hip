@@ -274,7 +274,9 @@ __global__ __launch_bounds__(kCellThreads) void k_reorder(
   const int64_t ws = t0 - nl - 1;  // window start (may be negative)
   const int wn = T + 2 * nl + 1;
   bool internal = false, bad = false;
-  constexpr int kBatch = 8;
+  // 9 items per thread cover the tile and its halo in one round trip for
+  // n_leaf <= 127
+  constexpr int kBatch = kCellIpt + 1;
   for (int i0 = 0; i0 < wn; i0 += kBatch * kCellThreads) {
     int32_t p[kBatch];
 #pragma unroll
@@ -670,6 +672,14 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   }
   if (threadIdx.x == 0) *s.nleaf = 0;
   if (threadIdx.x < kLenClasses) s.bucket[threadIdx.x] = 0;
+  // this thread's particles t0 + 8t .. t0 + 8t + 7: their keys (issued first,
+  // so that they travel with the batched loads below)
+  uint64_t kk[kCellIpt];
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) {
+    const int li = threadIdx.x * kCellIpt + j;
+    kk[j] = keys[t0 + (li < T ? li : T - 1)];
+  }
   // the tile's particles in key order plus the n_leaf halo, and their (a, D),
   // in batched loads
   const int span = (int)(min(t1 + (int64_t)nl, n) - t0);
@@ -695,13 +705,6 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
         }
       }
     }
-  }
-  // this thread's particles t0 + 8t .. t0 + 8t + 7: their keys
-  uint64_t kk[kCellIpt];
-#pragma unroll
-  for (int j = 0; j < kCellIpt; ++j) {
-    const int li = threadIdx.x * kCellIpt + j;
-    kk[j] = keys[t0 + (li < T ? li : T - 1)];
   }
   __syncthreads();
   uint8_t A[kCellIpt], D[kCellIpt];

@@ -35,9 +35,9 @@ def test_paper_min_depth_example():
     ka = int(a, 2) << (64 - len(a))
     kb = int(b, 2) << (64 - len(b))
     assert tc.min_depth(ka, kb) == int(md)
-    assert tc.extract_cell_key(ka, 1) == int(ca, 2)
-    assert tc.extract_cell_key(kb, 1) == int(cb, 2)
-    assert tc.extract_cell_key(ka, 0) == tc.extract_cell_key(kb, 0) == 1
+    assert tc.prefix_key(ka, 1) == int(ca, 2)
+    assert tc.prefix_key(kb, 1) == int(cb, 2)
+    assert tc.prefix_key(ka, 0) == tc.prefix_key(kb, 0) == 1
     # Points in those depth-1 octants (x lower, y upper, z lower / upper) give
     # oracle keys with those prefixes and, with n_leaf = 1, two depth-1 leaves.
     pos = np.array([[0.2, 0.6, 0.3], [0.2, 0.6, 0.7]], dtype=np.float32)
@@ -123,7 +123,8 @@ def test_oracle_equals_set_definition(name, pos, n_leaf):
 
 @pytest.mark.parametrize("seed", range(40))
 def test_oracle_equals_paper_algorithms(seed):
-    """Leaves from Algorithm 1 and parents from Algorithm 2 equal the oracle."""
+    """Leaves and parents built the leaf-first way (Sec. 2.3.1-2.3.2, Algorithms
+    1-2) equal the oracle's top-down tree."""
     rng = _rng(100 + seed)
     n = int(rng.integers(1, 200))
     n_leaf = int(rng.integers(1, 20))
@@ -144,8 +145,8 @@ def test_oracle_equals_paper_algorithms(seed):
     t = oracle.build(pos, mass, n_leaf, moments=False)
     _, keys = oracle.keys(pos)
     sk = keys[t["perm"]]
-    leaves = tc.paper_leaves(sk, n_leaf)
-    cells = tc.paper_parents(leaves)
+    leaves = tc.leaves_from_sorted_keys(sk, n_leaf)
+    cells = tc.parents_bottom_up(leaves)
     assert len(cells) == t["n_cells"]
     for c in range(t["n_cells"]):
         d, k = int(t["cell_level"][c]), int(t["cell_key"][c])

@@ -8,9 +8,10 @@ its result a different way from the oracle's top-down insertion:
   [i, i+1) x [j, j+1) x [k, k+1) scaled by side/2^d, it exists when its parent
   holds more than n_leaf particles, and its key is built by appending the
   3-bit octant to the parent key (Sec. 2.2).
-* ``paper_leaves`` / ``paper_parents`` -- a literal reading of Algorithm 1
-  (leaves straight from sorted keys with the leaf-depth formula proved in
-  Appendix A) and Algorithm 2 (parents per depth by the two-list merge).
+* ``leaves_from_sorted_keys`` / ``parents_bottom_up`` -- the leaf-first method
+  as the text of Sec. 2.3.1 and 2.3.2 describes it, written sequentially:
+  leaves one after another from sorted keys with the leaf-depth formula proved
+  in Appendix A, then parents one depth at a time from runs of equal key >> 3.
 * ``exact_moments`` -- monopole, centre of mass and traceless quadrupole of a
   particle set in exact rational arithmetic (fractions.Fraction).
 * ``check_invariants`` -- structural properties every correct tree has.
@@ -100,79 +101,62 @@ def min_depth(ki: int, kj: int) -> int:
     return -(-z // 3)
 
 
-def extract_cell_key(key: int, d: int) -> int:
-    """Upper 3d+1 bits of a 64-bit key."""
+def prefix_key(key: int, d: int) -> int:
+    """Key of the depth-d cell holding a particle: the upper 3d+1 bits (Sec. 2.3.1)."""
     return int(key) >> (64 - (3 * d + 1))
 
 
-def paper_leaves(sorted_keys, n_leaf: int):
-    """Algorithm 1 on sorted keys.  Returns [(depth, leaf_key, first, count)] in
-    creation order.  The leaf depth is capped at 21 (key resolution)."""
-    keys = [int(k) for k in sorted_keys]
+def leaves_from_sorted_keys(sorted_keys, n_leaf: int):
+    """Leaves read off sorted keys as Sec. 2.3.1 describes them, one leaf after
+    another: the first particle of a leaf fixes the leaf depth as the larger of
+    its minimum distinguished depth to the previous particle and to the particle
+    n_leaf places further on (either missing at the ends counts as 0; depth
+    capped at the 21-bit key resolution), and the leaf takes every following
+    particle whose key has the same prefix at that depth.
+    Returns [(depth, key, first, count)] in key order."""
+    keys = [int(x) for x in sorted_keys]
     n = len(keys)
-    leaves = []
-    k = 0
-    while k < n:
-        d = 0
-        if k > 0:
-            d = min_depth(keys[k - 1], keys[k])
-        if k + n_leaf < n:
-            d = max(d, min_depth(keys[k], keys[k + n_leaf]))
-        d = min(d, MAX_DEPTH)
-        leaf_key = extract_cell_key(keys[k], d)
-        first = k
-        while k < n and extract_cell_key(keys[k], d) == leaf_key:
-            k += 1
-        leaves.append((d, leaf_key, first, k - first))
-    return leaves
+    out = []
+    start = 0
+    while start < n:
+        left = min_depth(keys[start - 1], keys[start]) if start > 0 else 0
+        right = min_depth(keys[start], keys[start + n_leaf]) if start + n_leaf < n else 0
+        depth = min(max(left, right), MAX_DEPTH)
+        prefix = prefix_key(keys[start], depth)
+        stop = start + 1
+        while stop < n and prefix_key(keys[stop], depth) == prefix:
+            stop += 1
+        out.append((depth, prefix, start, stop - start))
+        start = stop
+    return out
 
 
-def paper_parents(leaves):
-    """Algorithm 2 applied from the deepest depth upwards.
-
-    Returns dict (depth, key) -> dict(first, count, children=[keys], leaf=bool)."""
+def parents_bottom_up(leaves):
+    """All cells from the leaves, one depth at a time from the deepest, as
+    Sec. 2.3.2 describes it: the cells of a depth (its leaves and the parents
+    made one step earlier) in key order fall into runs sharing key >> 3; every
+    run becomes one parent one depth up, with the run as its children.
+    Returns {(depth, key): dict(first, count, children=[keys], leaf)}."""
     cells = {}
-    leaf_keys = {}
+    at_depth = {}
     for d, key, first, count in leaves:
         cells[(d, key)] = dict(first=first, count=count, children=[], leaf=True)
-        leaf_keys.setdefault(d, []).append(key)
-    inner_keys = {}
-    max_d = max((d for d, *_ in leaves), default=0)
-    for d in range(max_d, 0, -1):
-        lk = leaf_keys.get(d, [])
-        ik = inner_keys.get(d, [])
-        i = j = 0
-        last_parent = 0  # keys are >= 1, so 0 never matches
-        parents = []
-
-        def construct_parent(ck):
-            nonlocal last_parent
-            pk = ck >> 3
-            if pk != last_parent:
-                cells[(d - 1, pk)] = dict(first=None, count=0, children=[], leaf=False)
-                parents.append(pk)
-                last_parent = pk
-            par = cells[(d - 1, pk)]
-            ch = cells[(d, ck)]
-            par["children"].append(ck)
-            par["count"] += ch["count"]
-            if par["first"] is None:
-                par["first"] = ch["first"]
-
-        while i < len(lk) and j < len(ik):
-            if lk[i] < ik[j]:
-                construct_parent(lk[i])
-                i += 1
-            else:
-                construct_parent(ik[j])
-                j += 1
-        while i < len(lk):
-            construct_parent(lk[i])
-            i += 1
-        while j < len(ik):
-            construct_parent(ik[j])
-            j += 1
-        inner_keys[d - 1] = parents
+        at_depth.setdefault(d, []).append(key)
+    deepest = max((d for d, *_ in leaves), default=0)
+    for d in range(deepest, 0, -1):
+        run_key, run = None, []
+        for key in sorted(at_depth.get(d, [])) + [None]:
+            up = None if key is None else key >> 3
+            if run and up != run_key:
+                kids = [cells[(d, k)] for k in run]
+                cells[(d - 1, run_key)] = dict(first=min(c["first"] for c in kids),
+                                               count=sum(c["count"] for c in kids),
+                                               children=list(run), leaf=False)
+                at_depth.setdefault(d - 1, []).append(run_key)
+                run = []
+            run_key = up
+            if key is not None:
+                run.append(key)
     return cells
 
 
