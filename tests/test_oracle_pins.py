@@ -3,7 +3,7 @@
 * the paper's worked example of the minimum distinguished depth (Sec. 2.3.1);
 * Morton keys derived by hand from the key definition (Sec. 2.2);
 * the set-definition tree in exact rational geometry (Sec. 2.1);
-* a literal reading of Algorithms 1 and 2 (Sec. 2.3.1-2.3.2, Appendix A);
+* the leaf-first method written sequentially from Sec. 2.3.1-2.3.2 (Appendix A);
 * closed forms: complete lattices, coincident points, tiny sets;
 * moments in exact rational arithmetic, two-body and cubic-symmetric cases,
   power-of-two masses.

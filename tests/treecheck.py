@@ -87,7 +87,7 @@ def geometric_tree(pos, n_leaf: int, lo=(0.0, 0.0, 0.0), side: float = 1.0):
 
 
 # ---------------------------------------------------------------------------
-# literal reading of Algorithms 1 and 2
+# the leaf-first method, sequentially (Sec. 2.3.1-2.3.2)
 # ---------------------------------------------------------------------------
 
 def clz64(x: int) -> int:
