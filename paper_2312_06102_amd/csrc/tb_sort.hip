@@ -227,29 +227,22 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   uint32_t trun = block_exclusive_sum<THREADS>(tsum, s_tmp, &dummy);
   uint32_t grun = block_exclusive_sum<THREADS>(gsum, s_tmp, &dummy);
 
-  // decoupled look-back, one thread per digit
+  // tile-local digit starts; the local sort below needs nothing global
+  uint32_t trun_d[DPT], grun_d[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
     const int d = threadIdx.x * DPT + t;
-    if (d < R) {
-      uint32_t excl = 0;
-      if (tile > 0) {
-        bool timed_out = false;
-        excl = lookback<2>(status, R, tile, d, timed_out);
-        if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
-        atomic_store_agent(&status[(size_t)tile * R + d],
-                           kFlagInclusive | (uint64_t)(excl + tcnt[t]));
-      }
-      s_tstart[d] = trun;
-      s_goff[d] = (int32_t)(grun + excl - trun);
-    }
+    if (d < R) s_tstart[d] = trun;
+    trun_d[t] = trun;
+    grun_d[t] = grun;
     trun += tcnt[t];
     grun += g[t];
   }
   __syncthreads();
 
   // sort the tile by digit in LDS (the input key when a key is written, else
-  // the digit)
+  // the digit), before the look-back so that predecessors have this time to
+  // publish
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     if (wbase + j * 64 < n) {
@@ -264,6 +257,23 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   }
   // the next pass's look-back words for this tile start cleared
   for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
+
+  // decoupled look-back, one thread per digit
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    if (d < R) {
+      uint32_t excl = 0;
+      if (tile > 0) {
+        bool timed_out = false;
+        excl = lookback<2>(status, R, tile, d, timed_out);
+        if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
+        atomic_store_agent(&status[(size_t)tile * R + d],
+                           kFlagInclusive | (uint64_t)(excl + tcnt[t]));
+      }
+      s_goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
+    }
+  }
   __syncthreads();
 
   // coalesced scatter: consecutive lanes write consecutive slots of a digit run
