@@ -32,9 +32,6 @@ namespace tb {
 
 constexpr int kWaves = kCellThreads / 64;
 constexpr int kMaxSpan = (kCellTile + TB_MAX_NLEAF + kCellThreads - 1) / kCellThreads;
-// Leaves are processed one per lane; sorting a tile's leaves by length first
-// gives every wave leaves of similar length, so lanes do not idle.
-constexpr int kLenClasses = 64;
 
 __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) & ~size_t(15); }
 
@@ -70,21 +67,22 @@ struct EmitLds {
   uint32_t *wtot;      // [kWaves][kLevelWords]
   uint32_t *lvl;       // [kLevels]       per-depth base of this tile
   uint16_t *off;       // [kLevels][kCellThreads] next cell slot per depth per thread
-  float4 *rec;         // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL)
+  float4 *rec;         // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL); stored once
+                       //                 the cells are placed, over the dead `off`
   uint32_t *leaf;      // [T]             leaf starting in the tile: local first particle |
                        //                 depth << 11 | slot within its depth << 16
-  uint16_t *leaf_len;  // [T]             particles of the leaf (65535: recompute); aliases off
-  uint16_t *order;     // [T]             leaves by decreasing length; aliases off
-  uint32_t *bucket;    // [2][kLenClasses] leaves per length class, then fill cursors
   uint8_t *heads;      // [T / 8]         bit li: particle t0 + li starts a leaf
   uint32_t *nleaf;     // [1]
 };
 
+__host__ __device__ inline size_t emit_union_bytes(int nl) {
+  const size_t off = (size_t)kLevels * kCellThreads * 2, rec = (size_t)(kCellTile + nl) * 16;
+  return round16(off > rec ? off : rec);
+}
+
 __host__ __device__ inline size_t emit_lds_bytes(int nl) {
   return round16(kCellTile + nl) + round16(kCellTile) + round16((size_t)kWaves * kLevelWords * 4) +
-         round16(kLevels * 4) + round16((size_t)kLevels * kCellThreads * 2) +
-         (size_t)(kCellTile + nl) * 16 + (size_t)kCellTile * 4 + 8 * kLenClasses + kCellTile / 8 +
-         16;
+         round16(kLevels * 4) + emit_union_bytes(nl) + (size_t)kCellTile * 4 + kCellTile / 8 + 16;
 }
 
 __device__ inline EmitLds carve_emit(unsigned char *base, int nl) {
@@ -97,17 +95,13 @@ __device__ inline EmitLds carve_emit(unsigned char *base, int nl) {
   base += round16((size_t)kWaves * kLevelWords * 4);
   s.lvl = reinterpret_cast<uint32_t *>(base);
   base += round16(kLevels * 4);
+  // the per-depth cursors are dead once the cells are placed; the particle
+  // records take their place for the moment phase
   s.off = reinterpret_cast<uint16_t *>(base);
-  base += round16((size_t)kLevels * kCellThreads * 2);
   s.rec = reinterpret_cast<float4 *>(base);
-  base += (size_t)(kCellTile + nl) * 16;
+  base += emit_union_bytes(nl);
   s.leaf = reinterpret_cast<uint32_t *>(base);
   base += (size_t)kCellTile * 4;
-  // the per-depth cursors are dead once the cells are placed
-  s.leaf_len = s.off;
-  s.order = s.off + kCellTile;
-  s.bucket = reinterpret_cast<uint32_t *>(base);
-  base += (size_t)8 * kLenClasses;
   s.heads = base;
   base += kCellTile / 8;
   s.nleaf = reinterpret_cast<uint32_t *>(base);
@@ -671,7 +665,6 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     s.lvl[d] = (uint32_t)(lvl_off[tr.b * (kLevels + 1) + d] + excl[d * cell_tiles + tile]);
   }
   if (threadIdx.x == 0) *s.nleaf = 0;
-  if (threadIdx.x < kLenClasses) s.bucket[threadIdx.x] = 0;
   // this thread's particles t0 + 8t .. t0 + 8t + 7: their keys (issued first,
   // so that they travel with the batched loads below)
   uint64_t kk[kCellIpt];
@@ -680,29 +673,23 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     const int li = threadIdx.x * kCellIpt + j;
     kk[j] = keys[t0 + (li < T ? li : T - 1)];
   }
-  // the tile's particles in key order plus the n_leaf halo, and their (a, D),
-  // in batched loads
+  // the (a, D) of the tile's particles and the n_leaf halo into LDS, in one
+  // batch of loads
   const int span = (int)(min(t1 + (int64_t)nl, n) - t0);
-  {
-    constexpr int kRecBatch = (kCellTile + 32 + kCellThreads - 1) / kCellThreads;
-    for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
-      float4 r[kRecBatch];
-      uint16_t v[kRecBatch];
+  constexpr int kRecBatch = kCellIpt + 1;  // covers span for n_leaf <= 256
+  for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
+    uint16_t v[kRecBatch];
 #pragma unroll
-      for (int u = 0; u < kRecBatch; ++u) {
-        const int x = x0 + u * kCellThreads + threadIdx.x;
-        const int xc = x < span ? x : span - 1;
-        r[u] = sorted[t0 + xc];
-        v[u] = ad[t0 + xc];
-      }
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      v[u] = ad[t0 + (x < span ? x : span - 1)];
+    }
 #pragma unroll
-      for (int u = 0; u < kRecBatch; ++u) {
-        const int x = x0 + u * kCellThreads + threadIdx.x;
-        if (x < span) {
-          s.rec[x] = r[u];
-          s.a[x] = (uint8_t)(v[u] & 0xff);
-          if (x < T) s.d[x] = (uint8_t)(v[u] >> 8);
-        }
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      if (x < span) {
+        s.a[x] = (uint8_t)(v[u] & 0xff);
+        if (x < T) s.d[x] = (uint8_t)(v[u] >> 8);
       }
     }
   }
@@ -740,6 +727,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
 
   // cell structure; leaves are queued for the moment phase
   bool internal = false;
+#pragma unroll
   for (int j = 0; j < kCellIpt; ++j) {
     const int a = A[j], dl = D[j];
     if (a > dl) continue;
@@ -771,34 +759,28 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
   }
   __syncthreads();
 
-  // leaf lengths, then a counting sort of the leaves by decreasing length
-  // (class = min(length, 63))
+  // the cursors are dead: the particle records (tile and halo) take their
+  // place, in batched loads
+  for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
+    float4 r[kRecBatch];
+#pragma unroll
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      r[u] = sorted[t0 + (x < span ? x : span - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      if (x < span) s.rec[x] = r[u];
+    }
+  }
+  __syncthreads();
   const uint32_t nlv = *s.nleaf;
-  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
-    const uint32_t e = s.leaf[x];
-    const int li = e & 0x7ff, dl = (e >> 11) & 31;
-    const int64_t len = leaf_end_fast(s, keys, n, nl, t0, T, li, dl) - (t0 + li);
-    s.leaf_len[x] = (uint16_t)min(len, (int64_t)65535);
-    atomicAdd(&s.bucket[kLenClasses - 1 - (int)min(len, (int64_t)kLenClasses - 1)], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const uint32_t c = threadIdx.x < kLenClasses ? s.bucket[threadIdx.x] : 0u;
-    const uint32_t inc = wave_inclusive_scan(c);
-    if (threadIdx.x < kLenClasses) s.bucket[kLenClasses + threadIdx.x] = inc - c;
-  }
-  __syncthreads();
-  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
-    const int cls = kLenClasses - 1 - min((int)s.leaf_len[x], kLenClasses - 1);
-    s.order[atomicAdd(&s.bucket[kLenClasses + cls], 1u)] = (uint16_t)x;
-  }
-  __syncthreads();
 
   // leaf moments: one lane per leaf, particles read from LDS
   const double lo[3] = {box[4 * tr.b + 0], box[4 * tr.b + 1], box[4 * tr.b + 2]};
   const double side = box[4 * tr.b + 3];
-  for (uint32_t xo = threadIdx.x; xo < nlv; xo += kCellThreads) {
-    const uint32_t x = s.order[xo];
+  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
     const uint32_t le = s.leaf[x];
     const int li = le & 0x7ff;
     const int dl = (le >> 11) & 31;
@@ -813,8 +795,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     }
     const int64_t i = t0 + li;
     const uint64_t key = keys[i];
-    const int64_t e =
-        s.leaf_len[x] < 65535 ? i + s.leaf_len[x] : leaf_end(s.a, keys, n, nl, t0, i, dl);
+    const int64_t e = leaf_end_fast(s, keys, n, nl, t0, T, li, dl);
     cell_count[ci] = (int32_t)(e - i);
     const int sh = kMaxDepth - dl;
     const uint32_t ijk[3] = {compact3(key >> 2) >> sh, compact3(key >> 1) >> sh, compact3(key) >> sh};
