@@ -8,10 +8,12 @@
 // are all registered.  In the (depth, key)-ordered array the children of a
 // depth-d cell are one contiguous run at depth d+1, and the cell placement pass
 // already recorded each internal cell's first child and, for that first child,
-// the slot of its parent.  One launch per depth: the depth-(d+1) cells are
-// staged through LDS in key order; a child whose key, shifted right by three,
-// differs from its predecessor's -- the boundary test of Algorithm 2 -- opens
-// the run of its siblings and combines them into their parent:
+// the slot of its parent.  One launch per depth: the depth-(d+1) cells (and the
+// parent slots of their first children) are staged through LDS in key order; a
+// child whose key, shifted right by three, differs from its predecessor's --
+// the boundary test of Algorithm 2 -- opens the run of its siblings.  The
+// openers of a chunk are packed to the low threads, each of which combines its
+// run into the parent:
 //
 //   M   = sum M_c
 //   com = sum M_c (com_c + s_c) / M
@@ -25,7 +27,32 @@
 namespace tb {
 
 constexpr int kChunk = kParentThreads;  // children staged per workgroup step
+static_assert(kChunk == kParentThreads, "one staged child (and parent slot) per thread");
 constexpr int kHalo = 7;                 // a parent has at most 8 children
+
+// Packs the chunk positions of the run openers (a child at or past L1 whose
+// key >> 3 differs from the previous child's) into s_open and returns their
+// number.  s_key holds the keys of [base - 1, base + kChunk + kHalo); zero
+// outside [L1, L2).  Both barriers are block-wide.
+__device__ inline int pack_openers(const uint64_t *s_key, int64_t base, int64_t L1, int64_t L2,
+                                   int *s_wop, uint16_t *s_open) {
+  const int t = threadIdx.x;
+  const int64_t c = base + t;
+  const bool op = c < L2 && (c == L1 || (s_key[t] >> 3) != (s_key[t + 1] >> 3));
+  const uint64_t bal = __ballot(op);
+  if (lane_id() == 0) s_wop[t >> 6] = __popcll(bal);
+  __syncthreads();
+  int before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kParentThreads / 64; ++w) {
+    const int v = s_wop[w];
+    before += w < (t >> 6) ? v : 0;
+    total += v;
+  }
+  if (op) s_open[before + __popcll(bal & lanemask_lt())] = (uint16_t)t;
+  __syncthreads();
+  return total;
+}
 
 __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
     int depth, const int64_t *__restrict__ level_offset, const uint64_t *__restrict__ cell_key,
@@ -35,6 +62,9 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
     const int64_t *__restrict__ par_start) {
   __shared__ uint64_t s_key[kChunk + kHalo + 1];  // keys of [base - 1, base + kChunk + kHalo)
   __shared__ int32_t s_cnt[kChunk + kHalo];
+  __shared__ int32_t s_hp[kChunk];  // parent slot of each staged first child
+  __shared__ int s_wop[kParentThreads / 64];
+  __shared__ uint16_t s_open[kChunk];
   __shared__ __align__(16) double s_com[(kChunk + kHalo) * 4];
   __shared__ __align__(16) double s_quad[(kChunk + kHalo) * 6];
 
@@ -61,6 +91,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
     uint64_t kv[KN];
     int32_t cv[CN];
     double2 mv[MN], qv[QN];
+    const int32_t hv = base + threadIdx.x < L2 ? head_parent[base + threadIdx.x] : -1;
     const double2 *com2 = reinterpret_cast<const double2 *>(com) + 2 * base;
     const double2 *quad2 = reinterpret_cast<const double2 *>(quad) + 3 * base;
 #pragma unroll
@@ -94,6 +125,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
       const int x = r * kParentThreads + threadIdx.x;
       if (x < lim) s_cnt[x] = cv[r];
     }
+    s_hp[threadIdx.x] = hv;
 #pragma unroll
     for (int r = 0; r < MN; ++r) {
       const int x = r * kParentThreads + threadIdx.x;
@@ -106,13 +138,11 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
     }
     __syncthreads();
 
-    const int t = threadIdx.x;
-    const int64_t c = base + t;
-    const uint64_t kp = s_key[t + 1] >> 3;
-    // Algorithm 2's test: a child opens a new parent when its key >> 3 differs
-    // from the previous child's
-    if (c < L2 && (c == L1 || (s_key[t] >> 3) != kp)) {
-      const int64_t pc = head_parent[c];
+    const int n_open = pack_openers(s_key, base, L1, L2, s_wop, s_open);
+    if ((int)threadIdx.x < n_open) {
+      const int t = s_open[threadIdx.x];
+      const uint64_t kp = s_key[t + 1] >> 3;
+      const int64_t pc = s_hp[t];
       int nch = 0;
       while (nch < 8 && t + nch < lim && (s_key[t + nch + 1] >> 3) == kp) ++nch;
       if (pc < P0 || pc >= P1) {
@@ -184,6 +214,9 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
     int32_t *__restrict__ status_word, int32_t nsets, const int64_t *__restrict__ par_start) {
   __shared__ uint64_t s_key[kChunk + kHalo + 1];
   __shared__ int32_t s_cnt[kChunk + kHalo];
+  __shared__ int32_t s_hp[kChunk];
+  __shared__ int s_wop[kParentThreads / 64];
+  __shared__ uint16_t s_open[kChunk];
   __shared__ float4 s_com[kChunk + kHalo];
   __shared__ __align__(16) float s_quad[(kChunk + kHalo) * 6];
   __shared__ float s_mlo[kChunk + kHalo];
@@ -209,6 +242,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
     constexpr int QN = ((kChunk + kHalo) * 3 + kParentThreads - 1) / kParentThreads;
     uint64_t kv[KN];
     int32_t cv[CN];
+    const int32_t hv = base + threadIdx.x < L2 ? head_parent[base + threadIdx.x] : -1;
     float4 mv[CN];
     float lv[CN];
     float2 qv[QN];
@@ -246,6 +280,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
         s_mlo[x] = lv[r];
       }
     }
+    s_hp[threadIdx.x] = hv;
 #pragma unroll
     for (int r = 0; r < QN; ++r) {
       const int x = r * kParentThreads + threadIdx.x;
@@ -253,11 +288,11 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
     }
     __syncthreads();
 
-    const int t = threadIdx.x;
-    const int64_t c = base + t;
-    const uint64_t kp = s_key[t + 1] >> 3;
-    if (c < L2 && (c == L1 || (s_key[t] >> 3) != kp)) {
-      const int64_t pc = head_parent[c];
+    const int n_open = pack_openers(s_key, base, L1, L2, s_wop, s_open);
+    if ((int)threadIdx.x < n_open) {
+      const int t = s_open[threadIdx.x];
+      const uint64_t kp = s_key[t + 1] >> 3;
+      const int64_t pc = s_hp[t];
       int nch = 0;
       while (nch < 8 && t + nch < lim && (s_key[t + nch + 1] >> 3) == kp) ++nch;
       if (pc < P0 || pc >= P1) {
