@@ -161,6 +161,22 @@ def test_duplicates_mixed():
     full_parity(pos, (rng.random(pos.shape[0]) + 0.5).astype(np.float32), 4)
 
 
+def test_coincident_pairs_many_cells_per_tile():
+    """Pairs of coincident points at n_leaf 1 each hang a chain of single-child
+    cells down to depth 21.  Packed into one corner, they make the first tiles
+    of 2048 sorted particles start several cells per particle (long per-thread
+    runs of placements across many depths), while the uniform singles elsewhere
+    start about one; both kinds of tile meet in one build."""
+    rng = _rng(21)
+    pairs = np.repeat((rng.random((3000, 3)) * 0.25).astype(np.float32), 2, axis=0)
+    singles = rng.random((12000, 3), dtype=np.float32)
+    pos = np.concatenate([pairs, singles])
+    pos = pos[rng.permutation(pos.shape[0])]
+    g, o = full_parity(pos, (rng.random(pos.shape[0]) + 0.5).astype(np.float32), 1)
+    per_tile = np.bincount(o["cell_first"] // 2048)  # a cell starts at its first particle
+    assert per_tile.max() > 8000 and per_tile.min() < 4000, per_tile
+
+
 def test_complete_lattice():
     g1 = (np.arange(32) + 0.5) / 32
     pos = np.stack(np.meshgrid(g1, g1, g1, indexing="ij"), -1).reshape(-1, 3).astype(np.float32)
