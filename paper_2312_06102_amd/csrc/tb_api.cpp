@@ -44,6 +44,11 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->coarse_shift = 0;
   while (((n + (int64_t(1) << p->coarse_shift) - 1) >> p->coarse_shift) > kCoarse) ++p->coarse_shift;
   p->sort_tiles = (n + sc.tile() - 1) / sc.tile();
+  // passes over 32-bit keys count their tiles' digits in a separate read (4
+  // bytes a key) instead of chaining the tiles through the look-back
+  p->counted = 0;
+  for (int k = 0; k < p->key_passes; ++k)
+    if (k * sc.bits >= 32) p->counted |= 1u << k;
   // tiles never straddle two sets: at most one partial tile per set
   p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;
   p->bbox_chunks = (flags & kAutoBoxFlag) ? (n + kBboxChunk - 1) / kBboxChunk + nsets : 1;
@@ -66,6 +71,7 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->status0 = take(8 * (size_t)p->sort_tiles * R);
   p->status1 = take(8 * (size_t)p->sort_tiles * R);
   p->counters = take(4 * 64);
+  p->tile_off = take(4 * (size_t)p->sort_tiles * R);
   p->set_off = take(8 * B1);
   p->box = take(8 * 4 * (size_t)nsets);
   p->bbox_part = take(8 * 6 * (size_t)p->bbox_chunks);
@@ -100,6 +106,7 @@ Work carve(const Plan &p, void *base) {
   w.status0 = reinterpret_cast<uint64_t *>(b + p.status0);
   w.status1 = reinterpret_cast<uint64_t *>(b + p.status1);
   w.counters = reinterpret_cast<uint32_t *>(b + p.counters);
+  w.tile_off = reinterpret_cast<uint32_t *>(b + p.tile_off);
   w.set_off = reinterpret_cast<int64_t *>(b + p.set_off);
   w.box = reinterpret_cast<double *>(b + p.box);
   w.bbox_part = reinterpret_cast<double *>(b + p.bbox_part);

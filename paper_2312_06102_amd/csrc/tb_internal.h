@@ -67,6 +67,7 @@ struct Plan {
   int key_passes;   // radix passes over the 63 key bits
   int set_passes;   // radix passes over the set id (0 when B == 1)
   int coarse_shift; // position >> coarse_shift indexes the coarse set table
+  uint32_t counted; // bit k: key pass k takes its tile offsets from a count and a scan
   int64_t sort_tiles;
   int64_t cell_tiles;   // upper bound of the cell tiles of all sets
   int64_t bbox_chunks;  // upper bound of the bounding-box chunks of all sets
@@ -78,6 +79,8 @@ struct Plan {
   size_t hist_part;     // u32 [keygen blocks][key_passes][radix] per-workgroup counts
   size_t status0, status1;  // u64 [sort_tiles][radix] look-back words (alternating passes)
   size_t counters;      // u32 [64] dynamic tile counters
+  size_t tile_off;      // u32 [radix][sort_tiles] digit counts of every tile, then their
+                        // exclusive prefix over the tiles (counted passes)
   size_t set_off;       // i64 [B + 1] particle offsets of the sets
   size_t box;           // f64 [B][4] the root box of each set
   size_t bbox_part;     // f64 [bbox_chunks][6] per-chunk min/max
@@ -111,6 +114,7 @@ struct Work {
   uint32_t *hist_part;
   uint64_t *status0, *status1;
   uint32_t *counters;
+  uint32_t *tile_off;
   int64_t *set_off;
   double *box;
   double *bbox_part;

@@ -16,6 +16,12 @@
 // The global digit counts come from the key-generation pass, so the keys are
 // read only once per pass.  The index payload of the last pass is `perm`.
 //
+// Passes over 32-bit keys are "counted" instead (reduce, then scan): a first
+// kernel reads only the keys and writes every tile's digit counts, a second
+// turns them into exclusive prefixes over the tiles, and the scatter kernel
+// reads its tile's offsets instead of waiting on its predecessors.  Reading
+// 4 bytes a key again costs less than the look-back chain across the chip.
+//
 // Key width shrinks as the passes go: a pass carries only the key bits later
 // passes still need.  Passes whose digit lies (partly) in the low 32 bits read
 // the 64-bit key; once those bits are consumed the key travels as its upper 32
@@ -76,14 +82,83 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
 // SETID passes take the digit from the set that holds the payload's original
 // index, so that after the key passes they group the particles by set without
 // disturbing the key order inside a set.
-template <int BITS, int IPT, int THREADS, int KIN, int KOUT>
+// Digit counts of one tile of a counted pass: tile t (the keys [t TILE,
+// (t + 1) TILE), as the scatter kernel tiles them) writes cnt[d][t].
+template <int BITS, int IPT, int THREADS, int KIN>
+__global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__ kin_v,
+                                                        uint32_t n, int shift,
+                                                        uint32_t *__restrict__ cnt,
+                                                        uint32_t n_tiles) {
+  using KI = typename KeyType<KIN>::T;
+  constexpr int R = 1 << BITS;
+  constexpr int WAVES = THREADS / 64;
+  constexpr uint32_t TILE = (uint32_t)THREADS * IPT;
+  __shared__ uint32_t h[WAVES * R];  // one histogram per wave
+  for (int i = threadIdx.x; i < WAVES * R; i += THREADS) h[i] = 0;
+  const KI *__restrict__ kin = static_cast<const KI *>(kin_v);
+  const uint32_t tile = blockIdx.x;
+  const uint32_t base = tile * TILE;
+  KI k[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) k[j] = kin[min(base + j * THREADS + threadIdx.x, n - 1u)];
+  __syncthreads();
+  uint32_t *hw = h + (threadIdx.x / 64) * R;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const bool valid = base + j * THREADS + threadIdx.x < n;
+    const uint32_t d = digit_of<BITS>(k[j], shift);
+    // clustered data gives few distinct digits per wave: groups of four or
+    // more equal digits add once (all masks wave-uniform), the rest one by one
+    uint64_t rem = __ballot(valid);
+    while (rem != 0) {
+      const int l = __builtin_ctzll(rem);
+      const uint32_t d0 = __builtin_amdgcn_readlane(d, l);
+      const uint64_t m = __ballot(d == d0) & rem;
+      const uint32_t c = (uint32_t)__popcll(m);
+      if (c < 4) break;
+      if (lane_id() == l) atomicAdd(&hw[d0], c);
+      rem &= ~m;
+    }
+    if ((rem >> lane_id()) & 1u) atomicAdd(&hw[d], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < R; d += THREADS) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) c += h[w * R + d];
+    cnt[(size_t)d * n_tiles + tile] = c;
+  }
+}
+
+// cnt[d][t] <- sum over t' < t of cnt[d][t']: one workgroup per digit, each
+// thread a contiguous run of tiles.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_tile_scan(uint32_t *__restrict__ cnt,
+                                                       uint32_t n_tiles) {
+  __shared__ uint32_t s_tmp[THREADS / 64];
+  uint32_t *row = cnt + (size_t)blockIdx.x * n_tiles;
+  const uint32_t per = (n_tiles + THREADS - 1) / THREADS;
+  const uint32_t t0 = min(threadIdx.x * per, n_tiles), t1 = min(t0 + per, n_tiles);
+  uint32_t sum = 0;
+  for (uint32_t t = t0; t < t1; ++t) sum += row[t];
+  uint32_t total;
+  uint32_t run = block_exclusive_sum<THREADS>(sum, s_tmp, &total);
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t c = row[t];
+    row[t] = run;
+    run += c;
+  }
+}
+
+template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const void *__restrict__ kin_v, void *__restrict__ kout_v,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
     const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
-    int32_t *__restrict__ status_word, uint32_t n_tiles, const int64_t *__restrict__ set_off,
-    int32_t nsets, const uint32_t *__restrict__ coarse, int coarse_shift) {
+    const uint32_t *__restrict__ tile_off, int32_t *__restrict__ status_word, uint32_t n_tiles,
+    const int64_t *__restrict__ set_off, int32_t nsets, const uint32_t *__restrict__ coarse,
+    int coarse_shift) {
   constexpr bool SETID = KIN == kKeyNone;
   using KI = typename KeyType<KIN == kKeyNone ? kKey32 : KIN>::T;
   using KO = typename KeyType<KOUT == kKeyNone ? kKey32 : KOUT>::T;
@@ -124,7 +199,9 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     }
   };
 
-  if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+  // look-back passes take tiles in the order they start, so that every earlier
+  // tile is already running; counted passes need no order
+  if (!COUNTED && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
   // the global digit counts do not depend on the tile: fetch them meanwhile
   uint32_t g[DPT];
 #pragma unroll
@@ -134,7 +211,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   }
   for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
   __syncthreads();
-  const uint32_t tile = s_tile;
+  const uint32_t tile = COUNTED ? blockIdx.x : s_tile;
   if (tile >= n_tiles) {  // the counter was not reset: never true after k_init
     if (threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
     return;
@@ -210,8 +287,9 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
         s_wc[q * R + d] = run;
         run += c;
       }
-      atomic_store_agent(&status[(size_t)tile * R + d],
-                         (tile == 0 ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
+      if constexpr (!COUNTED)
+        atomic_store_agent(&status[(size_t)tile * R + d],
+                           (tile == 0 ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
     }
     tcnt[t] = run;
   }
@@ -258,13 +336,15 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   // the next pass's look-back words for this tile start cleared
   for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
 
-  // decoupled look-back, one thread per digit
+  // decoupled look-back (or the counted offsets), one thread per digit
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
     const int d = threadIdx.x * DPT + t;
     if (d < R) {
       uint32_t excl = 0;
-      if (tile > 0) {
+      if (COUNTED) {
+        excl = tile_off[(size_t)d * n_tiles + tile];
+      } else if (tile > 0) {
         bool timed_out = false;
         excl = lookback<2>(status, R, tile, d, timed_out);
         if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
@@ -312,7 +392,7 @@ static int key_out(const Plan &p, int pass) {
   return pass + 1 < p.key_passes ? key_in(p, pass + 1) : kKeyNone;
 }
 
-template <int BITS, int IPT, int THREADS, int KIN, int KOUT>
+template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED>
 static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
   const int P = p.key_passes + p.set_passes;
@@ -331,10 +411,16 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
     shift = pass * BITS - (KIN == kKey32 ? 32 : 0);
   const int64_t ncoarse = ((p.n - 1) >> p.coarse_shift) + 1;
   const size_t lds = KIN == kKeyNone ? 4 * (size_t)(p.nsets + 1 + ncoarse + 1) : 0;
-  k_onesweep<BITS, IPT, THREADS, KIN, KOUT><<<(unsigned)p.sort_tiles, THREADS, lds, s>>>(
+  if constexpr (COUNTED) {
+    static_assert(KIN != kKeyNone, "set-id passes use the look-back");
+    k_tile_count<BITS, IPT, THREADS, KIN><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
+        K[pass % 2], (uint32_t)p.n, shift, w.tile_off, (uint32_t)p.sort_tiles);
+    k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
+  }
+  k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED><<<(unsigned)p.sort_tiles, THREADS, lds, s>>>(
       K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift,
-      w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, out.status,
-      (uint32_t)p.sort_tiles, w.set_off, p.nsets, w.coarse, p.coarse_shift);
+      w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, w.tile_off,
+      out.status, (uint32_t)p.sort_tiles, w.set_off, p.nsets, w.coarse, p.coarse_shift);
   return hipGetLastError();
 }
 
@@ -342,16 +428,22 @@ template <int BITS, int IPT, int THREADS>
 static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
   const int ki = key_in(p, pass), ko = key_out(p, pass);
+  const bool counted = pass < p.key_passes && ((p.counted >> pass) & 1u);
   if (ki == kKey64 && ko == kKey64)
-    return launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64>(p, w, pass, out, s);
+    return counted ? launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64, true>(p, w, pass, out, s)
+                   : launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64, false>(p, w, pass, out, s);
   if (ki == kKey64 && ko == kKey32)
-    return launch_pass_k<BITS, IPT, THREADS, kKey64, kKey32>(p, w, pass, out, s);
+    return counted ? launch_pass_k<BITS, IPT, THREADS, kKey64, kKey32, true>(p, w, pass, out, s)
+                   : launch_pass_k<BITS, IPT, THREADS, kKey64, kKey32, false>(p, w, pass, out, s);
   if (ki == kKey32 && ko == kKey32)
-    return launch_pass_k<BITS, IPT, THREADS, kKey32, kKey32>(p, w, pass, out, s);
+    return counted ? launch_pass_k<BITS, IPT, THREADS, kKey32, kKey32, true>(p, w, pass, out, s)
+                   : launch_pass_k<BITS, IPT, THREADS, kKey32, kKey32, false>(p, w, pass, out, s);
   if (ki == kKey32 && ko == kKeyNone)
-    return launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone>(p, w, pass, out, s);
+    return counted
+               ? launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone, true>(p, w, pass, out, s)
+               : launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone, false>(p, w, pass, out, s);
   if (ki == kKeyNone && ko == kKeyNone)
-    return launch_pass_k<BITS, IPT, THREADS, kKeyNone, kKeyNone>(p, w, pass, out, s);
+    return launch_pass_k<BITS, IPT, THREADS, kKeyNone, kKeyNone, false>(p, w, pass, out, s);
   return hipErrorInvalidValue;  // no other combination arises for 8- or 9-bit digits
 }
 
