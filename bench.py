@@ -123,6 +123,8 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: i
                 as 8 bytes while its digit touches the low 32 bits, then as the upper
                 4 bytes; the last key pass writes no key; payload 4 read (after pass 0)
                 and written by every pass
+                (passes over 32-bit keys also read their keys a second time to count
+                their tiles' digits: 4 bytes a key, not counted here)
     set_pass    as a later key pass
     reorder     read perm 4 + gathered record 16; write the record in key order 16, its
                 key 8 and its (a_i, D_i) 2
@@ -192,7 +194,8 @@ def roofline(trace, alg, key_passes, workload):
     avg_ms = total_ms / launches
     per_launch = alg["sort_pass"] / key_passes
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    r = {"kernel": "k_onesweep (radix scatter pass over the key bits, one launch per digit)",
+    r = {"kernel": "k_onesweep (radix pass over the key bits, one per digit; a counted pass over "
+                   "32-bit keys includes its k_tile_count and k_tile_scan)",
          "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
          "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
          "alg_bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 5)}
