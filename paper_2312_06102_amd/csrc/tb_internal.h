@@ -31,6 +31,7 @@ constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
 // Parent kernel: children staged per workgroup step.
 constexpr int kParentThreads = 256;
 constexpr int kParentChunk = kParentThreads;
+constexpr int64_t kCountedMaxTiles = 4096;  // largest sort grid with counted passes
 
 // Bounding-box chunks (auto box only).
 constexpr int kBboxChunk = 65536;

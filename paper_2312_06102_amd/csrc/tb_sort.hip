@@ -199,184 +199,191 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     }
   };
 
-  // look-back passes take tiles in the order they start, so that every earlier
-  // tile is already running; counted passes need no order
-  if (!COUNTED && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-  // the global digit counts do not depend on the tile: fetch them meanwhile
+  // The global digit counts do not depend on the tile.
   uint32_t g[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
     const int d = threadIdx.x * DPT + t;
     g[t] = (d < R) ? hist[d] : 0u;
   }
-  for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
-  __syncthreads();
-  const uint32_t tile = COUNTED ? blockIdx.x : s_tile;
-  if (tile >= n_tiles) {  // the counter was not reset: never true after k_init
-    if (threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
-    return;
-  }
-  const uint32_t base = tile * TILE;
-  const int wv = threadIdx.x / 64;
-  const int ln = lane_id();
-  const uint64_t lt = lanemask_lt();
-
-  // wave-striped load: item j of lane l is key base + wv*64*IPT + j*64 + l.
-  // Loads are branch-free (indices past the end are clamped and the items
-  // masked later) so that all of them are in flight together.
-  KI k[IPT];
-  uint32_t v[IPT];
-  uint32_t dg[IPT];
-  uint32_t rk[IPT];
-  const uint32_t wbase = base + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
-  if constexpr (!SETID) {
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, n - 1u)];
-  } else {
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) k[j] = 0;
-  }
-  if (vin) {
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, n - 1u)];
-  } else {
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
-  }
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) dg[j] = digit(k[j], v[j]);
-
-  // Stable wave-level ranking: for every digit bit a ballot; XOR-ing the
-  // ballot with "all ones unless my bit is set" keeps exactly the lanes that
-  // agree with me on that bit, so the AND over all bits is the set of lanes
-  // holding my digit.  Its population below my lane is my rank among them.
-  uint32_t *wc = s_wc + wv * R;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const bool valid = wbase + j * 64 < n;
-    const uint32_t d = dg[j];
-    const uint64_t vmask = __ballot(valid);
-    uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
-#pragma unroll
-    for (int b = 0; b < BITS; ++b) {
-      const uint32_t bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      const uint32_t flip = bit - 1u;  // 0 if my bit is set, all ones if clear
-      plo &= (uint32_t)bb ^ flip;
-      phi &= (uint32_t)(bb >> 32) ^ flip;
-    }
-    const uint64_t peers = ((uint64_t)phi << 32) | plo;
-    const uint32_t pre = (uint32_t)__popcll(peers & lt);
-    uint32_t cnt = 0;
-    if (valid) cnt = wc[d];
-    rk[j] = cnt + pre;
-    if (valid && pre == 0) wc[d] = cnt + (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-
-  // per digit: exclusive offsets across waves and the tile count
-  uint32_t tcnt[DPT];
-#pragma unroll
-  for (int t = 0; t < DPT; ++t) {
-    const int d = threadIdx.x * DPT + t;
-    uint32_t run = 0;
-    if (d < R) {
-#pragma unroll
-      for (int q = 0; q < WAVES; ++q) {
-        const uint32_t c = s_wc[q * R + d];
-        s_wc[q * R + d] = run;
-        run += c;
-      }
-      if constexpr (!COUNTED)
-        atomic_store_agent(&status[(size_t)tile * R + d],
-                           (tile == 0 ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
-    }
-    tcnt[t] = run;
-  }
-
-  // tile-local digit starts and global digit starts (block scans over digits)
-  uint32_t tsum = 0, gsum = 0;
-#pragma unroll
-  for (int t = 0; t < DPT; ++t) {
-    tsum += tcnt[t];
-    gsum += g[t];
-  }
-  uint32_t dummy;
-  uint32_t trun = block_exclusive_sum<THREADS>(tsum, s_tmp, &dummy);
-  uint32_t grun = block_exclusive_sum<THREADS>(gsum, s_tmp, &dummy);
-
-  // tile-local digit starts; the local sort below needs nothing global
-  uint32_t trun_d[DPT], grun_d[DPT];
-#pragma unroll
-  for (int t = 0; t < DPT; ++t) {
-    const int d = threadIdx.x * DPT + t;
-    if (d < R) s_tstart[d] = trun;
-    trun_d[t] = trun;
-    grun_d[t] = grun;
-    trun += tcnt[t];
-    grun += g[t];
-  }
-  __syncthreads();
-
-  // sort the tile by digit in LDS (the input key when a key is written, else
-  // the digit), before the look-back so that predecessors have this time to
-  // publish
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    if (wbase + j * 64 < n) {
-      const uint32_t d = dg[j];
-      const uint32_t p = s_tstart[d] + wc[d] + rk[j];
-      if constexpr (KOUT == kKeyNone)
-        reinterpret_cast<uint16_t *>(s_slot)[p] = (uint16_t)d;
-      else
-        reinterpret_cast<KI *>(s_slot)[p] = k[j];
-      s_vals[p] = v[j];
-    }
-  }
-  // the next pass's look-back words for this tile start cleared
-  for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
-
-  // decoupled look-back (or the counted offsets), one thread per digit
-#pragma unroll
-  for (int t = 0; t < DPT; ++t) {
-    const int d = threadIdx.x * DPT + t;
-    if (d < R) {
-      uint32_t excl = 0;
-      if (COUNTED) {
-        excl = tile_off[(size_t)d * n_tiles + tile];
-      } else if (tile > 0) {
-        bool timed_out = false;
-        excl = lookback<2>(status, R, tile, d, timed_out);
-        if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
-        atomic_store_agent(&status[(size_t)tile * R + d],
-                           kFlagInclusive | (uint64_t)(excl + tcnt[t]));
-      }
-      s_goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
-    }
-  }
-  __syncthreads();
-
-  // coalesced scatter: consecutive lanes write consecutive slots of a digit run
-  const uint32_t tile_n = (n - base) < (uint32_t)TILE ? (n - base) : (uint32_t)TILE;
   bool bad = false;
-  for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
-    uint32_t d;
-    KO key = 0;
-    if constexpr (KOUT == kKeyNone) {
-      d = reinterpret_cast<const uint16_t *>(s_slot)[i];
+  // Look-back passes take tiles in the order they start, so that every earlier
+  // tile is already running; counted passes need no order.  A set-id pass keeps
+  // its workgroups and takes tile after tile, so that each workgroup loads the
+  // set tables once.
+  for (;;) {
+    if (!COUNTED && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
+    __syncthreads();
+    const uint32_t tile = COUNTED ? blockIdx.x : s_tile;
+    if (tile >= n_tiles) {
+      // one tile per workgroup: the counter was not reset (never after k_init)
+      if (!SETID && threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
+      break;
+    }
+    const uint32_t base = tile * TILE;
+    const int wv = threadIdx.x / 64;
+    const int ln = lane_id();
+    const uint64_t lt = lanemask_lt();
+
+    // wave-striped load: item j of lane l is key base + wv*64*IPT + j*64 + l.
+    // Loads are branch-free (indices past the end are clamped and the items
+    // masked later) so that all of them are in flight together.
+    KI k[IPT];
+    uint32_t v[IPT];
+    uint32_t dg[IPT];
+    uint32_t rk[IPT];
+    const uint32_t wbase = base + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
+    if constexpr (!SETID) {
+  #pragma unroll
+      for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, n - 1u)];
     } else {
-      const KI kk = reinterpret_cast<const KI *>(s_slot)[i];
-      d = digit_of<BITS>(kk, shift);
-      // a 64-bit key keeps only its upper half once its low bits are consumed
-      key = (KIN == kKey64 && KOUT == kKey32) ? (KO)((uint64_t)kk >> 32) : (KO)kk;
+  #pragma unroll
+      for (int j = 0; j < IPT; ++j) k[j] = 0;
     }
-    const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
-    if (gp >= n) {  // cannot happen with consistent histograms
-      bad = true;
-      continue;
+    if (vin) {
+  #pragma unroll
+      for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, n - 1u)];
+    } else {
+  #pragma unroll
+      for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
     }
-    if constexpr (KOUT != kKeyNone) kout[gp] = key;
-    vout[gp] = s_vals[i];
+  #pragma unroll
+    for (int j = 0; j < IPT; ++j) dg[j] = digit(k[j], v[j]);
+
+    // Stable wave-level ranking: for every digit bit a ballot; XOR-ing the
+    // ballot with "all ones unless my bit is set" keeps exactly the lanes that
+    // agree with me on that bit, so the AND over all bits is the set of lanes
+    // holding my digit.  Its population below my lane is my rank among them.
+    uint32_t *wc = s_wc + wv * R;
+  #pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const bool valid = wbase + j * 64 < n;
+      const uint32_t d = dg[j];
+      const uint64_t vmask = __ballot(valid);
+      uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
+  #pragma unroll
+      for (int b = 0; b < BITS; ++b) {
+        const uint32_t bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        const uint32_t flip = bit - 1u;  // 0 if my bit is set, all ones if clear
+        plo &= (uint32_t)bb ^ flip;
+        phi &= (uint32_t)(bb >> 32) ^ flip;
+      }
+      const uint64_t peers = ((uint64_t)phi << 32) | plo;
+      const uint32_t pre = (uint32_t)__popcll(peers & lt);
+      uint32_t cnt = 0;
+      if (valid) cnt = wc[d];
+      rk[j] = cnt + pre;
+      if (valid && pre == 0) wc[d] = cnt + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    // per digit: exclusive offsets across waves and the tile count
+    uint32_t tcnt[DPT];
+  #pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      const int d = threadIdx.x * DPT + t;
+      uint32_t run = 0;
+      if (d < R) {
+  #pragma unroll
+        for (int q = 0; q < WAVES; ++q) {
+          const uint32_t c = s_wc[q * R + d];
+          s_wc[q * R + d] = run;
+          run += c;
+        }
+        if constexpr (!COUNTED)
+          atomic_store_agent(&status[(size_t)tile * R + d],
+                             (tile == 0 ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
+      }
+      tcnt[t] = run;
+    }
+
+    // tile-local digit starts and global digit starts (block scans over digits)
+    uint32_t tsum = 0, gsum = 0;
+  #pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      tsum += tcnt[t];
+      gsum += g[t];
+    }
+    uint32_t dummy;
+    uint32_t trun = block_exclusive_sum<THREADS>(tsum, s_tmp, &dummy);
+    uint32_t grun = block_exclusive_sum<THREADS>(gsum, s_tmp, &dummy);
+
+    // tile-local digit starts; the local sort below needs nothing global
+    uint32_t trun_d[DPT], grun_d[DPT];
+  #pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      const int d = threadIdx.x * DPT + t;
+      if (d < R) s_tstart[d] = trun;
+      trun_d[t] = trun;
+      grun_d[t] = grun;
+      trun += tcnt[t];
+      grun += g[t];
+    }
+    __syncthreads();
+
+    // sort the tile by digit in LDS (the input key when a key is written, else
+    // the digit), before the look-back so that predecessors have this time to
+    // publish
+  #pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      if (wbase + j * 64 < n) {
+        const uint32_t d = dg[j];
+        const uint32_t p = s_tstart[d] + wc[d] + rk[j];
+        if constexpr (KOUT == kKeyNone)
+          reinterpret_cast<uint16_t *>(s_slot)[p] = (uint16_t)d;
+        else
+          reinterpret_cast<KI *>(s_slot)[p] = k[j];
+        s_vals[p] = v[j];
+      }
+    }
+    // the next pass's look-back words for this tile start cleared
+    for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
+
+    // decoupled look-back (or the counted offsets), one thread per digit
+  #pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      const int d = threadIdx.x * DPT + t;
+      if (d < R) {
+        uint32_t excl = 0;
+        if (COUNTED) {
+          excl = tile_off[(size_t)d * n_tiles + tile];
+        } else if (tile > 0) {
+          bool timed_out = false;
+          excl = lookback<2>(status, R, tile, d, timed_out);
+          if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
+          atomic_store_agent(&status[(size_t)tile * R + d],
+                             kFlagInclusive | (uint64_t)(excl + tcnt[t]));
+        }
+        s_goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
+      }
+    }
+    __syncthreads();
+
+    // coalesced scatter: consecutive lanes write consecutive slots of a digit run
+    const uint32_t tile_n = (n - base) < (uint32_t)TILE ? (n - base) : (uint32_t)TILE;
+    for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
+      uint32_t d;
+      KO key = 0;
+      if constexpr (KOUT == kKeyNone) {
+        d = reinterpret_cast<const uint16_t *>(s_slot)[i];
+      } else {
+        const KI kk = reinterpret_cast<const KI *>(s_slot)[i];
+        d = digit_of<BITS>(kk, shift);
+        // a 64-bit key keeps only its upper half once its low bits are consumed
+        key = (KIN == kKey64 && KOUT == kKey32) ? (KO)((uint64_t)kk >> 32) : (KO)kk;
+      }
+      const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
+      if (gp >= n) {  // cannot happen with consistent histograms
+        bad = true;
+        continue;
+      }
+      if constexpr (KOUT != kKeyNone) kout[gp] = key;
+      vout[gp] = s_vals[i];
+    }
+    if constexpr (!SETID) break;
+    __syncthreads();  // the next tile reuses the shared arrays
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
@@ -391,6 +398,8 @@ static int key_in(const Plan &p, int pass) {
 static int key_out(const Plan &p, int pass) {
   return pass + 1 < p.key_passes ? key_in(p, pass + 1) : kKeyNone;
 }
+
+constexpr int64_t kSetPassWorkgroups = 512;
 
 template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED>
 static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb_tree &out,
@@ -417,7 +426,10 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
         K[pass % 2], (uint32_t)p.n, shift, w.tile_off, (uint32_t)p.sort_tiles);
     k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
   }
-  k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED><<<(unsigned)p.sort_tiles, THREADS, lds, s>>>(
+  // set-id passes: two workgroups per CU take the tiles in turn
+  const int64_t grid =
+      KIN == kKeyNone && p.sort_tiles > kSetPassWorkgroups ? kSetPassWorkgroups : p.sort_tiles;
+  k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED><<<(unsigned)grid, THREADS, lds, s>>>(
       K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift,
       w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, w.tile_off,
       out.status, (uint32_t)p.sort_tiles, w.set_off, p.nsets, w.coarse, p.coarse_shift);
