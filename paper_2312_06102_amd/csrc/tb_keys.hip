@@ -349,13 +349,21 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
     const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
     const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
     uint64_t *__restrict__ keys, float4 *__restrict__ packed, uint32_t *__restrict__ hist_part,
-    int passes, int32_t *__restrict__ status_word) {
+    int passes, const uint32_t *__restrict__ coarse, int coarse_shift,
+    int32_t *__restrict__ status_word) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
   __shared__ uint32_t h[MAXP * R];
-  extern __shared__ uint32_t s_off[];  // [nsets + 1] set offsets (positions < 2^31)
+  // [nsets + 1] set offsets (positions < 2^31), then (batches) the coarse set
+  // table: entry k is the set holding position k << coarse_shift
+  extern __shared__ uint32_t s_off[];
+  uint32_t *s_coarse = s_off + nsets + 1;
   for (int i = threadIdx.x; i < passes * R; i += blockDim.x) h[i] = 0;
   for (int i = threadIdx.x; i <= nsets; i += blockDim.x) s_off[i] = (uint32_t)set_off[i];
+  if (nsets > 1) {
+    const int ncoarse = (int)((n - 1) >> coarse_shift) + 1;
+    for (int i = threadIdx.x; i <= ncoarse; i += blockDim.x) s_coarse[i] = coarse[i];
+  }
   __syncthreads();
 
   bool bad = false;
@@ -382,7 +390,13 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
       const bool valid = i < n;
       double lo0 = b_lo0, lo1 = b_lo1, lo2 = b_lo2, scale = b_scale;
       if (nsets > 1) {
-        const int b = upper_index(s_off, nsets + 1, i);
+        // the set holding position i lies between the sets holding the coarse
+        // positions around it.  Positions past the end (masked below) look up
+        // the last particle's set: their coarse index would run past the table.
+        const int64_t ic = valid ? i : n - 1;
+        const int k = (int)(ic >> coarse_shift);
+        const int b = min(upper_index_in(s_off, (int)s_coarse[k], (int)s_coarse[k + 1], ic),
+                          nsets - 1);
         lo0 = box[4 * b + 0];
         lo1 = box[4 * b + 1];
         lo2 = box[4 * b + 2];
@@ -454,11 +468,12 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const f
                          const tb_tree &out, hipStream_t s) {
   const int blocks = keygen_blocks(p.n);
   const int passes = p.key_passes;
-  const size_t lds = 4 * (size_t)(p.nsets + 1);
+  const int64_t ncoarse = p.nsets > 1 ? ((p.n - 1) >> p.coarse_shift) + 1 : -1;
+  const size_t lds = 4 * (size_t)(p.nsets + 1 + ncoarse + 1);
 #define TB_KEYGEN(B)                                                                          \
   k_keygen<B><<<blocks, kKeygenThreads, lds, s>>>(pos, mass, p.n, w.set_off, p.nsets, w.box, \
                                                   w.keys0, w.packed, w.hist_part, passes,    \
-                                                  out.status)
+                                                  w.coarse, p.coarse_shift, out.status)
   switch (p.sort.bits) {
     case 8: TB_KEYGEN(8); break;
     case 9: TB_KEYGEN(9); break;
