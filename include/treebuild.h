@@ -95,6 +95,13 @@ extern "C" {
  * results; only speed and workspace size differ. */
 #define TB_SORT_CONFIG(k) (((uint32_t)(k)&0xffu) << 8)
 
+/* Radix passes over the upper 32 key bits normally take their tile offsets
+ * from a separate count of every tile's digits (one more read of 4 bytes a
+ * key) when the sort has at most 4096 tiles, and from the decoupled look-back
+ * across tiles otherwise.  This flag keeps the look-back in every pass.
+ * Results are bit-identical either way; the flag exists for tuning and tests. */
+#define TB_SORT_LOOKBACK (1u << 17)
+
 #define TB_MAX_DEPTH 21
 #define TB_MAX_NLEAF 1024 /* largest supported n_leaf */
 #define TB_MAX_N 2147483647LL

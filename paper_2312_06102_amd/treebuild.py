@@ -42,6 +42,7 @@ TB_STATUS_SETS = 8
 TB_STATUS_BOX = 16
 TB_FP64 = 0
 TB_MIXED = 1
+TB_SORT_LOOKBACK = 1 << 17  # keep the decoupled look-back in every radix pass
 TB_MAX_DEPTH = 21
 TB_MAX_NLEAF = 1024
 TB_MAX_SETS = 16383
@@ -352,11 +353,13 @@ class Builder(_Graphable):
     """Reusable workspace + outputs for repeated builds of N particles."""
 
     def __init__(self, n: int, n_leaf: int = 16, precision: str = "fp64", sort_config: int = 0,
-                 device="cuda", sorted_particles: bool = False, sorted_keys: bool = False):
+                 device="cuda", sorted_particles: bool = False, sorted_keys: bool = False,
+                 lookback: bool = False):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         self.n, self.n_leaf, self.precision = int(n), int(n_leaf), precision
-        self.flags = (TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
+        self.flags = ((TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
+                      | (TB_SORT_LOOKBACK if lookback else 0))
         self.ws_bytes = tb_workspace_bytes(self.n, self.n_leaf, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
@@ -396,13 +399,14 @@ class Builder(_Graphable):
 
 def build(pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 16, box=None,
           precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
-          sorted_keys: bool = False) -> dict:
+          sorted_keys: bool = False, lookback: bool = False) -> dict:
     """One-shot build; returns device tensors trimmed to n_cells.
 
     box: None (derive from data) or (lo[3], side) with side a power of two.
+    lookback: keep the decoupled look-back in every radix pass (TB_SORT_LOOKBACK).
     cell_key is returned as int64 holding the uint64 bit pattern."""
     b = Builder(pos.shape[0], n_leaf, precision, sort_config, pos.device, sorted_particles,
-                sorted_keys)
+                sorted_keys, lookback)
     b.launch(pos, mass, box)
     return b.result()
 
@@ -414,11 +418,12 @@ class BatchBuilder(_Graphable):
 
     def __init__(self, n_total: int, nsets: int, n_leaf: int = 16, precision: str = "fp64",
                  sort_config: int = 0, device="cuda", sorted_particles: bool = False,
-                 sorted_keys: bool = False):
+                 sorted_keys: bool = False, lookback: bool = False):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         self.n, self.nsets, self.n_leaf, self.precision = int(n_total), int(nsets), int(n_leaf), precision
-        self.flags = (TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
+        self.flags = ((TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
+                      | (TB_SORT_LOOKBACK if lookback else 0))
         self.ws_bytes = tb_workspace_bytes_batched(self.n, self.nsets, self.n_leaf, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
@@ -474,9 +479,9 @@ class BatchBuilder(_Graphable):
 def build_batched(pos: torch.Tensor, mass: torch.Tensor, set_offsets: torch.Tensor,
                   n_leaf: int = 16, boxes: Optional[torch.Tensor] = None,
                   precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
-                  sorted_keys: bool = False) -> dict:
+                  sorted_keys: bool = False, lookback: bool = False) -> dict:
     """One-shot batched build; returns device tensors trimmed to n_cells."""
     b = BatchBuilder(pos.shape[0], set_offsets.shape[0] - 1, n_leaf, precision, sort_config,
-                     pos.device, sorted_particles, sorted_keys)
+                     pos.device, sorted_particles, sorted_keys, lookback)
     b.launch(pos, mass, set_offsets, boxes)
     return b.result()

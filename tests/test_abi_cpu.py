@@ -63,6 +63,16 @@ def test_workspace_bytes_grows_with_n():
         tb.tb_workspace_bytes(10, 16, flags=7)
     with pytest.raises(tb.TreeBuildArgError):
         tb.tb_workspace_bytes(10, 16, flags=tb.TB_SORT_CONFIG(200))
+    # the look-back switch is a known flag (same workspace); neighbouring bits are not
+    assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_LOOKBACK) == tb.tb_workspace_bytes(10000, 16)
+    for bit in (16, 18, 31):
+        with pytest.raises(tb.TreeBuildArgError):
+            tb.tb_workspace_bytes(10, 16, flags=1 << bit)
+
+
+def test_lookback_flag_matches_header():
+    m = re.search(r"#define TB_SORT_LOOKBACK \(1u << (\d+)\)", open(HEADER).read())
+    assert m and (1 << int(m.group(1))) == tb.TB_SORT_LOOKBACK
 
 
 def test_sort_config_table():

@@ -152,14 +152,16 @@ def test_one_set_batch_equals_single_build():
     assert np.array_equal(v["com"], s["com"]) and np.array_equal(v["quad"], s["quad"])
 
 
+@pytest.mark.parametrize("lookback", [False, True])
 @pytest.mark.parametrize("sort_config", [0, 2])
-def test_many_small_sets_two_set_digits(sort_config):
-    """600 sets: two 8-bit set-id digits (config 0) or one 9-bit digit (config 2)."""
+def test_many_small_sets_two_set_digits(sort_config, lookback):
+    """600 sets: two 8-bit set-id digits (config 0) or one 9-bit digit (config 2),
+    after counted key passes or after the look-back in every key pass."""
     rng = _rng(33)
     sizes = rng.integers(0, 300, 600)
     sizes[::50] = 0
     pos, mass, offsets = plummer_batch(sizes, seed=33)
-    g = batch_build(pos, mass, offsets, 8, sort_config=sort_config)
+    g = batch_build(pos, mass, offsets, 8, sort_config=sort_config, lookback=lookback)
     check_offsets(g, offsets)
     check_against_oracle(pos, mass, offsets, 8, g, range(len(sizes)))
 

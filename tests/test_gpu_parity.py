@@ -257,16 +257,19 @@ def test_mixed_nonunit_box_and_duplicates():
 # --------------------------------------------------------------------------
 
 def test_every_sort_config_identical():
+    """Every sort shape, with the passes over 32-bit keys counted (the default on
+    small grids) and with the look-back kept in every pass, gives the same tree."""
     pos, mass = dg.plummer(150000, seed=9)
     o = oracle.build(pos, mass, 16)
     ref = None
     for k in range(len(tb.tb_sort_configs())):
-        g = gpu_build(pos, mass, 16, sort_config=k)
-        compare_structure(g, o)
-        if ref is None:
-            ref = g
-        else:
-            assert np.array_equal(g["com"], ref["com"]) and np.array_equal(g["quad"], ref["quad"])
+        for lookback in (False, True):
+            g = gpu_build(pos, mass, 16, sort_config=k, lookback=lookback)
+            compare_structure(g, o)
+            if ref is None:
+                ref = g
+            else:
+                assert np.array_equal(g["com"], ref["com"]) and np.array_equal(g["quad"], ref["quad"])
 
 
 def test_repeat_bit_identical():
