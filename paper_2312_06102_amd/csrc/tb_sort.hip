@@ -16,11 +16,15 @@
 // The global digit counts come from the key-generation pass, so the keys are
 // read only once per pass.  The index payload of the last pass is `perm`.
 //
-// Passes over 32-bit keys are "counted" instead (reduce, then scan): a first
-// kernel reads only the keys and writes every tile's digit counts, a second
-// turns them into exclusive prefixes over the tiles, and the scatter kernel
-// reads its tile's offsets instead of waiting on its predecessors.  Reading
-// 4 bytes a key again costs less than the look-back chain across the chip.
+// On small grids (see kCountedMaxTiles) passes over 32-bit keys are "counted"
+// instead (reduce, then scan): a first kernel reads only the keys and writes
+// every tile's digit counts, a second turns them into exclusive prefixes over
+// the tiles, and the scatter kernel reads its tile's offsets instead of waiting
+// on its predecessors.  There, reading 4 bytes a key again costs less than the
+// look-back chain across the chip; TB_SORT_LOOKBACK keeps the look-back.
+//
+// The set-id passes of a batch run a fixed grid whose workgroups take tile
+// after tile, so that each loads the set tables into LDS once.
 //
 // Key width shrinks as the passes go: a pass carries only the key bits later
 // passes still need.  Passes whose digit lies (partly) in the low 32 bits read
