@@ -218,6 +218,28 @@ def counter_summary(workload, ms_per_step):
             "source": prof["file"]}
 
 
+def stream_copy(reps: int = 10, nbytes: int = 1 << 30) -> dict:
+    """A plain device-to-device copy of `nbytes` (read + write), timed outside the
+    build steps: the bandwidth a streaming kernel reaches on this GPU, against
+    which the build's algorithmic byte rate is also quoted."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    gbps = 2 * nbytes / sec / 1e9
+    return {"bytes_moved": 2 * nbytes, "GBps": round(gbps, 1),
+            "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+
+
 def time_steps(run, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -442,6 +464,9 @@ def main():
         line, data = run_batched(args, tb, dg, torch, np)
     else:
         line, data = run_single(args, tb, dg, torch, np)
+    copy = stream_copy()
+    copy["build_alg_frac_of_copy"] = round(line["build_alg_GBps"] / copy["GBps"], 4)
+    line["stream_copy"] = copy
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, data, np)
     print(json.dumps(line))
