@@ -30,6 +30,19 @@ constexpr int kChunk = kParentThreads;  // children staged per workgroup step
 static_assert(kChunk == kParentThreads, "one staged child (and parent slot) per thread");
 constexpr int kHalo = 7;                 // a parent has at most 8 children
 
+// A set's parents [P0, P1) and children [P1, L2) at one depth, the first parent
+// chunk of the set (row_b) and the side of its root box.
+struct SetBounds {
+  int64_t P0, P1, L2, row_b;
+  double side;
+};
+
+__device__ inline SetBounds set_bounds(int b, int depth, const int64_t *row,
+                                       const int64_t *level_offset, const double *box) {
+  const int64_t *lo_b = level_offset + b * (kLevels + 1);
+  return {lo_b[depth], lo_b[depth + 1], lo_b[depth + 2], row[b], box[4 * b + 3]};
+}
+
 // Packs the chunk positions of the run openers (a child at or past L1 whose
 // key >> 3 differs from the previous child's) into s_open and returns their
 // number.  s_key holds the keys of [base - 1, base + kChunk + kHalo); zero
@@ -72,16 +85,20 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
   const int64_t *row = par_start + depth * (nsets + 1);
   const int64_t n_chunks = row[nsets];
   bool internal = false;
+  // the chunk's set and its bounds: loaded once for a single set (they are the
+  // same for every chunk), per chunk in a batch
+  SetBounds sb = {0, 0, 0, 0, 1.0};
+  if (nsets == 1) sb = set_bounds(0, depth, row, level_offset, box);
   for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-    // the chunk's set, then the set's parents [P0, P1) and children [L1, L2)
-    if (threadIdx.x == 0) s_set = upper_index(row, nsets + 1, ch);
-    __syncthreads();
-    const int b = s_set;
-    const int64_t *lo_b = level_offset + b * (kLevels + 1);
-    const int64_t P0 = lo_b[depth], P1 = lo_b[depth + 1];
-    const int64_t L1 = P1, L2 = lo_b[depth + 2];
-    const double q = ldexp(box[4 * b + 3], -(depth + 2));  // a quarter of the parent side
-    const int64_t base = L1 + (ch - row[b]) * (int64_t)kChunk;
+    if (nsets > 1) {
+      if (threadIdx.x == 0) s_set = upper_index(row, nsets + 1, ch);
+      __syncthreads();
+      sb = set_bounds(s_set, depth, row, level_offset, box);
+    }
+    const int64_t P0 = sb.P0, P1 = sb.P1;
+    const int64_t L1 = P1, L2 = sb.L2;
+    const double q = ldexp(sb.side, -(depth + 2));  // a quarter of the parent side
+    const int64_t base = L1 + (ch - sb.row_b) * (int64_t)kChunk;
     // stage the chunk: every load is issued before the first LDS store
     const int64_t lim = min((int64_t)(kChunk + kHalo), L2 - base);
     constexpr int KN = (kChunk + kHalo + 1 + kParentThreads - 1) / kParentThreads;
@@ -225,17 +242,20 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
   const int64_t *row = par_start + depth * (nsets + 1);
   const int64_t n_chunks = row[nsets];
   bool internal = false;
+  SetBounds sb = {0, 0, 0, 0, 1.0};
+  if (nsets == 1) sb = set_bounds(0, depth, row, level_offset, box);
   for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-    if (threadIdx.x == 0) s_set = upper_index(row, nsets + 1, ch);
-    __syncthreads();
-    const int b = s_set;
-    const int64_t *lo_b = level_offset + b * (kLevels + 1);
-    const int64_t P0 = lo_b[depth], P1 = lo_b[depth + 1];
-    const int64_t L1 = P1, L2 = lo_b[depth + 2];
-    const float lc = ldexpf((float)box[4 * b + 3], -(depth + 1));  // child side
-    const float lp = 2.0f * lc;                                    // parent side
+    if (nsets > 1) {
+      if (threadIdx.x == 0) s_set = upper_index(row, nsets + 1, ch);
+      __syncthreads();
+      sb = set_bounds(s_set, depth, row, level_offset, box);
+    }
+    const int64_t P0 = sb.P0, P1 = sb.P1;
+    const int64_t L1 = P1, L2 = sb.L2;
+    const float lc = ldexpf((float)sb.side, -(depth + 1));  // child side
+    const float lp = 2.0f * lc;                             // parent side
     const float inv_lc = 1.0f / lc, inv_lc2 = inv_lc * inv_lc;
-    const int64_t base = L1 + (ch - row[b]) * (int64_t)kChunk;
+    const int64_t base = L1 + (ch - sb.row_b) * (int64_t)kChunk;
     const int64_t lim = min((int64_t)(kChunk + kHalo), L2 - base);
     constexpr int KN = (kChunk + kHalo + 1 + kParentThreads - 1) / kParentThreads;
     constexpr int CN = (kChunk + kHalo + kParentThreads - 1) / kParentThreads;
