@@ -131,3 +131,21 @@ def test_full_size_clustered64m():
     structure_checks(pos, g, nl)
     print("[full clustered] invariants ok", flush=True)
     sampled_moments(pos, mass, g, FP64_TOL)
+
+
+def test_counted_passes_at_largest_grid():
+    """N = 2^24 with a 4096-key sort tile gives exactly 4096 tiles, the largest
+    grid on which the passes over 32-bit keys count their tiles instead of
+    looking back.  The tree must be bit-identical to the look-back build, and
+    the perm must sort the keys stably."""
+    cfgs = tb.tb_sort_configs()
+    k = next(i for i, (bits, ipt, thr) in enumerate(cfgs) if bits == 8 and ipt * thr == 4096)
+    pos, mass = dg.plummer(1 << 24, seed=2)
+    p, m = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    box = ((0.0, 0.0, 0.0), 1.0)
+    print(f"[fullsize] plummer 2^24 sort_config {k} {cfgs[k]} counted vs look-back", flush=True)
+    a = _np(tb.build(p, m, 16, box, sort_config=k))
+    b = _np(tb.build(p, m, 16, box, sort_config=k, lookback=True))
+    compare_structure(a, b)
+    assert np.array_equal(a["com"], b["com"]) and np.array_equal(a["quad"], b["quad"])
+    structure_checks(pos, a, 16)
