@@ -858,10 +858,10 @@ hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
   if (p.nsets <= 64)
     k_set_scan<64><<<1, 64, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off, out.level_offset,
                                     cell_offsets, out.n_cells, w.par_start, w.box, out.box_out);
-  else
-    k_set_scan<1024><<<1, 1024, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
-                                        out.level_offset, cell_offsets, out.n_cells, w.par_start,
-                                        w.box, out.box_out);
+  else  // 512 threads: its 22 counts per set fit in registers (1024 would spill)
+    k_set_scan<512><<<1, 512, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
+                                      out.level_offset, cell_offsets, out.n_cells, w.par_start,
+                                      w.box, out.box_out);
   return hipGetLastError();
 }
 
