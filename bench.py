@@ -70,8 +70,10 @@ def parse():
                     help="batched4096: skip the 4096 sequential single-set builds")
     ap.add_argument("--no-compare", action="store_true",
                     help="mixed16m: skip the FP64 build on the same data")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22,
-                    help="particles of the workload the oracle builds for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="particles of the workload the oracle builds for the CPU baseline "
+                         "(default: all of a single set up to 2^24, the first 2^24 of a larger "
+                         "one, whole sets up to 2^22 particles of a batch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 256 MiB (to scale HBM byte counters)")
     return ap.parse_args()
@@ -418,30 +420,76 @@ def run_batched(args, tb, dg, torch, np):
     return line, (pos_np, mass_np, n_leaf, offsets_np)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first /proc/cpuinfo entry)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(args, data, np):
+    """The CPU oracle (top-down insertion + direct FP64 moments, one thread) timed
+    on this host, per stage, on the workload itself when N <= 2^24, else on a
+    bounded sample; beside it the paper's own leaf-first method on one thread
+    (Algorithms 1 + 2, moments from the children) on the same particles."""
     import oracle
     pos_np, mass_np, n_leaf, offsets = data
     oracle.load()
     if offsets is None:
-        m = min(args.cpu_sample, pos_np.shape[0])
+        m = pos_np.shape[0] if args.cpu_sample is None else min(args.cpu_sample, pos_np.shape[0])
+        p, w = np.ascontiguousarray(pos_np[:m]), np.ascontiguousarray(mass_np[:m])
         tc0 = time.perf_counter()
-        oracle.build(np.ascontiguousarray(pos_np[:m]), np.ascontiguousarray(mass_np[:m]), n_leaf)
+        ref = oracle.build(p, w, n_leaf)
         tc1 = time.perf_counter()
-        what = f"first {m} particles of the same workload"
+        lf = oracle.leaf_first_build(p, w, n_leaf)
+        tc2 = time.perf_counter()
+        if lf["n_cells"] != ref["n_cells"]:
+            raise RuntimeError("leaf-first CPU reference disagrees with the oracle")
+        stages = {k: round(v, 3) for k, v in ref["stage_s"].items()}
+        lf_stages = {k: round(v, 3) for k, v in lf["stage_s"].items()}
+        what = ("the whole workload" if m == pos_np.shape[0]
+                else f"the first {m} particles of the workload")
+        what += f" (N = {m}), one run"
     else:
         # whole sets from the start of the batch, about cpu_sample particles
-        nb = int(np.searchsorted(offsets, args.cpu_sample)) or 1
+        want = args.cpu_sample or (1 << 22)
+        nb = int(np.searchsorted(offsets, want)) or 1
         m = int(offsets[nb])
+        stages = dict.fromkeys(oracle.ORACLE_STAGES, 0.0)
+        lf_stages = dict.fromkeys(oracle.LEAF_FIRST_STAGES, 0.0)
         tc0 = time.perf_counter()
         for b in range(nb):
             s0, s1 = int(offsets[b]), int(offsets[b + 1])
-            oracle.build(pos_np[s0:s1], mass_np[s0:s1], n_leaf)
+            r = oracle.build(pos_np[s0:s1], mass_np[s0:s1], n_leaf)
+            for k, v in r["stage_s"].items():
+                stages[k] += v
         tc1 = time.perf_counter()
-        what = f"first {nb} sets ({m} particles) of the same batch, one oracle build per set"
+        for b in range(nb):
+            s0, s1 = int(offsets[b]), int(offsets[b + 1])
+            r = oracle.leaf_first_build(pos_np[s0:s1], mass_np[s0:s1], n_leaf)
+            for k, v in r["stage_s"].items():
+                lf_stages[k] += v
+        tc2 = time.perf_counter()
+        stages = {k: round(v, 3) for k, v in stages.items()}
+        lf_stages = {k: round(v, 3) for k, v in lf_stages.items()}
+        what = f"the first {nb} sets ({m} particles) of the same batch, one build per set, one run"
+    host = f"{cpu_model()}, host nproc={os.cpu_count()}"
     return {"value": m / (tc1 - tc0), "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}, full oracle build (keys, top-down insertion, perm, canonical "
-                      f"order, direct FP64 moments), {tc1 - tc0:.2f} s on "
-                      f"{platform.processor() or platform.machine()} (host nproc={os.cpu_count()})"}
+            "sample": f"{what}: full oracle build (FP64 keys, top-down insertion, perm, "
+                      f"canonical order, direct FP64 moments per cell), {tc1 - tc0:.2f} s on "
+                      f"one thread of {host}",
+            "N": m, "seconds": round(tc1 - tc0, 3), "stages_s": stages, "cpu_model": cpu_model(),
+            "paper_method": {
+                "value": m / (tc2 - tc1), "unit": "particles/s", "cores": 1,
+                "seconds": round(tc2 - tc1, 3), "stages_s": lf_stages,
+                "what": "the paper's leaf-first build on one thread (keys, sort of key/index "
+                        "pairs, reorder, leaves by Algorithm 1, parents by Algorithm 2 with "
+                        "moments combined from the children), same particles"}}
 
 
 def main():
@@ -468,6 +516,10 @@ def main():
     copy["build_alg_frac_of_copy"] = round(line["build_alg_GBps"] / copy["GBps"], 4)
     line["stream_copy"] = copy
     if not args.no_cpu_baseline:
+        if args.cpu_sample is None and data[3] is None and data[0].shape[0] > (1 << 24):
+            args.cpu_sample = 1 << 24
+        print("[bench] timing the CPU oracle and the CPU leaf-first reference", file=sys.stderr,
+              flush=True)
         line["cpu_baseline"] = cpu_baseline(args, data, np)
     print(json.dumps(line))
 

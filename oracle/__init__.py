@@ -8,7 +8,10 @@ from the product path.
 The C source ``tb_oracle.c`` is a sequential top-down Barnes-Hut insertion
 build (Sec. 2.1) over hashed Morton keys (Sec. 2.2) with direct FP64 moment
 sums per cell; see the header comment there for each step and its source.
-``build_library()`` compiles it with gcc into ``liboracle.so`` next to it.
+``tb_leaffirst.c`` is a second CPU reference: the paper's own leaf-first
+method (Sec. 2.3, Algorithms 1 and 2) on one thread, moments combined from the
+children as cells are created.  ``build_library()`` compiles both with gcc into
+``liboracle.so`` next to them.
 """
 from __future__ import annotations
 
@@ -21,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "tb_oracle.c")
+LEAF_FIRST_SRC = os.path.join(_HERE, "tb_leaffirst.c")
 LIB = os.path.join(_HERE, "liboracle.so")
 
 # Strict IEEE FP64: no contraction into FMA, no fast-math reassociation.
@@ -33,8 +37,9 @@ _lib = None
 
 
 def build_library(src: str = SRC, out: str = LIB, extra_flags=()) -> str:
-    """Compile the oracle C source into a shared library (gcc)."""
-    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", out + ".tmp", src, "-lm"]
+    """Compile the oracle C source (``src``, normally tb_oracle.c) together with
+    the leaf-first reference into a shared library (gcc)."""
+    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", out + ".tmp", src, LEAF_FIRST_SRC, "-lm"]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     os.replace(out + ".tmp", out)
     return out
@@ -49,6 +54,10 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.tbo_max_cells.restype = i64
     lib.tbo_build.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double] + [P] * 11
     lib.tbo_build.restype = ctypes.c_int
+    lib.tbo_build_timed.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double] + [P] * 12
+    lib.tbo_build_timed.restype = ctypes.c_int
+    lib.tbl_build.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double] + [P] * 11
+    lib.tbl_build.restype = ctypes.c_int
     lib.tbo_cell_moments.argtypes = [P, P, P, ctypes.c_double, P, i64, i64,
                                      ctypes.c_uint64, ctypes.c_int, P, P]
     lib.tbo_cell_moments.restype = ctypes.c_int
@@ -103,12 +112,17 @@ def max_cells(n: int, n_leaf: int, lib=None) -> int:
     return int(lib.tbo_max_cells(n, n_leaf))
 
 
+ORACLE_STAGES = ("keys", "insertion", "perm", "canonical", "moments")
+LEAF_FIRST_STAGES = ("keys", "sort", "reorder", "leaves", "parents", "output")
+
+
 def build(pos: np.ndarray, mass: np.ndarray, n_leaf: int, lo=(0.0, 0.0, 0.0), side: float = 1.0,
           moments: bool = True, lib=None) -> dict:
     """Reference tree.  Returns a dict of numpy arrays trimmed to n_cells:
     perm, dfs_perm, cell_key, cell_level, cell_first, cell_count, child_ptr [C,2],
     com [C,4] (dx, dy, dz relative to the cell centre, M), quad [C,6]
-    (xx, xy, xz, yy, yz, zz), level_offset [23], n_cells."""
+    (xx, xy, xz, yy, yz, zz), level_offset [23], n_cells, and stage_s: seconds
+    of each step named in ORACLE_STAGES."""
     lib = lib or load()
     pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
     mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
@@ -128,21 +142,58 @@ def build(pos: np.ndarray, mass: np.ndarray, n_leaf: int, lo=(0.0, 0.0, 0.0), si
     quad = np.empty((cmax, 6), dtype=np.float64) if moments else None
     loff = np.zeros(23, dtype=np.int64)
     nc = np.zeros(1, dtype=np.int64)
+    stage = np.zeros(len(ORACLE_STAGES), dtype=np.float64)
     null = ctypes.c_void_p(0)
-    rc = lib.tbo_build(_ptr(pos), _ptr(mass), n, n_leaf, _ptr(lo), side, _ptr(perm), _ptr(dfs),
-                       _ptr(key), _ptr(level), _ptr(first), _ptr(count), _ptr(child),
-                       _ptr(com) if moments else null, _ptr(quad) if moments else null,
-                       _ptr(loff), _ptr(nc))
+    rc = lib.tbo_build_timed(_ptr(pos), _ptr(mass), n, n_leaf, _ptr(lo), side, _ptr(perm),
+                             _ptr(dfs), _ptr(key), _ptr(level), _ptr(first), _ptr(count),
+                             _ptr(child), _ptr(com) if moments else null,
+                             _ptr(quad) if moments else null, _ptr(loff), _ptr(nc), _ptr(stage))
     if rc:
         raise OracleError(rc)
     c = int(nc[0])
     out = dict(perm=perm[:n], dfs_perm=dfs[:n], cell_key=key[:c], cell_level=level[:c],
                cell_first=first[:c], cell_count=count[:c], child_ptr=child[:c],
-               level_offset=loff, n_cells=c)
+               level_offset=loff, n_cells=c, stage_s=dict(zip(ORACLE_STAGES, stage.tolist())))
     if moments:
         out["com"] = com[:c]
         out["quad"] = quad[:c]
     return out
+
+
+def leaf_first_build(pos: np.ndarray, mass: np.ndarray, n_leaf: int, lo=(0.0, 0.0, 0.0),
+                     side: float = 1.0, lib=None) -> dict:
+    """The paper's leaf-first method on one CPU thread (tb_leaffirst.c), same
+    output layout as build() (without dfs_perm); stage_s holds the seconds of
+    each step named in LEAF_FIRST_STAGES."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+    n = pos.shape[0]
+    if mass.shape[0] != n:
+        raise ValueError("pos and mass lengths differ")
+    lo, side = _box(lo, side)
+    cmax = max(max_cells(n, n_leaf, lib), 1)
+    perm = np.empty(max(n, 1), dtype=np.int32)
+    key = np.empty(cmax, dtype=np.uint64)
+    level = np.empty(cmax, dtype=np.uint8)
+    first = np.empty(cmax, dtype=np.int32)
+    count = np.empty(cmax, dtype=np.int32)
+    child = np.empty((cmax, 2), dtype=np.int32)
+    com = np.empty((cmax, 4), dtype=np.float64)
+    quad = np.empty((cmax, 6), dtype=np.float64)
+    loff = np.zeros(23, dtype=np.int64)
+    nc = np.zeros(1, dtype=np.int64)
+    stage = np.zeros(len(LEAF_FIRST_STAGES), dtype=np.float64)
+    rc = lib.tbl_build(_ptr(pos), _ptr(mass), n, n_leaf, _ptr(lo), side, _ptr(perm), _ptr(key),
+                       _ptr(level), _ptr(first), _ptr(count), _ptr(child), _ptr(com), _ptr(quad),
+                       _ptr(loff), _ptr(nc), _ptr(stage))
+    if rc:
+        raise OracleError(rc)
+    c = int(nc[0])
+    return dict(perm=perm[:n], cell_key=key[:c], cell_level=level[:c], cell_first=first[:c],
+                cell_count=count[:c], child_ptr=child[:c], com=com[:c], quad=quad[:c],
+                level_offset=loff, n_cells=c,
+                stage_s=dict(zip(LEAF_FIRST_STAGES, stage.tolist())))
 
 
 def cell_moments(pos, mass, perm, first: int, count: int, key: int, level: int,

@@ -46,10 +46,12 @@
  * Build with -O2 -ffp-contract=off and no fast-math, so every FP64 operation is
  * a single IEEE round-to-nearest step.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define TBO_OK 0
 #define TBO_ERR_ARG (-1)
@@ -367,6 +369,13 @@ static void cell_moments(const float *pos, const float *mass, const double lo[3]
 /* Public entry points                                                     */
 /* ---------------------------------------------------------------------- */
 
+/* Wall-clock seconds (monotonic), for the optional per-stage timings. */
+static double now_s(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 /* Upper bound on the number of cells: at most N leaves, and at each of the
  * depths 0..20 at most floor(N/(n_leaf+1)) split cells (they are disjoint and
  * each holds more than n_leaf particles). */
@@ -385,11 +394,15 @@ int64_t tbo_max_cells(int64_t n, int32_t n_leaf) {
  *   com [cells][4], quad [cells][6]            moments (NULL to skip them)
  *   level_offset [23]                          first cell of each depth, [22] = n_cells
  * Returns 0 or a negative error code; *n_cells receives the number of cells.
+ * stage_s [5] (may be NULL) receives the seconds spent in steps 1-2 (keys),
+ * 3 (insertion), 4 (perm and its DFS cross-check), 5 (canonical order, ranges,
+ * child links) and 6 (moments).
  */
-int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, const double lo[3],
-              double side, int32_t *perm, int32_t *dfs_perm, uint64_t *cell_key,
-              uint8_t *cell_level, int32_t *cell_first, int32_t *cell_count, int32_t *child_ptr,
-              double *com, double *quad, int64_t *level_offset, int64_t *n_cells) {
+int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                    const double lo[3], double side, int32_t *perm, int32_t *dfs_perm,
+                    uint64_t *cell_key, uint8_t *cell_level, int32_t *cell_first,
+                    int32_t *cell_count, int32_t *child_ptr, double *com, double *quad,
+                    int64_t *level_offset, int64_t *n_cells, double *stage_s) {
   tbo_tree t;
   uint32_t *q = NULL;
   uint64_t *keys = NULL;
@@ -398,7 +411,10 @@ int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, co
   int64_t *order = NULL, *pos_of = NULL;
   int64_t i, c, nc;
   int rc = TBO_OK, lvl;
+  double t0 = now_s(), t1;
 
+  if (stage_s)
+    for (lvl = 0; lvl < 5; ++lvl) stage_s[lvl] = 0.0;
   if (n < 0 || n > 2147483647LL || n_leaf < 1 || !lo || !n_cells || !level_offset)
     return TBO_ERR_ARG;
   if (n > 0 && (!pos || !mass || !perm || !cell_key || !cell_level || !cell_first ||
@@ -426,6 +442,9 @@ int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, co
   }
   rc = tbo_keys(pos, n, lo, side, q, keys);
   if (rc) goto done;
+  t1 = now_s();
+  if (stage_s) stage_s[0] = t1 - t0;
+  t0 = t1;
 
   /* step 3: top-down insertion in index order */
   t.q = q;
@@ -439,6 +458,9 @@ int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, co
     rc = TBO_ERR_NOMEM;
     goto done;
   }
+  t1 = now_s();
+  if (stage_s) stage_s[1] = t1 - t0;
+  t0 = t1;
 
   /* step 4: perm = stable key order; cross-check with the DFS order */
   for (i = 0; i < n; ++i) {
@@ -464,6 +486,9 @@ int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, co
       }
     if (dfs_perm) memcpy(dfs_perm, dfs, (size_t)n * sizeof(int32_t));
   }
+  t1 = now_s();
+  if (stage_s) stage_s[2] = t1 - t0;
+  t0 = t1;
 
   /* step 5: canonical order */
   nc = t.n;
@@ -539,6 +564,9 @@ int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, co
   for (lvl = TBO_MAX_DEPTH; lvl >= 0; --lvl)
     if (level_offset[lvl] > level_offset[lvl + 1]) level_offset[lvl] = level_offset[lvl + 1];
   *n_cells = nc;
+  t1 = now_s();
+  if (stage_s) stage_s[3] = t1 - t0;
+  t0 = t1;
 
   /* step 6: moments */
   if (com && quad) {
@@ -546,6 +574,7 @@ int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, co
       cell_moments(pos, mass, lo, side, perm, cell_first[c], cell_count[c], cell_key[c],
                    cell_level[c], &com[4 * c], &quad[6 * c]);
   }
+  if (stage_s) stage_s[4] = now_s() - t0;
 
 done:
   for (i = 0; i < t.n; ++i) free(t.v[i].mem);
@@ -557,6 +586,15 @@ done:
   free(pos_of);
   free(order);
   return rc;
+}
+
+int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, const double lo[3],
+              double side, int32_t *perm, int32_t *dfs_perm, uint64_t *cell_key,
+              uint8_t *cell_level, int32_t *cell_first, int32_t *cell_count, int32_t *child_ptr,
+              double *com, double *quad, int64_t *level_offset, int64_t *n_cells) {
+  return tbo_build_timed(pos, mass, n, n_leaf, lo, side, perm, dfs_perm, cell_key, cell_level,
+                         cell_first, cell_count, child_ptr, com, quad, level_offset, n_cells,
+                         NULL);
 }
 
 /* Moments of one arbitrary particle range [first, first+count) of `perm`, in the

@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -88,3 +89,85 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in line["error"]
+
+
+# --------------------------------------------------------------------------
+# the batched set lookup through the coarse set table, emulated on the CPU
+# --------------------------------------------------------------------------
+# The key kernel and the set-id sort passes find the set that holds position x
+# as follows (tb_keys.hip, k_setup / k_keygen; tb_sort.hip, k_onesweep):
+#   shift  : smallest s with ceil(n / 2^s) <= K_COARSE                (make_plan)
+#   coarse : coarse[k] = last b with off[b] <= min(k << shift, n - 1),
+#            for k = 0 .. ((n - 1) >> shift)                            (k_setup)
+#   lookup : k = x >> shift; b = last index in [coarse[k], coarse[k + 1]]
+#            with off[b] <= x, found by the kernels' binary search; the key
+#            kernel clamps x to n - 1 for lanes past the end and b to B - 1.
+# The emulation checks that every index stays inside the table and that the
+# set found is the one a plain search over all offsets finds.
+
+K_COARSE = 4096
+
+
+def _coarse_shift(n):
+    s = 0
+    while (n + (1 << s) - 1) >> s > K_COARSE:
+        s += 1
+    return s
+
+
+def _upper_index_in(tab, lo, hi, x):
+    """Vectorised copy of the kernels' search: last b in [lo, hi] with tab[b] <= x,
+    given tab[lo] <= x."""
+    lo, hi = lo.copy(), hi.copy()
+    while True:
+        act = lo < hi
+        if not act.any():
+            return lo
+        mid = (lo + hi + 1) >> 1
+        ok = tab[np.minimum(mid, len(tab) - 1)] <= x
+        lo = np.where(act & ok, mid, lo)
+        hi = np.where(act & ~ok, mid - 1, hi)
+
+
+def _random_layout(rng):
+    nsets = int(rng.choice([1, 2, 7, 64, 1000, 4096, 16383]))
+    sizes = rng.integers(0, rng.choice([3, 40, 3000, 70000]), nsets)
+    sizes[rng.random(nsets) < 0.2] = 0  # empty sets anywhere, also at both ends
+    if sizes.sum() == 0:
+        sizes[rng.integers(0, nsets)] = 1
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return nsets, off
+
+
+def test_coarse_set_lookup_emulation():
+    rng = np.random.default_rng(2024)
+    lookups = 0
+    for _ in range(300):
+        nsets, off = _random_layout(rng)
+        n = int(off[-1])
+        shift = _coarse_shift(n)
+        K = ((n - 1) >> shift) + 1
+        assert K <= K_COARSE
+        kpos = np.minimum(np.arange(K + 1, dtype=np.int64) << shift, n - 1)
+        # k_setup: the set holding each coarse position (search over all B + 1 offsets)
+        coarse = _upper_index_in(off, np.zeros(K + 1, np.int64), np.full(K + 1, nsets, np.int64),
+                                 kpos)
+        assert coarse.max() <= nsets - 1  # off[B] = n is never <= a position below n
+        # every position of small batches, a sample plus every set boundary of large
+        # ones, and lanes past the end (clamped to n - 1 by the key kernel)
+        if n <= 20000:
+            x = np.arange(n, dtype=np.int64)
+        else:
+            edges = np.concatenate([off[:-1], off[1:] - 1, kpos]).clip(0, n - 1)
+            x = np.concatenate([rng.integers(0, n, 20000), edges])
+        x = np.concatenate([x, np.full(64, n - 1, np.int64)])
+        k = x >> shift
+        assert k.max() + 1 <= K  # both table entries read stay inside the K + 1 entries
+        lo, hi = coarse[k], coarse[k + 1]
+        assert np.all(off[lo] <= x) and np.all(lo <= hi)
+        b = np.minimum(_upper_index_in(off, lo, hi, x), nsets - 1)
+        want = np.searchsorted(off, x, side="right") - 1
+        assert np.array_equal(b, want)
+        assert np.all((off[b] <= x) & (x < off[b + 1]))  # a non-empty set holding x
+        lookups += x.size
+    assert lookups > 5_000_000

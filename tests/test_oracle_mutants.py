@@ -33,6 +33,14 @@ MUTANTS = {
     "round_not_floor": ("return (uint32_t)floor(t);", "return (uint32_t)floor(t + 0.5);"),
     "centre_half": ("off[0] = ((double)ijk[0] + 0.5) * h;", "off[0] = ((double)ijk[0]) * h;"),
     "depth_cap": ("#define TBO_MAX_DEPTH 21", "#define TBO_MAX_DEPTH 20"),
+    # the single-cell entry point used by the sampled full-size checks
+    "cell_moments_first_count": (
+        "cell_moments(pos, mass, lo, side, perm, first, count, key, level, com_out, quad_out);",
+        "cell_moments(pos, mass, lo, side, perm, count, first, key, level, com_out, quad_out);"),
+    "cell_moments_frame": (
+        "cell_moments(pos, mass, lo, side, perm, first, count, key, level, com_out, quad_out);",
+        "cell_moments(pos, mass, lo, side, perm, first, count, key >> 3, level - 1, com_out,"
+        " quad_out);"),
 }
 
 
@@ -90,10 +98,29 @@ def _pin_checks(lib):
             assert max(abs(t["com"][c, a] - float(cx[a])) for a in range(3)) <= 1e-15 * l
             assert max(abs(t["quad"][c, i] - float(qx[i])) for i in range(6)) <= 1e-14 * float(M) * l * l
 
+    def cell_moments_wrapper():
+        rng = _rng(301)
+        lo, side = (-4.0, -4.0, -4.0), 8.0
+        pos = (rng.random((50, 3)) * 6.0 - 3.0).astype(np.float32)
+        mass = (rng.random(50) + 0.1).astype(np.float32)
+        t = oracle.build(pos, mass, 2, lo=lo, side=side, lib=lib)
+        for c in range(t["n_cells"]):
+            f, n = int(t["cell_first"][c]), int(t["cell_count"][c])
+            key, lv = int(t["cell_key"][c]), int(t["cell_level"][c])
+            com, quad = oracle.cell_moments(pos, mass, t["perm"], f, n, key, lv, lo=lo, side=side,
+                                            lib=lib)
+            M, cx, qx = tc.exact_moments(pos, mass, list(t["perm"][f:f + n]), key, lv, lo=lo,
+                                         side=side)
+            l = side * 2.0 ** -lv
+            assert abs(com[3] - float(M)) <= 1e-15 * float(M)
+            assert max(abs(com[a] - float(cx[a])) for a in range(3)) <= 1e-15 * l
+            assert max(abs(quad[i] - float(qx[i])) for i in range(6)) <= 1e-14 * float(M) * l * l
+
     check("hand_keys", hand_keys)
     check("set_definition", set_definition)
     check("coincident", coincident)
     check("exact_moments", exact_moments)
+    check("cell_moments_wrapper", cell_moments_wrapper)
     return failures
 
 

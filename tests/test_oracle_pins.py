@@ -351,3 +351,104 @@ def test_root_matches_global_sums():
         ca = math.fsum(mass.astype(np.float64) * pos[:, a].astype(np.float64)) / M - 0.5
         assert abs(t["com"][0, a] - ca) < 1e-15
     assert abs(t["quad"][0, 0] + t["quad"][0, 3] + t["quad"][0, 5]) < 1e-15 * M
+
+
+# --------------------------------------------------------------------------
+# the single-cell moment wrapper (used by the large sampled parity checks)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_cell_moments_every_cell(seed):
+    """oracle.cell_moments, given each cell's own range of the oracle's perm and
+    the cell's key and depth, returns the build's moments bit for bit, and both
+    equal the exact rational moments of the cell's particles.  Odd seeds use a
+    non-unit box, so a dropped box corner or side also fails."""
+    rng = _rng(300 + seed)
+    n = 70
+    if seed % 2:
+        lo, side = (-4.0, -4.0, -4.0), 8.0
+        pos = (rng.random((n, 3)) * 6.0 - 3.0).astype(np.float32)
+    else:
+        lo, side = (0.0, 0.0, 0.0), 1.0
+        pos = rng.random((n, 3), dtype=np.float32)
+    mass = (rng.random(n) + 0.1).astype(np.float32)
+    t = oracle.build(pos, mass, 2, lo=lo, side=side)
+    for c in range(t["n_cells"]):
+        f, cnt = int(t["cell_first"][c]), int(t["cell_count"][c])
+        key, lvl = int(t["cell_key"][c]), int(t["cell_level"][c])
+        com, quad = oracle.cell_moments(pos, mass, t["perm"], f, cnt, key, lvl, lo=lo, side=side)
+        assert np.array_equal(com, t["com"][c]) and np.array_equal(quad, t["quad"][c]), c
+        M, cx, qx = tc.exact_moments(pos, mass, list(t["perm"][f:f + cnt]), key, lvl, lo=lo,
+                                     side=side)
+        em, ec, eq = _rel_errors(com, quad, M, cx, qx, lvl, side)
+        assert em < 1e-15 and ec < 1e-15 and eq < 1e-14, (c, em, ec, eq)
+
+
+def test_cell_moments_argument_roles():
+    """A range that is not the cell's, or the right range in another cell's frame,
+    gives other moments: first/count, key and depth each matter."""
+    rng = _rng(310)
+    pos = rng.random((200, 3), dtype=np.float32)
+    mass = (rng.random(200) + 0.1).astype(np.float32)
+    t = oracle.build(pos, mass, 4)
+    c = int(np.nonzero((t["cell_level"] == 2) & (t["cell_count"] > 3))[0][0])
+    f, cnt = int(t["cell_first"][c]), int(t["cell_count"][c])
+    key, lvl = int(t["cell_key"][c]), int(t["cell_level"][c])
+    ref_c, ref_q = oracle.cell_moments(pos, mass, t["perm"], f, cnt, key, lvl)
+    M, cx, _ = tc.exact_moments(pos, mass, list(t["perm"][f:f + cnt]), key, lvl)
+    assert abs(ref_c[3] - float(M)) <= 1e-15 * float(M)
+    for args in [(f + 1, cnt - 1, key, lvl), (f, cnt, key ^ 1, lvl), (f, cnt, key >> 3, lvl - 1)]:
+        oc, oq = oracle.cell_moments(pos, mass, t["perm"], *args)
+        assert not (np.array_equal(oc, ref_c) and np.array_equal(oq, ref_q)), args
+
+
+# --------------------------------------------------------------------------
+# the paper's own method on one CPU thread (second CPU reference)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(24))
+def test_leaf_first_reference_equals_oracle(seed):
+    """The sequential leaf-first build (Sec. 2.3, Algorithms 1 and 2, moments
+    combined from the children) gives the oracle's tree bit for bit and its
+    moments to rounding, on adversarial tiny inputs."""
+    rng = _rng(400 + seed)
+    n = int(rng.integers(1, 300))
+    n_leaf = int(rng.integers(1, 20))
+    kind = seed % 4
+    if kind == 0:
+        pos = rng.random((n, 3), dtype=np.float32)
+    elif kind == 1:
+        r = rng.random(n) ** 8 * 0.5
+        v = rng.standard_normal((n, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        pos = np.clip(0.5 + r[:, None] * v, 0, 0.999).astype(np.float32)
+    elif kind == 2:
+        base = rng.random((max(1, n // 10), 3), dtype=np.float32)
+        pos = base[rng.integers(0, base.shape[0], n)]
+    else:
+        pos = (rng.integers(0, 8, (n, 3)) / 8.0 + 2.0 ** -22).astype(np.float32)
+    mass = (rng.random(n) + 0.05).astype(np.float32)
+    a = oracle.build(pos, mass, n_leaf)
+    b = oracle.leaf_first_build(pos, mass, n_leaf)
+    for k in ("perm", "cell_key", "cell_level", "cell_first", "cell_count", "child_ptr",
+              "level_offset"):
+        assert np.array_equal(a[k], b[k]), k
+    lvl = a["cell_level"].astype(np.int64)
+    l = np.ldexp(1.0, -lvl)
+    M = a["com"][:, 3]
+    assert np.max(np.abs(b["com"][:, 3] - M) / M) <= 1e-14
+    assert np.max(np.abs(b["com"][:, :3] - a["com"][:, :3]).max(1) / l) <= 1e-14
+    assert np.max(np.abs(b["quad"] - a["quad"]).max(1) / (M * l * l)) <= 1e-13
+
+
+def test_leaf_first_reference_degenerate():
+    """Empty set, a root leaf, and coincident points (a saturated depth-21 leaf)."""
+    e = oracle.leaf_first_build(np.zeros((0, 3), np.float32), np.zeros(0, np.float32), 4)
+    assert e["n_cells"] == 0
+    pos = _rng(5).random((3, 3), dtype=np.float32)
+    r = oracle.leaf_first_build(pos, np.ones(3, np.float32), 4)
+    assert r["n_cells"] == 1 and r["child_ptr"][0, 0] == -1 and r["cell_key"][0] == 1
+    pos = np.tile(np.array([[0.3, 0.7, 0.1]], np.float32), (40, 1))
+    r = oracle.leaf_first_build(pos, np.full(40, 0.25, np.float32), 8)
+    assert r["n_cells"] == 22 and np.all(r["cell_count"] == 40)
+    assert np.all(r["quad"] == 0.0) and np.all(r["com"][:, 3] == 10.0)
