@@ -78,6 +78,7 @@ extern "C" {
 #define TB_ERR_NONFINITE (-5) /* a position is NaN or infinite (device-detected) */
 #define TB_ERR_MASS (-6)      /* a mass is not finite and positive (device-detected) */
 #define TB_ERR_INTERNAL (-7)  /* a kernel found an inconsistent intermediate (a library bug) */
+#define TB_ERR_SCRATCH (-8)   /* tb_build_noalloc: the build needs more than its fixed scratch */
 
 /* Bits of the device status word. */
 #define TB_STATUS_NONFINITE 1
@@ -160,6 +161,28 @@ int tb_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, con
 int tb_build_sync(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
                   const tb_box *box, uint32_t flags, void *workspace, size_t ws_bytes,
                   const tb_tree *out, void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* A build that allocates nothing, for callers that cannot allocate device
+ * memory or pass a workspace: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, steps and results
+ * as tb_build() without workspace / ws_bytes: the scratch space is a fixed
+ * array of TB_NOALLOC_SCRATCH_BYTES in the library's device memory, one per
+ * GPU, held from the first call on that GPU until the process ends.
+ *   - The call allocates nothing (no hipMalloc, no hipFree, no allocating
+ *     library routine) and performs no host synchronisation.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap in time
+ *     on one GPU (two streams, two threads) race and give wrong results.
+ *     Serialise them, e.g. on one stream.  The build clears what it needs
+ *     cleared itself.
+ *   - The caller still owns pos, mass and every output buffer of `out`.
+ * Errors: as tb_build(), plus TB_ERR_SCRATCH (synchronous, before any launch)
+ * when tb_workspace_bytes() for these arguments exceeds
+ * TB_NOALLOC_SCRATCH_BYTES (64 MiB: about 10^6 particles at n_leaf 16). */
+#define TB_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int tb_build_noalloc(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                     const tb_box *box, uint32_t flags, const tb_tree *out, void *stream);
 
 /* ------------------------------------------------------------------------- */
 /* Batched builds: B independent particle sets in one sequence of launches.

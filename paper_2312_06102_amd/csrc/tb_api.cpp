@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -149,8 +150,8 @@ static std::vector<TraceRec> g_pending;
 static std::map<std::string, TraceAcc> g_acc;
 
 template <class F>
-static hipError_t traced(const char *name, hipStream_t s, F &&f) {
-  if (!g_trace) return f();
+static hipError_t traced(bool on, const char *name, hipStream_t s, F &&f) {
+  if (!on) return f();
   TraceRec r{name, nullptr, nullptr};
   if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return hipErrorOutOfMemory;
   (void)hipEventRecord(r.a, s);
@@ -212,7 +213,7 @@ static bool box_ok(const tb_box &b) {
 static int build_impl(const float *pos, const float *mass, int64_t n, int32_t nsets,
                       int32_t n_leaf, const BatchIn &in, uint32_t flags, void *workspace,
                       size_t ws_bytes, const tb_tree *out, int64_t *cell_offsets,
-                      hipStream_t s) {
+                      hipStream_t s, bool allow_trace = true) {
   int rc = check_sizes(n, n_leaf);
   if (rc) return rc;
   if (nsets < 1 || nsets > kMaxSetsLds) return TB_ERR_ARG;
@@ -221,9 +222,11 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
   if (rc) return rc;
   if (!out || !out->level_offset || !out->n_cells || !out->status) return TB_ERR_ARG;
   if (in.host_box && !box_ok(*in.host_box)) return TB_ERR_BOX;
+  // the timing events are host resources a no-allocation caller must not get
+  const bool trace = allow_trace && g_trace;
   if (n == 0) {
-    return traced("empty", s, [&] { return launch_empty(*out, nsets, in, cell_offsets, s); }) ==
-                   hipSuccess
+    return traced(trace, "empty", s,
+                  [&] { return launch_empty(*out, nsets, in, cell_offsets, s); }) == hipSuccess
                ? TB_OK
                : TB_ERR_HIP;
   }
@@ -239,7 +242,7 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
 
   hipError_t e = hipSuccess;
   auto run = [&](const char *name, auto &&f) {
-    if (e == hipSuccess) e = traced(name, s, f);
+    if (e == hipSuccess) e = traced(trace, name, s, f);
   };
   run("init", [&] { return launch_init(p, w, in, *out, s); });
   run("setup", [&] { return launch_setup(p, w, in, out->status, s); });
@@ -255,6 +258,31 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
   for (int d = kMaxDepth - 1; d >= 0; --d)
     run("parents", [&] { return launch_parents(p, w, d, *out, s); });
   return e == hipSuccess ? TB_OK : TB_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// the build without allocation: workspace in a fixed device array
+// ---------------------------------------------------------------------------
+// Each GPU the library runs on holds its own copy of this array until the
+// process ends.  Host code never uses the array's name as an address: its
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[TB_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, or NULL if it cannot be had.
+static void *scratch_ptr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
 }
 
 static int status_code(int32_t status) {
@@ -326,6 +354,24 @@ int tb_build_sync(const float *pos, const float *mass, int64_t n, int32_t n_leaf
   const int rc = tb_build(pos, mass, n, n_leaf, box, flags, workspace, ws_bytes, out, stream);
   if (rc) return rc;
   return tb::wait_status(out, static_cast<hipStream_t>(stream));
+}
+
+int tb_build_noalloc(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                     const tb_box *box, uint32_t flags, const tb_tree *out, void *stream) {
+  // sizes first: a build that does not fit the array is refused before any
+  // HIP call
+  size_t need = 0;
+  const int rc = tb_workspace_bytes(n, n_leaf, flags, &need);
+  if (rc) return rc;
+  if (need > (size_t)TB_NOALLOC_SCRATCH_BYTES) return TB_ERR_SCRATCH;
+  void *ws = nullptr;
+  if (n > 0) {
+    ws = tb::scratch_ptr();
+    if (!ws) return TB_ERR_HIP;
+  }
+  const tb::BatchIn in{nullptr, box, nullptr, box == nullptr};
+  return tb::build_impl(pos, mass, n, 1, n_leaf, in, flags, ws, TB_NOALLOC_SCRATCH_BYTES, out,
+                        nullptr, static_cast<hipStream_t>(stream), /*traced=*/false);
 }
 
 int tb_build_batched(const float *pos, const float *mass, int64_t n_total, int32_t nsets,

@@ -6,7 +6,7 @@ no CPU fallback: without the native library, or with tensors that are not on a
 GPU, every call raises.
 
 The functions ``tb_max_cells``, ``tb_workspace_bytes``,
-``tb_workspace_bytes_batched``, ``tb_build``, ``tb_build_sync``,
+``tb_workspace_bytes_batched``, ``tb_build``, ``tb_build_sync``, ``tb_build_noalloc``,
 ``tb_build_batched``, ``tb_build_batched_sync``, ``tb_trace_enable``,
 ``tb_trace_read``, ``tb_sort_configs`` and ``tb_version`` mirror the C entry
 points of the same names.  ``Builder`` keeps a workspace and output buffers for
@@ -35,6 +35,7 @@ TB_ERR_HIP = -4
 TB_ERR_NONFINITE = -5
 TB_ERR_MASS = -6
 TB_ERR_INTERNAL = -7
+TB_ERR_SCRATCH = -8
 TB_STATUS_NONFINITE = 1
 TB_STATUS_MASS = 2
 TB_STATUS_INTERNAL = 4
@@ -46,14 +47,15 @@ TB_SORT_LOOKBACK = 1 << 17  # keep the decoupled look-back in every radix pass
 TB_MAX_DEPTH = 21
 TB_MAX_NLEAF = 1024
 TB_MAX_SETS = 16383
+TB_NOALLOC_SCRATCH_BYTES = 64 << 20  # the fixed scratch array of tb_build_noalloc
 
 EXPORTS = ("tb_max_cells", "tb_workspace_bytes", "tb_workspace_bytes_batched", "tb_build",
-           "tb_build_sync", "tb_build_batched", "tb_build_batched_sync", "tb_trace_enable",
+           "tb_build_sync", "tb_build_noalloc", "tb_build_batched", "tb_build_batched_sync", "tb_trace_enable",
            "tb_trace_read", "tb_sort_configs", "tb_version")
 
 _ERRNAMES = {TB_ERR_ARG: "TB_ERR_ARG", TB_ERR_BOX: "TB_ERR_BOX", TB_ERR_WORKSPACE: "TB_ERR_WORKSPACE",
              TB_ERR_HIP: "TB_ERR_HIP", TB_ERR_NONFINITE: "TB_ERR_NONFINITE", TB_ERR_MASS: "TB_ERR_MASS",
-             TB_ERR_INTERNAL: "TB_ERR_INTERNAL"}
+             TB_ERR_INTERNAL: "TB_ERR_INTERNAL", TB_ERR_SCRATCH: "TB_ERR_SCRATCH"}
 
 
 def TB_SORT_CONFIG(k: int) -> int:
@@ -86,7 +88,8 @@ class TreeBuildArgError(TreeBuildError, ValueError):
 
 
 def _raise(code: int, what: str):
-    if code in (TB_ERR_ARG, TB_ERR_BOX, TB_ERR_WORKSPACE, TB_ERR_NONFINITE, TB_ERR_MASS):
+    if code in (TB_ERR_ARG, TB_ERR_BOX, TB_ERR_WORKSPACE, TB_ERR_NONFINITE, TB_ERR_MASS,
+                TB_ERR_SCRATCH):
         raise TreeBuildArgError(code, what)
     raise TreeBuildError(code, what)
 
@@ -110,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
            ctypes.POINTER(TbTree), P]
     lib.tb_build.argtypes = sig
     lib.tb_build_sync.argtypes = sig
+    lib.tb_build_noalloc.argtypes = [P, P, i64, i32, ctypes.POINTER(TbBox), ctypes.c_uint32,
+                                     ctypes.POINTER(TbTree), P]
     lib.tb_workspace_bytes_batched.argtypes = [i64, i32, i32, ctypes.c_uint32,
                                                ctypes.POINTER(ctypes.c_size_t)]
     bsig = [P, P, i64, i32, P, i32, P, ctypes.c_uint32, P, ctypes.c_size_t,
@@ -161,6 +166,16 @@ def tb_build_sync(pos_ptr: int, mass_ptr: int, n: int, n_leaf: int, box: Optiona
                                         int(n_leaf), ctypes.byref(box) if box is not None else None,
                                         int(flags), ctypes.c_void_p(ws_ptr), int(ws_bytes),
                                         ctypes.byref(out), ctypes.c_void_p(stream))
+
+
+def tb_build_noalloc(pos_ptr: int, mass_ptr: int, n: int, n_leaf: int, box: Optional[TbBox],
+                     flags: int, out: TbTree, stream: int) -> int:
+    """Raw call of the build that allocates nothing (scratch in the library's fixed
+    device array); returns the C return code."""
+    return load_library().tb_build_noalloc(ctypes.c_void_p(pos_ptr), ctypes.c_void_p(mass_ptr),
+                                           int(n), int(n_leaf),
+                                           ctypes.byref(box) if box is not None else None,
+                                           int(flags), ctypes.byref(out), ctypes.c_void_p(stream))
 
 
 def tb_workspace_bytes_batched(n_total: int, nsets: int, n_leaf: int, flags: int = TB_FP64) -> int:

@@ -177,3 +177,19 @@ def test_status_bits_distinct():
                     tb.TB_STATUS_SETS, tb.TB_STATUS_BOX]
     assert len(set(bits)) == 5 and all(b & (b - 1) == 0 for b in bits)
     assert int(re.search(r"#define TB_MAX_SETS (\d+)", text).group(1)) == tb.TB_MAX_SETS
+
+
+def test_noalloc_rejects_oversize_on_the_host():
+    """The build without allocation refuses a build whose workspace would not fit
+    its fixed array before any HIP call (fake pointers, no GPU here), and checks
+    its other arguments like tb_build."""
+    t = _fake_tree()
+    box = tb.TbBox()
+    box.side = 1.0
+    n = 1 << 24
+    assert tb.tb_workspace_bytes(n, 16) > tb.TB_NOALLOC_SCRATCH_BYTES
+    assert tb.tb_build_noalloc(0x10, 0x20, n, 16, box, 0, t, 0) == tb.TB_ERR_SCRATCH
+    assert tb.tb_build_noalloc(0x10, 0x20, 100, 0, box, 0, t, 0) == tb.TB_ERR_ARG
+    assert tb.tb_build_noalloc(0x10, 0x20, 100, 16, box, 99, t, 0) == tb.TB_ERR_ARG
+    m = re.search(r"#define TB_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == tb.TB_NOALLOC_SCRATCH_BYTES
