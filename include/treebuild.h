@@ -238,6 +238,48 @@ int tb_build_batched_sync(const float *pos, const float *mass, int64_t n_total, 
                           int64_t *cell_offsets, void *stream);
 
 /* ------------------------------------------------------------------------- */
+/* Gravity on the tree (Sec. 2.1): Barnes-Hut accelerations and potentials of
+ * every particle, G = 1, from an FP64 tree that tb_build() made.
+ *
+ * Groups (Barnes' modified algorithm, Sec. 2.1): going down from the root, the
+ * first cell on each path that holds at most n_crit particles, or is a leaf, is
+ * a group, and its particles share one interaction list.  A cell C is accepted
+ * for group G when it is neither G nor an ancestor of G and l_C < theta * d
+ * (eq. 1), d the distance from C's centre of mass to the closest point of G's
+ * cube; otherwise it is opened: a leaf contributes its particles, an internal
+ * cell its children.  Terms, with r = x_i - x_C:
+ *   accepted cell  phi = -M / r - (r.Q.r) / (2 r^5),
+ *                  a = -M r / r^3 + Q r / r^5 - 5/2 (r.Q.r) r / r^7
+ *                  (the Q terms with TB_GRAV_QUADRUPOLE, else monopole only);
+ *   particle j     phi = -m_j / s, a = -m_j (x_i - x_j) / s^3,
+ *                  s = (|x_i - x_j|^2 + eps^2)^(1/2), j != i.
+ * Evaluated in FP64.
+ *
+ *   pos_sorted, mass_sorted  [N][3], [N] float, DEVICE: the particles in key
+ *               order (tb_build's pos_sorted / mass_sorted outputs)
+ *   tree        host pointer to the tb_tree of that build (TB_FP64 moments);
+ *               box_out must have been filled; n_cells is read on the device
+ *   c_max       tb_max_cells() of that build (bounds the cells examined)
+ *   theta       opening angle (>= 0; 0 opens everything: direct summation)
+ *   n_crit      group size (>= 1)
+ *   eps         Plummer softening of the particle terms (>= 0)
+ *   flags       0 or TB_GRAV_QUADRUPOLE
+ *   acc         [N][4] double, DEVICE, out: ax, ay, az, phi in key order
+ *   stats       [2] int64, DEVICE, or NULL: number of groups, and number of
+ *               interactions (cell terms plus particle pairs) over all particles
+ *   workspace   DEVICE, at least tb_gravity_workspace_bytes(c_max) bytes
+ * Asynchronous on `stream`.  A group whose walk outgrows the kernel's 4096-cell
+ * LDS stack sets TB_STATUS_INTERNAL in tree->status.
+ * Errors (synchronous): TB_ERR_ARG, TB_ERR_WORKSPACE, TB_ERR_HIP. */
+#define TB_GRAV_QUADRUPOLE 1u
+
+int tb_gravity_workspace_bytes(int64_t c_max, size_t *bytes);
+
+int tb_gravity(const float *pos_sorted, const float *mass_sorted, int64_t n, const tb_tree *tree,
+               int64_t c_max, double theta, int32_t n_crit, double eps, uint32_t flags,
+               double *acc, int64_t *stats, void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Kernel timing.  When enabled, every kernel launch of a build is bracketed by
  * HIP events recorded on the build's stream; the per-kernel durations are
  * summed when tb_trace_read() is called (which synchronises on the events).

@@ -10,8 +10,9 @@ build (Sec. 2.1) over hashed Morton keys (Sec. 2.2) with direct FP64 moment
 sums per cell; see the header comment there for each step and its source.
 ``tb_leaffirst.c`` is a second CPU reference: the paper's own leaf-first
 method (Sec. 2.3, Algorithms 1 and 2) on one thread, moments combined from the
-children as cells are created.  ``build_library()`` compiles both with gcc into
-``liboracle.so`` next to them.
+children as cells are created.  ``tb_gravity.c`` holds the gravity references
+(Sec. 2.1): O(N^2) direct summation and a sequential Barnes-Hut group walk.
+``build_library()`` compiles all three with gcc into ``liboracle.so``.
 """
 from __future__ import annotations
 
@@ -25,6 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "tb_oracle.c")
 LEAF_FIRST_SRC = os.path.join(_HERE, "tb_leaffirst.c")
+GRAVITY_SRC = os.path.join(_HERE, "tb_gravity.c")
 LIB = os.path.join(_HERE, "liboracle.so")
 
 # Strict IEEE FP64: no contraction into FMA, no fast-math reassociation.
@@ -36,10 +38,13 @@ MAX_DEPTH = 21
 _lib = None
 
 
-def build_library(src: str = SRC, out: str = LIB, extra_flags=()) -> str:
+def build_library(src: str = SRC, out: str = LIB, extra_flags=(), gravity_src: str = GRAVITY_SRC
+                  ) -> str:
     """Compile the oracle C source (``src``, normally tb_oracle.c) together with
-    the leaf-first reference into a shared library (gcc)."""
-    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", out + ".tmp", src, LEAF_FIRST_SRC, "-lm"]
+    the leaf-first reference and the gravity references into a shared library
+    (gcc)."""
+    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", out + ".tmp", src, LEAF_FIRST_SRC, gravity_src,
+           "-lm"]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     os.replace(out + ".tmp", out)
     return out
@@ -61,6 +66,14 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.tbo_cell_moments.argtypes = [P, P, P, ctypes.c_double, P, i64, i64,
                                      ctypes.c_uint64, ctypes.c_int, P, P]
     lib.tbo_cell_moments.restype = ctypes.c_int
+    lib.tbg_direct.argtypes = [P, P, i64, ctypes.c_double, P]
+    lib.tbg_direct.restype = ctypes.c_int
+    lib.tbg_direct_subset.argtypes = [P, P, i64, ctypes.c_double, P, i64, P]
+    lib.tbg_direct_subset.restype = ctypes.c_int
+    lib.tbg_walk_tree.argtypes = [P, P, P, i64] + [P] * 7 + [P, ctypes.c_double, ctypes.c_double,
+                                                             ctypes.c_int32, ctypes.c_double,
+                                                             ctypes.c_int, P, P]
+    lib.tbg_walk_tree.restype = ctypes.c_int
     lib.tbo_auto_box.argtypes = [P, i64, P, P]
     lib.tbo_auto_box.restype = ctypes.c_int
     return lib
@@ -72,7 +85,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     if path is not None:
         return _bind(ctypes.CDLL(path))
     if _lib is None:
-        if not os.path.exists(LIB):
+        sources = (SRC, LEAF_FIRST_SRC, GRAVITY_SRC)
+        if not os.path.exists(LIB) or any(os.path.getmtime(f) > os.path.getmtime(LIB)
+                                           for f in sources):
             build_library()
         _lib = _bind(ctypes.CDLL(LIB))
     return _lib
@@ -212,6 +227,55 @@ def cell_moments(pos, mass, perm, first: int, count: int, key: int, level: int,
     if rc:
         raise OracleError(rc)
     return com, quad
+
+
+def direct_forces(pos, mass, eps: float = 0.0, lib=None) -> np.ndarray:
+    """O(N^2) direct summation (Sec. 2.1), FP64: [N][4] = (ax, ay, az, phi) in input
+    order, G = 1, Plummer softening eps, no self term."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+    acc = np.zeros((pos.shape[0], 4), dtype=np.float64)
+    rc = lib.tbg_direct(_ptr(pos), _ptr(mass), pos.shape[0], float(eps), _ptr(acc))
+    if rc:
+        raise OracleError(rc)
+    return acc
+
+
+def direct_forces_at(pos, mass, idx, eps: float = 0.0, lib=None) -> np.ndarray:
+    """Direct summation for the particles idx only: [len(idx)][4] (ax, ay, az, phi)."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+    idx = np.ascontiguousarray(idx, dtype=np.int64).reshape(-1)
+    acc = np.zeros((idx.shape[0], 4), dtype=np.float64)
+    rc = lib.tbg_direct_subset(_ptr(pos), _ptr(mass), pos.shape[0], float(eps), _ptr(idx),
+                               idx.shape[0], _ptr(acc))
+    if rc:
+        raise OracleError(rc)
+    return acc
+
+
+def walk_forces(pos, mass, tree: dict, theta: float = 0.75, n_crit: int = 512, eps: float = 0.0,
+                quadrupole: bool = True, lo=(0.0, 0.0, 0.0), side: float = 1.0, lib=None):
+    """Sequential Barnes-Hut group walk over an oracle tree (build() output).
+    Returns (acc [N][5] in sorted order: ax, ay, az, phi, sum of |terms|,
+    stats dict with the number of groups and interactions)."""
+    lib = lib or load()
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
+    n = pos.shape[0]
+    lo, side = _box(lo, side)
+    acc = np.zeros((n, 5), dtype=np.float64)
+    stats = np.zeros(2, dtype=np.int64)
+    arrs = [np.ascontiguousarray(tree[k]) for k in ("perm", "cell_key", "cell_level", "cell_first",
+                                                    "cell_count", "child_ptr", "com", "quad")]
+    rc = lib.tbg_walk_tree(_ptr(pos), _ptr(mass), _ptr(arrs[0]), n, *[_ptr(a) for a in arrs[1:]],
+                           _ptr(lo), side, float(theta), int(n_crit), float(eps),
+                           1 if quadrupole else 0, _ptr(acc), _ptr(stats))
+    if rc:
+        raise OracleError(rc)
+    return acc, {"groups": int(stats[0]), "interactions": int(stats[1])}
 
 
 def auto_box(pos, lib=None):

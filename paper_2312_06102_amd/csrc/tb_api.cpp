@@ -394,6 +394,32 @@ int tb_build_batched_sync(const float *pos, const float *mass, int64_t n_total, 
   return tb::wait_status(out, static_cast<hipStream_t>(stream));
 }
 
+int tb_gravity_workspace_bytes(int64_t c_max, size_t *bytes) {
+  if (!bytes || c_max < 0 || c_max > 2147483647LL) return TB_ERR_ARG;
+  *bytes = tb::gravity_workspace_bytes(c_max);
+  return TB_OK;
+}
+
+int tb_gravity(const float *pos_sorted, const float *mass_sorted, int64_t n, const tb_tree *tree,
+               int64_t c_max, double theta, int32_t n_crit, double eps, uint32_t flags,
+               double *acc, int64_t *stats, void *workspace, size_t ws_bytes, void *stream) {
+  if (n < 0 || n > TB_MAX_N || c_max < 0 || c_max > 2147483647LL || n_crit < 1) return TB_ERR_ARG;
+  if (!(theta >= 0.0) || !std::isfinite(theta) || !(eps >= 0.0) || !std::isfinite(eps))
+    return TB_ERR_ARG;
+  if (flags & ~TB_GRAV_QUADRUPOLE) return TB_ERR_ARG;
+  if (!tree) return TB_ERR_ARG;
+  if (n == 0) return TB_OK;
+  if (!pos_sorted || !mass_sorted || !acc || !tree->cell_key || !tree->cell_level ||
+      !tree->cell_first || !tree->cell_count || !tree->child_ptr || !tree->com || !tree->quad ||
+      !tree->n_cells || !tree->box_out || !tree->status || c_max < 1)
+    return TB_ERR_ARG;
+  if (!workspace || ws_bytes < tb::gravity_workspace_bytes(c_max)) return TB_ERR_WORKSPACE;
+  tb::GravIn in{pos_sorted, mass_sorted, n, tree, c_max, theta, eps, n_crit,
+                (flags & TB_GRAV_QUADRUPOLE) != 0, acc, stats, workspace};
+  return tb::launch_gravity(in, static_cast<hipStream_t>(stream)) == hipSuccess ? TB_OK
+                                                                               : TB_ERR_HIP;
+}
+
 int tb_trace_enable(int on) {
   tb::g_trace = on != 0;
   return TB_OK;

@@ -177,6 +177,23 @@ size_t cell_lds_limit();
 hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
                           hipStream_t s);
 
+// tb_gravity.hip
+struct GravIn {
+  const float *pos_sorted;  // [n][3] device, key order
+  const float *mass_sorted; // [n] device, key order
+  int64_t n;
+  const tb_tree *tree;      // an FP64 build's outputs (box_out required)
+  int64_t c_max;
+  double theta, eps;
+  int32_t n_crit;
+  bool quadrupole;
+  double *acc;              // [n][4] device: ax, ay, az, phi in key order
+  int64_t *stats;           // [2] device or NULL: groups, interactions
+  void *workspace;          // int32 [c_max] groups + u32 counter
+};
+hipError_t launch_gravity(const GravIn &in, hipStream_t s);
+size_t gravity_workspace_bytes(int64_t c_max);
+
 // The sorted keys, recomputed from the sorted particles by the reorder pass (the
 // sort passes themselves stop carrying the key once its bits are consumed).
 inline uint64_t *sorted_keys(const Plan &, const Work &w) { return w.keys0; }

@@ -48,9 +48,11 @@ TB_MAX_DEPTH = 21
 TB_MAX_NLEAF = 1024
 TB_MAX_SETS = 16383
 TB_NOALLOC_SCRATCH_BYTES = 64 << 20  # the fixed scratch array of tb_build_noalloc
+TB_GRAV_QUADRUPOLE = 1
 
 EXPORTS = ("tb_max_cells", "tb_workspace_bytes", "tb_workspace_bytes_batched", "tb_build",
-           "tb_build_sync", "tb_build_noalloc", "tb_build_batched", "tb_build_batched_sync", "tb_trace_enable",
+           "tb_build_sync", "tb_build_noalloc", "tb_gravity_workspace_bytes", "tb_gravity",
+           "tb_build_batched", "tb_build_batched_sync", "tb_trace_enable",
            "tb_trace_read", "tb_sort_configs", "tb_version")
 
 _ERRNAMES = {TB_ERR_ARG: "TB_ERR_ARG", TB_ERR_BOX: "TB_ERR_BOX", TB_ERR_WORKSPACE: "TB_ERR_WORKSPACE",
@@ -115,6 +117,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_build_sync.argtypes = sig
     lib.tb_build_noalloc.argtypes = [P, P, i64, i32, ctypes.POINTER(TbBox), ctypes.c_uint32,
                                      ctypes.POINTER(TbTree), P]
+    lib.tb_gravity_workspace_bytes.argtypes = [i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.tb_gravity.argtypes = [P, P, i64, ctypes.POINTER(TbTree), i64, ctypes.c_double, i32,
+                               ctypes.c_double, ctypes.c_uint32, P, P, P, ctypes.c_size_t, P]
     lib.tb_workspace_bytes_batched.argtypes = [i64, i32, i32, ctypes.c_uint32,
                                                ctypes.POINTER(ctypes.c_size_t)]
     bsig = [P, P, i64, i32, P, i32, P, ctypes.c_uint32, P, ctypes.c_size_t,
@@ -176,6 +181,25 @@ def tb_build_noalloc(pos_ptr: int, mass_ptr: int, n: int, n_leaf: int, box: Opti
                                            int(n), int(n_leaf),
                                            ctypes.byref(box) if box is not None else None,
                                            int(flags), ctypes.byref(out), ctypes.c_void_p(stream))
+
+
+def tb_gravity_workspace_bytes(c_max: int) -> int:
+    out = ctypes.c_size_t(0)
+    rc = load_library().tb_gravity_workspace_bytes(int(c_max), ctypes.byref(out))
+    if rc:
+        _raise(rc, "tb_gravity_workspace_bytes")
+    return out.value
+
+
+def tb_gravity(pos_ptr: int, mass_ptr: int, n: int, tree: TbTree, c_max: int, theta: float,
+               n_crit: int, eps: float, flags: int, acc_ptr: int, stats_ptr: Optional[int],
+               ws_ptr: int, ws_bytes: int, stream: int) -> int:
+    """Raw call of the tree walk: device pointers as ints; returns the C code."""
+    return load_library().tb_gravity(ctypes.c_void_p(pos_ptr), ctypes.c_void_p(mass_ptr), int(n),
+                                     ctypes.byref(tree), int(c_max), float(theta), int(n_crit),
+                                     float(eps), int(flags), ctypes.c_void_p(acc_ptr),
+                                     ctypes.c_void_p(stats_ptr), ctypes.c_void_p(ws_ptr),
+                                     int(ws_bytes), ctypes.c_void_p(stream))
 
 
 def tb_workspace_bytes_batched(n_total: int, nsets: int, n_leaf: int, flags: int = TB_FP64) -> int:
@@ -410,6 +434,35 @@ class Builder(_Graphable):
         if o.key_sorted is not None:
             res["key_sorted"] = o.key_sorted[:self.n]
         return res
+
+
+    def gravity(self, theta: float = 0.75, n_crit: int = 512, eps: float = 0.0,
+                quadrupole: bool = True, stream=None):
+        """Barnes-Hut accelerations and potentials (tb_gravity) from the last
+        build, which must be FP64 with sorted_particles=True.  Returns
+        (acc [N][4] float64 device tensor in key order: ax, ay, az, phi;
+        stats dict with the number of groups and of interactions)."""
+        if self.precision != "fp64" or self.out.pos_sorted is None:
+            raise ValueError("gravity needs an FP64 Builder with sorted_particles=True")
+        c_max = max(tb_max_cells(self.n, self.n_leaf), 1)
+        if getattr(self, "_grav_ws", None) is None:
+            self._grav_ws_bytes = tb_gravity_workspace_bytes(c_max)
+            self._grav_ws = torch.empty(self._grav_ws_bytes, dtype=torch.uint8,
+                                        device=self.workspace.device)
+        acc = torch.empty((max(self.n, 1), 4), dtype=torch.float64, device=self.workspace.device)
+        stats = torch.zeros(2, dtype=torch.int64, device=self.workspace.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = tb_gravity(self.out.pos_sorted.data_ptr(), self.out.mass_sorted.data_ptr(), self.n,
+                        self._struct, c_max, theta, n_crit, eps,
+                        TB_GRAV_QUADRUPOLE if quadrupole else 0, acc.data_ptr(),
+                        stats.data_ptr(), self._grav_ws.data_ptr(), self._grav_ws_bytes,
+                        s.cuda_stream)
+        if rc:
+            _raise(rc, "tb_gravity")
+        torch.cuda.synchronize()
+        _check_status(int(self.out.status.item()), "tb_gravity")
+        st = stats.cpu().tolist()
+        return acc[:self.n], {"groups": st[0], "interactions": st[1]}
 
 
 def build(pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 16, box=None,

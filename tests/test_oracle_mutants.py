@@ -145,3 +145,87 @@ def test_planted_mistake_is_caught(tmp_path, name):
     assert text.count(old) == 1, f"mutation site for {name} not found exactly once"
     lib = _compile(tmp_path, name, text.replace(old, new))
     assert _pin_checks(lib), f"no pin caught the planted mistake {name}"
+
+
+# --------------------------------------------------------------------------
+# the gravity references (tb_gravity.c)
+# --------------------------------------------------------------------------
+
+GRAVITY_MUTANTS = {
+    "quad_sign": ("t[q] += Qr[q] * rinv5 - 2.5 * rQr * r[q] * rinv7;",
+                  "t[q] -= Qr[q] * rinv5 - 2.5 * rQr * r[q] * rinv7;"),
+    "quad_coefficient": ("t[q] += Qr[q] * rinv5 - 2.5 * rQr * r[q] * rinv7;",
+                         "t[q] += Qr[q] * rinv5 - 1.5 * rQr * r[q] * rinv7;"),
+    "expansion_about_centre": ("r[q] = xi[q] - (cen[q] + w->com[4 * c + q]);",
+                               "r[q] = xi[q] - cen[q];"),
+    "open_criterion_side": ("if (l * l < w->theta * w->theta * d2) {",
+                            "if (l < w->theta * w->theta * d2) {"),
+    "self_term": ("if (j == s) continue;", "if (j == s && 0) continue;"),
+    "direct_sign": ("ax -= (double)mass[j] * dx * rinv3;", "ax += (double)mass[j] * dx * rinv3;"),
+}
+
+
+def _gravity_pins(lib):
+    import test_gravity_oracle as tg
+    failures = []
+    pos, mass = tg.dg.plummer(2500, seed=13)
+    tree = oracle.build(pos, mass, 10, lib=lib)
+    direct = oracle.direct_forces(pos, mass, eps=1e-4, lib=lib)[tree["perm"]]
+
+    def check(name, fn):
+        try:
+            fn()
+        except Exception:
+            failures.append(name)
+
+    def newton():
+        acc = oracle.direct_forces(pos, mass, eps=1e-4, lib=lib)
+        m = mass.astype(np.float64)[:, None]
+        assert np.all(np.abs((m * acc[:, :3]).sum(0)) <= 1e-12 * (m * np.abs(acc[:, :3])).sum(0))
+        two = oracle.direct_forces(np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]], np.float32),
+                                   np.array([0.5, 0.25], np.float32), lib=lib)
+        assert two[0, 0] > 0 and two[1, 0] < 0  # attraction
+
+    def theta_zero():
+        w, _ = oracle.walk_forces(pos, mass, tree, theta=0.0, n_crit=256, eps=1e-4, lib=lib)
+        assert np.all(np.linalg.norm(w[:, :3] - direct[:, :3], axis=1) <= 1e-12 * w[:, 4])
+
+    def accuracy():
+        med = {}
+        for quad in (False, True):
+            w, _ = oracle.walk_forces(pos, mass, tree, theta=0.5, n_crit=256, eps=1e-4,
+                                      quadrupole=quad, lib=lib)
+            err = np.linalg.norm(w[:, :3] - direct[:, :3], axis=1) / np.linalg.norm(
+                direct[:, :3], axis=1)
+            med[quad] = np.median(err)
+        assert med[False] < 2e-3 and med[True] <= 0.5 * med[False], med
+
+    def dumbbell():
+        e = tg.dumbbell_errors(lib=lib)
+        assert e[True][0] < 1e-7 and e[True][1] < 1e-7 and e[False][0] > 1e-5, e
+
+    check("newton", newton)
+    check("theta_zero", theta_zero)
+    check("dumbbell", dumbbell)
+    check("accuracy", accuracy)
+    return failures
+
+
+def test_unmodified_gravity_passes_pins(tmp_path):
+    src = tmp_path / "grav.c"
+    src.write_text(open(oracle.GRAVITY_SRC).read())
+    out = str(tmp_path / "libgrav.so")
+    oracle.build_library(out=out, gravity_src=str(src))
+    assert _gravity_pins(oracle.load(out)) == []
+
+
+@pytest.mark.parametrize("name", sorted(GRAVITY_MUTANTS))
+def test_planted_gravity_mistake_is_caught(tmp_path, name):
+    old, new = GRAVITY_MUTANTS[name]
+    text = open(oracle.GRAVITY_SRC).read()
+    assert text.count(old) == 1, f"mutation site for {name} not found exactly once"
+    src = tmp_path / f"{name}.c"
+    src.write_text(text.replace(old, new))
+    out = str(tmp_path / f"lib{name}.so")
+    oracle.build_library(out=out, gravity_src=str(src))
+    assert _gravity_pins(oracle.load(out)), f"no pin caught the planted mistake {name}"
