@@ -161,7 +161,7 @@ GRAVITY_MUTANTS = {
     "open_criterion_side": ("if (l * l < w->theta * w->theta * d2) {",
                             "if (l < w->theta * w->theta * d2) {"),
     "self_term": ("if (j == s) continue;", "if (j == s && 0) continue;"),
-    "direct_sign": ("ax -= (double)mass[j] * dx * rinv3;", "ax += (double)mass[j] * dx * rinv3;"),
+    "direct_sign": ("    acc[4 * i + 0] = ax;", "    acc[4 * i + 0] = -ax;"),
 }
 
 
