@@ -28,9 +28,6 @@ constexpr int kCellThreads = 256;
 constexpr int kCellIpt = 8;
 constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
 
-// Parent kernel: children staged per workgroup step.
-constexpr int kParentThreads = 256;
-constexpr int kParentChunk = kParentThreads;
 constexpr int64_t kCountedMaxTiles = 4096;  // largest sort grid with counted passes
 
 // Bounding-box chunks (auto box only).
@@ -41,6 +38,9 @@ constexpr int kMaxSetsLds = TB_MAX_SETS;
 // Coarse set table of the set-id passes: the set holding every 2^shift-th
 // position, at most kCoarse + 1 entries.
 constexpr int kCoarse = 4096;
+
+// counters[kUpperCounter + d]: number of cells above the blocks at depth d
+constexpr int kUpperCounter = 32;
 
 // Lookback status word: flag in bits 63:62, value in bits 31:0.
 constexpr uint64_t kFlagAggregate = 1ull << 62;
@@ -73,6 +73,7 @@ struct Plan {
   int64_t cell_tiles;   // upper bound of the cell tiles of all sets
   int64_t bbox_chunks;  // upper bound of the bounding-box chunks of all sets
   int64_t c_max;
+  int64_t upper_cap;    // cells above the blocks, per depth: at most n / (n_serial + 1) + B
   // offsets
   size_t keys0, keys1;  // u64 [n] ping-pong key buffers
   size_t vals1;         // u32 [n] payload buffer (the other one is out->perm)
@@ -94,12 +95,12 @@ struct Plan {
   size_t set_tot;       // u32 [B][kLevels] cells of each set and depth
   size_t set_cells;     // i64 [B + 1] first cell of each set; [B] = all cells
   size_t lvl_off;       // i64 [B][kLevels + 1] first cell of each depth of each set
-  size_t par_start;     // i64 [kLevels][B + 1] parent-pass chunks per depth and set
   size_t coarse;        // u32 [kCoarse + 1] set holding position k << coarse_shift
   size_t packed;        // f32x4 [n] (x, y, z, m) records in original order
   size_t sorted;        // f32x4 [n] the same records in key order
   size_t ad;            // u16 [n] a_i | D_i << 8 of every particle in key order
-  size_t head_parent;   // i32 [c_max] parent slot of every first child
+  size_t blk;           // u8 [n] root depth of the block a particle starts, or 0xff
+  size_t upper;         // i32 [kLevels][upper_cap] slots of the cells above the blocks
   size_t m_lo;          // f32 [c_max] compensation of each cell mass (mixed precision)
   size_t total;
 };
@@ -128,12 +129,12 @@ struct Work {
   uint32_t *set_tot;
   int64_t *set_cells;
   int64_t *lvl_off;
-  int64_t *par_start;
   uint32_t *coarse;
   float4 *packed;
   float4 *sorted;
   uint16_t *ad;
-  int32_t *head_parent;
+  uint8_t *blk;
+  int32_t *upper;
   float *m_lo;
 };
 
@@ -170,12 +171,12 @@ bool sort_config_supported(const SortConfig &c);
 hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
                             int64_t *cell_offsets, hipStream_t s);
 hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
-hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
-size_t cell_emit_lds(int nl);
 size_t cell_lds_limit();
-// tb_parents.hip
-hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
-                          hipStream_t s);
+size_t cell_reorder_lds(int nl);
+// tb_blocks.hip
+hipError_t launch_blocks(const Plan &p, const Work &w, hipStream_t s);
+hipError_t launch_block_build(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
+hipError_t launch_upper(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
 
 // tb_gravity.hip
 struct GravIn {

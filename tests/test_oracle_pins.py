@@ -452,3 +452,66 @@ def test_leaf_first_reference_degenerate():
     r = oracle.leaf_first_build(pos, np.full(40, 0.25, np.float32), 8)
     assert r["n_cells"] == 22 and np.all(r["cell_count"] == 40)
     assert np.all(r["quad"] == 0.0) and np.all(r["com"][:, 3] == 10.0)
+
+
+# --------------------------------------------------------------------------
+# subtree-rooted build (Sec. 2.3.3, eq. 2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(30))
+def test_subtree_rooted_build_equals_oracle(seed):
+    """Blocks of at most n_serial particles, each built alone with the leaf depth
+    of eq. 2 (d_root), plus the cells above the block roots, give exactly the
+    oracle's tree; every block is one of its cells."""
+    rng = _rng(500 + seed)
+    n = int(rng.integers(1, 400))
+    n_leaf = int(rng.integers(1, 12))
+    n_serial = int(rng.integers(n_leaf, 4 * n_leaf + 30))
+    kind = seed % 4
+    if kind == 0:
+        pos = rng.random((n, 3), dtype=np.float32)
+    elif kind == 1:
+        r = rng.random(n) ** 8 * 0.5
+        v = rng.standard_normal((n, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        pos = np.clip(0.5 + r[:, None] * v, 0, 0.999).astype(np.float32)
+    elif kind == 2:
+        base = rng.random((max(1, n // 12), 3), dtype=np.float32)
+        pos = base[rng.integers(0, base.shape[0], n)]
+    else:
+        pos = (rng.integers(0, 8, (n, 3)) / 8.0 + 2.0 ** -22).astype(np.float32)
+    t = oracle.build(pos, np.ones(n, np.float32), n_leaf, moments=False)
+    _, keys = oracle.keys(pos)
+    sk = keys[t["perm"]]
+    cells = tc.subtree_build(sk, n_leaf, n_serial)
+    assert len(cells) == t["n_cells"]
+    index = {(int(t["cell_level"][c]), int(t["cell_key"][c])): c for c in range(t["n_cells"])}
+    for (d, k), cl in cells.items():
+        c = index[(d, k)]
+        assert cl["first"] == t["cell_first"][c] and cl["count"] == t["cell_count"][c]
+        assert cl["leaf"] == (t["child_ptr"][c, 0] < 0)
+        if not cl["leaf"]:
+            f, m = t["child_ptr"][c]
+            assert [int(x) for x in t["cell_key"][f:f + m]] == cl["children"]
+    for s, e, d_root in tc.subtree_blocks(sk, n_serial):
+        c = index[(d_root, tc.prefix_key(int(sk[s]), d_root))]
+        assert t["cell_first"][c] == s and t["cell_count"][c] == e - s
+        assert e - s <= n_serial or d_root == 21
+
+
+def test_eq2_needs_d_root():
+    """Without the d_root term, a block of at most n_leaf particles read on its own
+    has neither neighbour term (its first particle has no left neighbour inside
+    the block and no particle n_leaf places further), so it would become a leaf
+    at depth 0 instead of the leaf at the block root."""
+    rng = _rng(77)
+    pos = rng.random((300, 3), dtype=np.float32)
+    t = oracle.build(pos, np.ones(300, np.float32), 4, moments=False)
+    _, keys = oracle.keys(pos)
+    sk = keys[t["perm"]]
+    blocks = tc.subtree_blocks(sk, 20)
+    s, e, d_root = next(b for b in blocks if b[2] > 0 and b[1] - b[0] <= 4)
+    with_root = tc.leaves_in_block(sk[s:e], 4, d_root)
+    without = tc.leaves_in_block(sk[s:e], 4, 0)
+    assert with_root == [(d_root, tc.prefix_key(int(sk[s]), d_root), 0, e - s)]
+    assert without == [(0, 1, 0, e - s)]

@@ -280,3 +280,83 @@ def check_invariants(tree: dict, sorted_keys: np.ndarray, n_leaf: int):
     parent_count = np.zeros(C, dtype=np.int64)
     np.add.at(parent_count, ch, 1)
     assert parent_count[0] == 0 and np.all(parent_count[1:] == 1)
+
+
+# ---------------------------------------------------------------------------
+# subtree-rooted build (Sec. 2.3.3, eq. 2), sequentially
+# ---------------------------------------------------------------------------
+
+def subtree_blocks(sorted_keys, n_serial: int):
+    """Sec. 2.3.3: divide the sorted keys recursively into blocks until each block
+    is a subtree of at most n_serial particles, splitting a range by the next
+    3-bit digit of its keys (so no two blocks share a cell).  A range of
+    identical keys at depth 21 cannot be divided and stays one block.
+    Returns [(first, end, d_root)] in key order."""
+    keys = [int(x) for x in sorted_keys]
+    out = []
+
+    def divide(s, e, d):
+        if e - s <= n_serial or d == MAX_DEPTH:
+            out.append((s, e, d))
+            return
+        k = s
+        while k < e:
+            p = prefix_key(keys[k], d + 1)
+            j = k
+            while j < e and prefix_key(keys[j], d + 1) == p:
+                j += 1
+            divide(k, j, d + 1)
+            k = j
+
+    if keys:
+        divide(0, len(keys), 0)
+    return out
+
+
+def leaves_in_block(block_keys, n_leaf: int, d_root: int):
+    """The leaves of one block, read off its own sorted keys as Sec. 2.3.1 does
+    for the whole set, with the leaf depth of eq. 2:
+        D_k = max(minDepth(k, k-1), minDepth(k, k + n_leaf), d_root)
+    where the two neighbours count only inside the block (capped at depth 21).
+    Returns [(depth, key, first, count)] with first relative to the block."""
+    keys = [int(x) for x in block_keys]
+    n = len(keys)
+    out = []
+    k = 0
+    while k < n:
+        left = min_depth(keys[k - 1], keys[k]) if k > 0 else 0
+        right = min_depth(keys[k], keys[k + n_leaf]) if k + n_leaf < n else 0
+        depth = min(max(left, right, d_root), MAX_DEPTH)
+        prefix = prefix_key(keys[k], depth)
+        stop = k + 1
+        while stop < n and prefix_key(keys[stop], depth) == prefix:
+            stop += 1
+        out.append((depth, prefix, k, stop - k))
+        k = stop
+    return out
+
+
+def subtree_build(sorted_keys, n_leaf: int, n_serial: int):
+    """All cells by the subtree-rooted method: every block builds its own leaves
+    (eq. 2) and its parents up to its root, independently; the cells above the
+    block roots are then built from the roots, bottom-up (Sec. 2.3.3).
+    Returns {(depth, key): dict(first, count, children, leaf)} like
+    parents_bottom_up."""
+    cells = {}
+    roots = []
+    for s, e, d_root in subtree_blocks(sorted_keys, n_serial):
+        leaves = [(d, key, s + f, c) for d, key, f, c in
+                  leaves_in_block(sorted_keys[s:e], n_leaf, d_root)]
+        sub = parents_bottom_up(leaves)
+        # the block's cells stop at its root
+        for (d, key), cl in sub.items():
+            if d >= d_root:
+                cells[(d, key)] = cl
+        root_key = prefix_key(int(sorted_keys[s]), d_root)
+        roots.append((d_root, root_key, s, e - s))
+    # upper cells: the block roots play the part of leaves for the cells above
+    upper = parents_bottom_up(roots)
+    for (d, key), cl in upper.items():
+        if not cl["leaf"]:
+            cells[(d, key)] = cl
+    return cells
