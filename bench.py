@@ -69,7 +69,10 @@ def parse():
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched4096: skip the 4096 sequential single-set builds")
     ap.add_argument("--no-compare", action="store_true",
-                    help="mixed16m: skip the FP64 build on the same data")
+                    help="mixed16m: skip the FP64 build on the same data; single sets: skip "
+                         "timing the subtree-rooted cell build on the same data")
+    ap.add_argument("--subtrees", action="store_true",
+                    help="time the subtree-rooted cell build (TB_SUBTREES) as the step")
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="particles of the workload the oracle builds for the CPU baseline "
                          "(default: all of a single set up to 2^24, the first 2^24 of a larger "
@@ -135,6 +138,11 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: i
                 moments per leaf
     parents     per child cell read key 8 + count 4 + moments; per parent read head 4,
                 write count 4 + child count 4 + moments
+    (with TB_SUBTREES, in place of cell_emit and parents:)
+    blocks      read sorted keys 8; write the block-start byte 1
+    block_build read sorted keys 8 + block-start byte 1 + sorted record 16 per particle;
+                write key 8, depth 1, first 4, child link 8, count 4 + moments per cell
+    upper       (the cells above the blocks: a few thousand, not counted)
     moments: FP64 80 B (com 32 + quad 48); mixed 44 B (com 16 + quad 24 + mass term 4)
     """
     mom = 80 if precision == "fp64" else 44
@@ -153,6 +161,8 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: i
         "reorder": 46 * n,
         "cell_emit": 26 * n + 25 * cells + (4 + mom) * leaves,
         "parents": (12 + mom) * max(cells - 1, 0) + (12 + mom) * inner,
+        "blocks": 9 * n,
+        "block_build": 25 * n + (25 + mom) * cells,
     }
 
 
@@ -281,7 +291,7 @@ def run_single(args, tb, dg, torch, np):
     pos = torch.from_numpy(pos_np).to(dev)
     mass = torch.from_numpy(mass_np).to(dev)
     box = ((0.0, 0.0, 0.0), 1.0)
-    b = tb.Builder(n, n_leaf, precision, k, dev)
+    b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=args.subtrees)
     run = lambda: b.launch(pos, mass, box)
     sec = time_steps(run, args.steps, args.warmup)
     print(f"[bench] {args.steps} builds, {sec * 1e3:.3f} ms/build", file=sys.stderr, flush=True)
@@ -301,7 +311,8 @@ def run_single(args, tb, dg, torch, np):
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "N": n,
                    "n_leaf": n_leaf, "precision": precision, "box": "unit cube",
                    "sort_config": list(tb.tb_sort_configs()[k]), "cells": cells,
-                   "leaves": leaves},
+                   "leaves": leaves,
+                   "cell_build": "subtree-rooted blocks" if args.subtrees else "tiles + parents"},
         "roofline": roofline(trace, alg, key_passes, args.workload),
         "build_method_bytes": total_method,
         "build_alg_GBps": round(total_method / sec / 1e9, 1),
@@ -310,6 +321,20 @@ def run_single(args, tb, dg, torch, np):
         "traced_ms_per_build": round(sum(v[1] for v in trace.values()) / args.steps, 4),
         "kernels": kernels_table(trace, args.steps, alg),
     }
+    if not args.no_compare:
+        # the other cell build on the same data (the tree is the same either way)
+        alt_b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=not args.subtrees)
+        alt_run = lambda: alt_b.launch(pos, mass, box)
+        sec_alt = time_steps(alt_run, args.steps, args.warmup)
+        alt = alt_b.result()
+        same = all(torch.equal(res[f], alt[f]) for f in
+                   ("perm", "cell_key", "cell_level", "cell_first", "cell_count", "child_ptr"))
+        alt_trace = traced_kernels(alt_run, min(args.steps, 5), tb)
+        line["other_cell_build"] = {
+            "cell_build": "tiles + parents" if args.subtrees else "subtree-rooted blocks",
+            "ms_per_step": sec_alt * 1e3, "tree_identical": bool(same),
+            "kernels": kernels_table(alt_trace, min(args.steps, 5), alg)}
+        del alt_b, alt
     if args.workload == "mixed16m" and not args.no_compare:
         # the FP64 path on the same data and the mixed path's error against it
         # (the FP64 path matches the FP64 oracle to 1e-12 in the parity tests)

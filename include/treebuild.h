@@ -103,6 +103,17 @@ extern "C" {
  * Results are bit-identical either way; the flag exists for tuning and tests. */
 #define TB_SORT_LOOKBACK (1u << 17)
 
+/* Build the cells subtree by subtree (Sec. 2.3.3, eq. 2): the sorted keys are
+ * divided into blocks of at most 2048 particles that share no cell (the leaves
+ * of the tree n_leaf = 2048 would give); one workgroup builds each block's
+ * cells and moments with the leaf depth D_k = max(minDepth(k, k-1),
+ * minDepth(k, k + n_leaf), d_root), d_root the block's depth; the cells above
+ * the blocks are built from the block roots last.  Without the flag the cells
+ * are placed tile by tile and the parents built one depth at a time over the
+ * whole tree.  The tree is identical either way; only speed and workspace
+ * differ. */
+#define TB_SUBTREES (1u << 18)
+
 #define TB_MAX_DEPTH 21
 #define TB_MAX_NLEAF 1024 /* largest supported n_leaf */
 #define TB_MAX_N 2147483647LL

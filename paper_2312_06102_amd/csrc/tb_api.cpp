@@ -89,15 +89,20 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->set_tot = take(4 * (size_t)nsets * kLevels);
   p->set_cells = take(8 * B1);
   p->lvl_off = take(8 * (size_t)nsets * (kLevels + 1));
+  p->par_start = take(8 * (size_t)kLevels * B1);
   p->coarse = take(4 * (size_t)(kCoarse + 1));
   p->packed = take(16 * (size_t)n);
   p->sorted = take(16 * (size_t)n);
   p->ad = take(2 * (size_t)n);
-  p->blk = take((size_t)n);
-  // the cells above the blocks at one depth are disjoint and each holds more
-  // than n_serial particles
-  p->upper_cap = n / (kCellTile + 1) + nsets;
-  p->upper = take(4 * (size_t)kLevels * (size_t)p->upper_cap);
+  if (flags & TB_SUBTREES) {
+    p->blk = take((size_t)n);
+    // the cells above the blocks at one depth are disjoint and each holds more
+    // than n_serial particles
+    p->upper_cap = n / (kCellTile + 1) + nsets;
+    p->upper = take(4 * (size_t)kLevels * (size_t)p->upper_cap);
+  } else {
+    p->head_parent = take(4 * (size_t)p->c_max);
+  }
   p->m_lo = take((flags & 0xffu) == TB_MIXED ? 4 * (size_t)p->c_max : 0);
   p->total = off;
   return TB_OK;
@@ -127,10 +132,12 @@ Work carve(const Plan &p, void *base) {
   w.set_tot = reinterpret_cast<uint32_t *>(b + p.set_tot);
   w.set_cells = reinterpret_cast<int64_t *>(b + p.set_cells);
   w.lvl_off = reinterpret_cast<int64_t *>(b + p.lvl_off);
+  w.par_start = reinterpret_cast<int64_t *>(b + p.par_start);
   w.coarse = reinterpret_cast<uint32_t *>(b + p.coarse);
   w.packed = reinterpret_cast<float4 *>(b + p.packed);
   w.sorted = reinterpret_cast<float4 *>(b + p.sorted);
   w.ad = reinterpret_cast<uint16_t *>(b + p.ad);
+  w.head_parent = reinterpret_cast<int32_t *>(b + p.head_parent);
   w.blk = b + p.blk;
   w.upper = reinterpret_cast<int32_t *>(b + p.upper);
   w.m_lo = reinterpret_cast<float *>(b + p.m_lo);
@@ -200,7 +207,7 @@ static int check_sizes(int64_t n, int32_t n_leaf) {
 static int config_from_flags(uint32_t flags, SortConfig *sc) {
   const uint32_t prec = flags & 0xffu;
   if (prec != TB_FP64 && prec != TB_MIXED) return TB_ERR_ARG;
-  if (flags & ~(0xffffu | TB_SORT_LOOKBACK)) return TB_ERR_ARG;
+  if (flags & ~(0xffffu | TB_SORT_LOOKBACK | TB_SUBTREES)) return TB_ERR_ARG;
   const int k = (int)((flags >> 8) & 0xffu);
   if (k >= kSortTableSize) return TB_ERR_ARG;
   *sc = kSortTable[k];
@@ -239,8 +246,8 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
   Plan p;
   make_plan(n, nsets, n_leaf, flags | (in.auto_box ? kAutoBoxFlag : 0u), sc, &p);
   if (!workspace || ws_bytes < p.total) return TB_ERR_WORKSPACE;
-  // the reorder pass stages a tile plus an n_leaf halo in LDS
-  if (cell_reorder_lds(n_leaf) > cell_lds_limit()) return TB_ERR_ARG;
+  // the cell kernels stage a tile plus an n_leaf halo in LDS
+  if (cell_emit_lds(n_leaf) > cell_lds_limit()) return TB_ERR_ARG;
   const Work w = carve(p, workspace);
 
   hipError_t e = hipSuccess;
@@ -257,9 +264,15 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
         [&] { return launch_sort_pass(p, w, pass, *out, s); });
   run("reorder", [&] { return launch_reorder(p, w, *out, s); });
   run("cell_scan", [&] { return launch_cell_scan(p, w, *out, cell_offsets, s); });
-  run("blocks", [&] { return launch_blocks(p, w, s); });
-  run("block_build", [&] { return launch_block_build(p, w, *out, s); });
-  run("upper", [&] { return launch_upper(p, w, *out, s); });
+  if (flags & TB_SUBTREES) {
+    run("blocks", [&] { return launch_blocks(p, w, s); });
+    run("block_build", [&] { return launch_block_build(p, w, *out, s); });
+    run("upper", [&] { return launch_upper(p, w, *out, s); });
+  } else {
+    run("cell_emit", [&] { return launch_cell_emit(p, w, *out, s); });
+    for (int d = kMaxDepth - 1; d >= 0; --d)
+      run("parents", [&] { return launch_parents(p, w, d, *out, s); });
+  }
   return e == hipSuccess ? TB_OK : TB_ERR_HIP;
 }
 

@@ -23,9 +23,13 @@
 //                the keys of its tile plus an n_leaf halo, a_i and D_i of every
 //                particle and the tile's per-depth cell counts;
 // k_cell_scan  : per-depth prefix over the tiles of each set;
-// k_set_scan   : first cell of every set and depth.
-// The cells themselves are written block by block (tb_blocks.hip).
+// k_set_scan   : first cell of every set and depth;
+// k_cell_emit  : writes key, depth, first particle and first-child slot of
+//                every cell, and count plus moments of every leaf.
+// (With TB_SUBTREES the cells are written block by block instead:
+// tb_blocks.hip.)
 #include "tb_internal.h"
+#include "tb_moments.h"
 #include "tb_tiles.h"
 
 namespace tb {
@@ -56,6 +60,54 @@ __device__ inline WindowLds carve_window(unsigned char *base, int nl) {
   s.a = base;
   base += round16(kCellTile + nl);
   s.wtot = reinterpret_cast<uint32_t *>(base);
+  return s;
+}
+
+// Shared layout of the emit pass.
+struct EmitLds {
+  uint8_t *a;          // [T + NL]        a_i, i in [t0, t1 + NL)
+  uint8_t *d;          // [T]             D_i, i in [t0, t1)
+  uint32_t *wtot;      // [kWaves][kLevelWords]
+  uint32_t *lvl;       // [kLevels]       per-depth base of this tile
+  uint16_t *off;       // [kLevels][kCellThreads] next cell slot per depth per thread
+  float4 *rec;         // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL); stored once
+                       //                 the cells are placed, over the dead `off`
+  uint32_t *leaf;      // [T]             leaf starting in the tile: local first particle |
+                       //                 depth << 11 | slot within its depth << 16
+  uint8_t *heads;      // [T / 8]         bit li: particle t0 + li starts a leaf
+  uint32_t *nleaf;     // [1]
+};
+
+__host__ __device__ inline size_t emit_union_bytes(int nl) {
+  const size_t off = (size_t)kLevels * kCellThreads * 2, rec = (size_t)(kCellTile + nl) * 16;
+  return round16(off > rec ? off : rec);
+}
+
+__host__ __device__ inline size_t emit_lds_bytes(int nl) {
+  return round16(kCellTile + nl) + round16(kCellTile) + round16((size_t)kWaves * kLevelWords * 4) +
+         round16(kLevels * 4) + emit_union_bytes(nl) + (size_t)kCellTile * 4 + kCellTile / 8 + 16;
+}
+
+__device__ inline EmitLds carve_emit(unsigned char *base, int nl) {
+  EmitLds s;
+  s.a = base;
+  base += round16(kCellTile + nl);
+  s.d = base;
+  base += round16(kCellTile);
+  s.wtot = reinterpret_cast<uint32_t *>(base);
+  base += round16((size_t)kWaves * kLevelWords * 4);
+  s.lvl = reinterpret_cast<uint32_t *>(base);
+  base += round16(kLevels * 4);
+  // the per-depth cursors are dead once the cells are placed; the particle
+  // records take their place for the moment phase
+  s.off = reinterpret_cast<uint16_t *>(base);
+  s.rec = reinterpret_cast<float4 *>(base);
+  base += emit_union_bytes(nl);
+  s.leaf = reinterpret_cast<uint32_t *>(base);
+  base += (size_t)kCellTile * 4;
+  s.heads = base;
+  base += kCellTile / 8;
+  s.nleaf = reinterpret_cast<uint32_t *>(base);
   return s;
 }
 
@@ -271,42 +323,53 @@ __global__ __launch_bounds__(THREADS) void k_cell_scan(
   }
 }
 
-// One workgroup over all sets, THREADS sets per round: the first cell of every
-// set and of every depth of every set, the outputs level_offset [B][23],
-// cell_offsets [B+1] and n_cells, and the boxes used.
+// One workgroup over all sets, THREADS sets per round and every row of a round
+// at once: the first cell of every set and of every depth of every set, the
+// outputs level_offset [B][23], cell_offsets [B+1] and n_cells, the
+// parent-pass chunk tables, and the boxes used.  Up to 64 sets take one wave.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_set_scan(
     const uint32_t *__restrict__ set_tot, int32_t nsets, int64_t *__restrict__ set_cells,
     int64_t *__restrict__ lvl_off, int64_t *__restrict__ level_offset,
     int64_t *__restrict__ cell_offsets, int64_t *__restrict__ n_cells,
-    const double *__restrict__ box, double *__restrict__ box_out) {
+    int64_t *__restrict__ par_start, const double *__restrict__ box,
+    double *__restrict__ box_out) {
   constexpr int kSetScanWaves = THREADS / 64;
-  __shared__ uint32_t s_w[kSetScanWaves];
-  __shared__ int64_t s_carry;
+  // rows: 0 = cells per set, r = 1..21 = parent chunks at depth r - 1 (children at depth r)
+  __shared__ uint32_t s_w[kLevels][kSetScanWaves];
+  __shared__ int64_t s_carry[kLevels];
   const int wv = threadIdx.x / 64;
-  if (threadIdx.x == 0) s_carry = 0;
+  if (threadIdx.x < kLevels) s_carry[threadIdx.x] = 0;
   __syncthreads();
   for (int r0 = 0; r0 < nsets; r0 += THREADS) {
     const int b = r0 + threadIdx.x;
-    uint32_t t[kLevels], v = 0;
+    uint32_t t[kLevels];
 #pragma unroll
-    for (int d = 0; d < kLevels; ++d) {
-      t[d] = (b < nsets) ? set_tot[b * kLevels + d] : 0u;
-      v += t[d];
+    for (int d = 0; d < kLevels; ++d) t[d] = (b < nsets) ? set_tot[b * kLevels + d] : 0u;
+    uint32_t v[kLevels], inc[kLevels];
+    v[0] = 0;
+#pragma unroll
+    for (int d = 0; d < kLevels; ++d) v[0] += t[d];
+#pragma unroll
+    for (int r = 1; r < kLevels; ++r) v[r] = (t[r] + kParentChunk - 1) / kParentChunk;
+#pragma unroll
+    for (int r = 0; r < kLevels; ++r) inc[r] = wave_inclusive_scan(v[r]);
+    if (lane_id() == 63) {
+#pragma unroll
+      for (int r = 0; r < kLevels; ++r) s_w[r][wv] = inc[r];
     }
-    const uint32_t inc = wave_inclusive_scan(v);
-    if (lane_id() == 63) s_w[wv] = inc;
     __syncthreads();
-    int64_t off = s_carry, tot = 0;
-    for (int q = 0; q < kSetScanWaves; ++q) {
-      off += q < wv ? s_w[q] : 0u;
-      tot += s_w[q];
+    int64_t off[kLevels];
+#pragma unroll
+    for (int r = 0; r < kLevels; ++r) {
+      int64_t o = s_carry[r];
+      for (int q = 0; q < wv; ++q) o += s_w[r][q];
+      off[r] = o + (int64_t)(inc[r] - v[r]);
     }
-    off += (int64_t)(inc - v);
     if (b < nsets) {
-      set_cells[b] = off;
-      if (cell_offsets) cell_offsets[b] = off;
-      int64_t run = off;
+      set_cells[b] = off[0];
+      if (cell_offsets) cell_offsets[b] = off[0];
+      int64_t run = off[0];
 #pragma unroll
       for (int d = 0; d < kLevels; ++d) {
         lvl_off[b * (kLevels + 1) + d] = run;
@@ -317,16 +380,286 @@ __global__ __launch_bounds__(THREADS) void k_set_scan(
       level_offset[b * (kLevels + 1) + kLevels] = run;
       if (box_out)
         for (int k = 0; k < 4; ++k) box_out[4 * b + k] = box[4 * b + k];
+#pragma unroll
+      for (int r = 1; r < kLevels; ++r) par_start[(r - 1) * (nsets + 1) + b] = off[r];
     }
     __syncthreads();
-    if (threadIdx.x == 0) s_carry += tot;
+    if (threadIdx.x < kLevels) {
+      int64_t tot = 0;
+      for (int q = 0; q < kSetScanWaves; ++q) tot += s_w[threadIdx.x][q];
+      s_carry[threadIdx.x] += tot;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    set_cells[nsets] = s_carry;
-    if (cell_offsets) cell_offsets[nsets] = s_carry;
-    *n_cells = s_carry;
+  if (threadIdx.x < kLevels) {
+    const int r = threadIdx.x;
+    const int64_t total = s_carry[r];
+    if (r == 0) {
+      set_cells[nsets] = total;
+      if (cell_offsets) cell_offsets[nsets] = total;
+      *n_cells = total;
+    } else {
+      par_start[(r - 1) * (nsets + 1) + nsets] = total;
+    }
   }
+}
+
+// ---------------------------------------------------------------------------
+// leaf moments
+// ---------------------------------------------------------------------------
+
+// End (exclusive) of the leaf that starts at particle i with depth dl, from
+// the a_i of the particles after it (a: [t0, t1 + nl) relative to t0).
+__device__ inline int64_t leaf_end(const uint8_t *a, const uint64_t *__restrict__ keys, int64_t n,
+                                   int nl, int64_t t0, int64_t i, int dl) {
+  // n is the end of the particle's set
+  const int64_t lim = min(n, i + nl + 1);
+  for (int64_t j = i + 1; j < lim; ++j)
+    if (a[j - t0] <= dl) return j;
+  if (lim == n) return n;
+  // only a depth-21 leaf of identical keys can be longer than n_leaf
+  const uint64_t k = keys[i];
+  int64_t lo = i + nl + 1, hi = n;  // first index in [lo, hi) whose key differs
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (keys[mid] == k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// The same leaf end from the tile's head mask: a leaf ends where the next leaf
+// starts (a particle inside the leaf shares the leaf's prefix with its
+// predecessor, so it starts no cell; the first particle past the leaf differs
+// from its predecessor at depth <= the leaf depth and starts its own leaf).
+// Only a leaf reaching past the tile falls back to the halo scan.
+__device__ inline int64_t leaf_end_fast(const EmitLds &s, const uint64_t *__restrict__ keys,
+                                        int64_t n, int nl, int64_t t0, int T, int li, int dl) {
+  const uint64_t *hw = reinterpret_cast<const uint64_t *>(s.heads);
+  const int nw = (T + 63) >> 6;
+  int w = li >> 6;
+  const int b = li & 63;
+  uint64_t bits = b == 63 ? 0ull : (hw[w] >> (b + 1)) << (b + 1);
+  while (bits == 0 && ++w < nw) bits = hw[w];
+  if (bits != 0) {
+    const int p = (w << 6) + __ffsll((long long)bits) - 1;
+    if (p < T) return t0 + p;
+  }
+  return leaf_end(s.a, keys, n, nl, t0, t0 + li, dl);
+}
+
+// ---------------------------------------------------------------------------
+// emit pass
+// ---------------------------------------------------------------------------
+// One workgroup per cell tile: a_i and D_i (from the reorder pass) give every
+// cell whose first particle lies in the tile; the per-depth prefix places it.
+template <bool MIXED>
+__global__ __launch_bounds__(kCellThreads) void k_cell_emit(
+    const uint64_t *__restrict__ keys, const uint16_t *__restrict__ ad, int nl,
+    const uint32_t *__restrict__ excl, int64_t cell_tiles, const int64_t *__restrict__ tile_start,
+    const int32_t *__restrict__ tile_set, const int64_t *__restrict__ set_off, int32_t nsets,
+    const int64_t *__restrict__ lvl_off, const double *__restrict__ box,
+    const float4 *__restrict__ sorted, uint64_t *__restrict__ cell_key,
+    uint8_t *__restrict__ cell_level, int32_t *__restrict__ cell_first,
+    int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr, void *__restrict__ com_v,
+    void *__restrict__ quad_v, float *__restrict__ m_lo, int32_t *__restrict__ head_parent,
+    int64_t c_max, int32_t *__restrict__ status_word) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const EmitLds s = carve_emit(lds, nl);
+  const int64_t tile = blockIdx.x;
+  if (tile >= tile_start[nsets]) return;
+  const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
+  const int64_t t0 = tr.t0, t1 = tr.t1, n = tr.E;  // n: end of this tile's set
+  const int T = (int)(t1 - t0);
+
+  // per-depth base of this tile: the set's first cell of the depth plus the
+  // cells of the set's earlier tiles
+  if (threadIdx.x < kLevels) {
+    const int d = threadIdx.x;
+    s.lvl[d] = (uint32_t)(lvl_off[tr.b * (kLevels + 1) + d] + excl[d * cell_tiles + tile]);
+  }
+  if (threadIdx.x == 0) *s.nleaf = 0;
+  // this thread's particles t0 + 8t .. t0 + 8t + 7: their keys (issued first,
+  // so that they travel with the batched loads below)
+  uint64_t kk[kCellIpt];
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) {
+    const int li = threadIdx.x * kCellIpt + j;
+    kk[j] = keys[t0 + (li < T ? li : T - 1)];
+  }
+  // the (a, D) of the tile's particles and the n_leaf halo into LDS, in one
+  // batch of loads
+  const int span = (int)(min(t1 + (int64_t)nl, n) - t0);
+  constexpr int kRecBatch = kCellIpt + 1;  // covers span for n_leaf <= 256
+  for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
+    uint16_t v[kRecBatch];
+#pragma unroll
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      v[u] = ad[t0 + (x < span ? x : span - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      if (x < span) {
+        s.a[x] = (uint8_t)(v[u] & 0xff);
+        if (x < T) s.d[x] = (uint8_t)(v[u] >> 8);
+      }
+    }
+  }
+  __syncthreads();
+  uint8_t A[kCellIpt], D[kCellIpt];
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) {
+    const int li = threadIdx.x * kCellIpt + j;
+    A[j] = li < T ? s.a[li] : 23;  // 23: starts no cell
+    D[j] = li < T ? s.d[li] : 0;
+  }
+  {
+    // the head mask holds one byte per thread: bit j of byte t is particle 8t + j
+    static_assert(kCellIpt == 8 && kCellThreads * kCellIpt == kCellTile,
+                  "the head mask layout needs 8 particles per thread");
+    uint32_t hb = 0;
+#pragma unroll
+    for (int j = 0; j < kCellIpt; ++j) hb |= (A[j] <= D[j] ? 1u : 0u) << j;
+    s.heads[threadIdx.x] = (uint8_t)hb;  // items 8t .. 8t+7 (none past the tile end)
+  }
+  uint32_t c[kLevelWords], tot[kLevelWords];
+  thread_level_counts(A, D, c);
+  block_level_scan(s.wtot, c, tot);  // its barrier also publishes s.heads
+#pragma unroll
+  for (int d = 0; d < kLevels; ++d) s.off[d * kCellThreads + threadIdx.x] = (uint16_t)unpack(c, d);
+  // this thread's leaves go to a contiguous run of the leaf list
+  uint32_t my_leaves = 0;
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) my_leaves += (A[j] <= D[j]) ? 1u : 0u;
+  const uint32_t inc = wave_inclusive_scan(my_leaves);
+  uint32_t wave_base = 0;
+  if (lane_id() == 63) wave_base = atomicAdd(s.nleaf, inc);
+  wave_base = __shfl(wave_base, 63, 64);
+  uint32_t leaf_slot = wave_base + inc - my_leaves;
+
+  // cell structure; leaves are queued for the moment phase
+  bool internal = false;
+#pragma unroll
+  for (int j = 0; j < kCellIpt; ++j) {
+    const int a = A[j], dl = D[j];
+    if (a > dl) continue;
+    const int li = threadIdx.x * kCellIpt + j;
+    const int64_t i = t0 + li;
+    const uint64_t key = kk[j];
+    for (int d = a; d <= dl; ++d) {
+      const uint32_t rel = s.off[d * kCellThreads + threadIdx.x];
+      s.off[d * kCellThreads + threadIdx.x] = (uint16_t)(rel + 1);
+      const uint32_t ci = s.lvl[d] + rel;
+      if ((int64_t)ci >= c_max) {  // cannot happen with consistent counts
+        internal = true;
+        continue;
+      }
+      cell_key[ci] = key >> (63 - 3 * d);
+      cell_level[ci] = (uint8_t)d;
+      cell_first[ci] = (int32_t)i;
+      if (d < dl) {
+        // first child: this particle's cell one depth down (emitted next)
+        const uint32_t fc = s.lvl[d + 1] + s.off[(d + 1) * kCellThreads + threadIdx.x];
+        reinterpret_cast<int2 *>(child_ptr)[ci] = make_int2((int32_t)fc, 0);
+        if ((int64_t)fc < c_max) head_parent[fc] = (int32_t)ci;
+      } else {
+        reinterpret_cast<int2 *>(child_ptr)[ci] = make_int2(-1, 0);
+        s.leaf[leaf_slot] = (uint32_t)li | ((uint32_t)dl << 11) | (rel << 16);
+        ++leaf_slot;
+      }
+    }
+  }
+  __syncthreads();
+
+  // the cursors are dead: the particle records (tile and halo) take their
+  // place, in batched loads
+  for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
+    float4 r[kRecBatch];
+#pragma unroll
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      r[u] = sorted[t0 + (x < span ? x : span - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kRecBatch; ++u) {
+      const int x = x0 + u * kCellThreads + threadIdx.x;
+      if (x < span) s.rec[x] = r[u];
+    }
+  }
+  __syncthreads();
+  const uint32_t nlv = *s.nleaf;
+
+  // leaf moments: one lane per leaf, particles read from LDS
+  const double lo[3] = {box[4 * tr.b + 0], box[4 * tr.b + 1], box[4 * tr.b + 2]};
+  const double side = box[4 * tr.b + 3];
+  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
+    const uint32_t le = s.leaf[x];
+    const int li = le & 0x7ff;
+    const int dl = (le >> 11) & 31;
+    if (dl > kMaxDepth || li >= T) {  // cannot happen: entries come from the loop above
+      internal = true;
+      continue;
+    }
+    const uint32_t ci = s.lvl[dl] + (le >> 16);
+    if ((int64_t)ci >= c_max) {
+      internal = true;
+      continue;
+    }
+    const int64_t i = t0 + li;
+    const uint64_t key = keys[i];
+    const int64_t e = leaf_end_fast(s, keys, n, nl, t0, T, li, dl);
+    cell_count[ci] = (int32_t)(e - i);
+    const int sh = kMaxDepth - dl;
+    const uint32_t ijk[3] = {compact3(key >> 2) >> sh, compact3(key >> 1) >> sh, compact3(key) >> sh};
+    const int64_t e_lds = min(e, t0 + (int64_t)span);
+    if constexpr (!MIXED) {
+      double *com = static_cast<double *>(com_v);
+      double *quad = static_cast<double *>(quad_v);
+      const double h = ldexp(side, -dl);
+      const double off[3] = {((double)ijk[0] + 0.5) * h, ((double)ijk[1] + 0.5) * h,
+                             ((double)ijk[2] + 0.5) * h};
+      LeafSums acc = {0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+      for (int64_t q = i; q < e_lds; ++q) leaf_add(acc, s.rec[q - t0], lo, off);
+      // only a saturated depth-21 leaf reaches past the staged halo
+      for (int64_t q = e_lds; q < e; ++q) leaf_add(acc, sorted[q], lo, off);
+      double cm[4], qd[6];
+      leaf_finish(acc, cm, qd);
+      double2 *cd = reinterpret_cast<double2 *>(com + 4 * (int64_t)ci);
+      cd[0] = make_double2(cm[0], cm[1]);
+      cd[1] = make_double2(cm[2], cm[3]);
+      double2 *qq = reinterpret_cast<double2 *>(quad + 6 * (int64_t)ci);
+      qq[0] = make_double2(qd[0], qd[1]);
+      qq[1] = make_double2(qd[2], qd[3]);
+      qq[2] = make_double2(qd[4], qd[5]);
+    } else {
+      float *com = static_cast<float *>(com_v);
+      float *quad = static_cast<float *>(quad_v);
+      const double scale = 2097152.0 / side;
+      const uint32_t base[3] = {ijk[0] << sh, ijk[1] << sh, ijk[2] << sh};
+      const float half = ldexpf(1.0f, sh - 1);
+      LeafSumsF acc;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) acc.s[k] = acc.c[k] = 0.0f;
+      for (int64_t q = i; q < e_lds; ++q) leaf_add_f(acc, s.rec[q - t0], lo, scale, base, half, dl);
+      for (int64_t q = e_lds; q < e; ++q) leaf_add_f(acc, sorted[q], lo, scale, base, half, dl);
+      float cm[4], qd[6], mlo;
+      leaf_finish_f(acc, cm, mlo, qd);
+      // stored in absolute units: scaling by the side (a power of two) is exact
+      const float l = ldexpf((float)side, -dl);
+      reinterpret_cast<float4 *>(com)[ci] = make_float4(cm[0] * l, cm[1] * l, cm[2] * l, cm[3]);
+      const float l2 = l * l;
+      float2 *qq = reinterpret_cast<float2 *>(quad + 6 * (int64_t)ci);
+      qq[0] = make_float2(qd[0] * l2, qd[1] * l2);
+      qq[1] = make_float2(qd[2] * l2, qd[3] * l2);
+      qq[2] = make_float2(qd[4] * l2, qd[5] * l2);
+      m_lo[ci] = mlo;
+    }
+  }
+  if (__ballot(internal) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
 hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
@@ -340,11 +673,11 @@ hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
                                                       p.nsets, w.cell_excl, w.set_tot);
   if (p.nsets <= 64)
     k_set_scan<64><<<1, 64, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off, out.level_offset,
-                                    cell_offsets, out.n_cells, w.box, out.box_out);
-  else
-    k_set_scan<1024><<<1, 1024, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
-                                        out.level_offset, cell_offsets, out.n_cells, w.box,
-                                        out.box_out);
+                                    cell_offsets, out.n_cells, w.par_start, w.box, out.box_out);
+  else  // 512 threads: its 22 counts per set fit in registers (1024 would spill)
+    k_set_scan<512><<<1, 512, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
+                                      out.level_offset, cell_offsets, out.n_cells, w.par_start,
+                                      w.box, out.box_out);
   return hipGetLastError();
 }
 
@@ -357,7 +690,7 @@ hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipS
 }
 
 // Largest dynamic LDS a workgroup may use on the current device (cached per
-// device), after opting the reorder kernel in to it.
+// device), after opting the cell kernels in to it.
 size_t cell_lds_limit() {
   static int cached_dev = -1;
   static size_t cached = 0;
@@ -366,8 +699,12 @@ size_t cell_lds_limit() {
   if (dev != cached_dev) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
-    const int want = (int)cell_reorder_lds(TB_MAX_NLEAF);
+    const int want = (int)cell_emit_lds(TB_MAX_NLEAF);
     const int opt = v < want ? v : want;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, opt);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_cell_emit<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, opt);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_reorder),
                               hipFuncAttributeMaxDynamicSharedMemorySize, opt);
     cached = (size_t)v;
@@ -376,7 +713,24 @@ size_t cell_lds_limit() {
   return cached;
 }
 
+hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s) {
+  const size_t lds = emit_lds_bytes(p.n_leaf);
+  auto k = (p.flags & 0xffu) == TB_MIXED ? k_cell_emit<true> : k_cell_emit<false>;
+  k<<<(unsigned)p.cell_tiles, kCellThreads, lds, s>>>(
+      sorted_keys(p, w), w.ad, p.n_leaf, w.cell_excl, p.cell_tiles, w.tile_start, w.tile_set,
+      w.set_off, p.nsets, w.lvl_off, w.box, w.sorted, out.cell_key, out.cell_level,
+      out.cell_first, out.cell_count, out.child_ptr, out.com, out.quad, w.m_lo, w.head_parent,
+      p.c_max, out.status);
+  return hipGetLastError();
+}
+
 // Dynamic LDS of the reorder pass for this n_leaf.
 size_t cell_reorder_lds(int nl) { return window_lds_bytes(nl); }
+
+// The larger of the two cell kernels' LDS needs for this n_leaf.
+size_t cell_emit_lds(int nl) {
+  const size_t a = emit_lds_bytes(nl), b = window_lds_bytes(nl);
+  return a > b ? a : b;
+}
 
 }  // namespace tb

@@ -30,6 +30,10 @@ constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
 
 constexpr int64_t kCountedMaxTiles = 4096;  // largest sort grid with counted passes
 
+// Parent kernel: children staged per workgroup step.
+constexpr int kParentThreads = 256;
+constexpr int kParentChunk = kParentThreads;
+
 // Bounding-box chunks (auto box only).
 constexpr int kBboxChunk = 65536;
 
@@ -95,10 +99,12 @@ struct Plan {
   size_t set_tot;       // u32 [B][kLevels] cells of each set and depth
   size_t set_cells;     // i64 [B + 1] first cell of each set; [B] = all cells
   size_t lvl_off;       // i64 [B][kLevels + 1] first cell of each depth of each set
+  size_t par_start;     // i64 [kLevels][B + 1] parent-pass chunks per depth and set
   size_t coarse;        // u32 [kCoarse + 1] set holding position k << coarse_shift
   size_t packed;        // f32x4 [n] (x, y, z, m) records in original order
   size_t sorted;        // f32x4 [n] the same records in key order
   size_t ad;            // u16 [n] a_i | D_i << 8 of every particle in key order
+  size_t head_parent;   // i32 [c_max] parent slot of every first child
   size_t blk;           // u8 [n] root depth of the block a particle starts, or 0xff
   size_t upper;         // i32 [kLevels][upper_cap] slots of the cells above the blocks
   size_t m_lo;          // f32 [c_max] compensation of each cell mass (mixed precision)
@@ -129,10 +135,12 @@ struct Work {
   uint32_t *set_tot;
   int64_t *set_cells;
   int64_t *lvl_off;
+  int64_t *par_start;
   uint32_t *coarse;
   float4 *packed;
   float4 *sorted;
   uint16_t *ad;
+  int32_t *head_parent;
   uint8_t *blk;
   int32_t *upper;
   float *m_lo;
@@ -173,6 +181,11 @@ hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
 hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
 size_t cell_lds_limit();
 size_t cell_reorder_lds(int nl);
+hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);
+size_t cell_emit_lds(int nl);
+// tb_parents.hip
+hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree &out,
+                          hipStream_t s);
 // tb_blocks.hip
 hipError_t launch_blocks(const Plan &p, const Work &w, hipStream_t s);
 hipError_t launch_block_build(const Plan &p, const Work &w, const tb_tree &out, hipStream_t s);

@@ -65,7 +65,9 @@ def test_workspace_bytes_grows_with_n():
         tb.tb_workspace_bytes(10, 16, flags=tb.TB_SORT_CONFIG(200))
     # the look-back switch is a known flag (same workspace); neighbouring bits are not
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_LOOKBACK) == tb.tb_workspace_bytes(10000, 16)
-    for bit in (16, 18, 31):
+    # the subtree-rooted cell build is a known flag too
+    assert tb.tb_workspace_bytes(10000, 16, tb.TB_SUBTREES) > 0
+    for bit in (16, 19, 31):
         with pytest.raises(tb.TreeBuildArgError):
             tb.tb_workspace_bytes(10, 16, flags=1 << bit)
 
@@ -73,6 +75,8 @@ def test_workspace_bytes_grows_with_n():
 def test_lookback_flag_matches_header():
     m = re.search(r"#define TB_SORT_LOOKBACK \(1u << (\d+)\)", open(HEADER).read())
     assert m and (1 << int(m.group(1))) == tb.TB_SORT_LOOKBACK
+    m = re.search(r"#define TB_SUBTREES \(1u << (\d+)\)", open(HEADER).read())
+    assert m and (1 << int(m.group(1))) == tb.TB_SUBTREES
 
 
 def test_sort_config_table():

@@ -323,23 +323,26 @@ def test_data_errors_reported():
 @pytest.mark.timeout(1200)
 def test_full_size_plummer_16m():
     """The headline configuration, every cell against a full oracle build: perm,
-    keys and structure bit for bit, FP64 moments of all cells within 1e-12."""
+    keys and structure bit for bit, FP64 moments of all cells within 1e-12; for
+    the default cell build and for the subtree-rooted one."""
     import time
     n = 1 << 24
     pos, mass, nl = dg.workload("plummer16m")
     print("[full] generated", flush=True)
-    g = gpu_build(pos, mass, nl)
-    print(f"[full] built on the GPU, {g['n_cells']} cells", flush=True)
     t0 = time.time()
     o = oracle.build(pos, mass, nl)
     print(f"[full] oracle built in {time.time() - t0:.1f} s, {o['n_cells']} cells", flush=True)
-    compare_structure(g, o)
     _, keys = oracle.keys(pos)
-    assert np.array_equal(g["key_sorted"], keys[o["perm"]])
-    assert g["perm"].shape[0] == n
-    em, ec, eq = moment_errors(g["com"], g["quad"], o["com"], o["quad"], o["cell_level"])
-    print(f"[full] all {o['n_cells']} cells: max rel err M={em:.2e} com={ec:.2e} Q={eq:.2e}",
-          flush=True)
-    assert em <= FP64_TOL and ec <= FP64_TOL and eq <= FP64_TOL, (em, ec, eq)
-    # the structural invariants, independently of the oracle
-    tc.check_invariants(g, g["key_sorted"], nl)
+    for subtrees in (False, True):
+        g = gpu_build(pos, mass, nl, subtrees=subtrees)
+        print(f"[full] built on the GPU (subtrees={subtrees}), {g['n_cells']} cells", flush=True)
+        compare_structure(g, o)
+        assert np.array_equal(g["key_sorted"], keys[o["perm"]])
+        assert g["perm"].shape[0] == n
+        em, ec, eq = moment_errors(g["com"], g["quad"], o["com"], o["quad"], o["cell_level"])
+        print(f"[full] all {o['n_cells']} cells: max rel err M={em:.2e} com={ec:.2e} Q={eq:.2e}",
+              flush=True)
+        assert em <= FP64_TOL and ec <= FP64_TOL and eq <= FP64_TOL, (em, ec, eq)
+        # the structural invariants, independently of the oracle
+        tc.check_invariants(g, g["key_sorted"], nl)
+        del g
