@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="mixed16m: skip the FP64 build on the same data; single sets: skip "
                          "timing the subtree-rooted cell build on the same data")
+    ap.add_argument("--sort-counted", action="store_true",
+                    help="count the tiles' digits in every radix pass (TB_SORT_COUNTED)")
     ap.add_argument("--subtrees", action="store_true",
                     help="time the subtree-rooted cell build (TB_SUBTREES) as the step")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -291,7 +293,8 @@ def run_single(args, tb, dg, torch, np):
     pos = torch.from_numpy(pos_np).to(dev)
     mass = torch.from_numpy(mass_np).to(dev)
     box = ((0.0, 0.0, 0.0), 1.0)
-    b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=args.subtrees)
+    b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=args.subtrees,
+                   counted=args.sort_counted)
     run = lambda: b.launch(pos, mass, box)
     sec = time_steps(run, args.steps, args.warmup)
     print(f"[bench] {args.steps} builds, {sec * 1e3:.3f} ms/build", file=sys.stderr, flush=True)
@@ -312,7 +315,8 @@ def run_single(args, tb, dg, torch, np):
                    "n_leaf": n_leaf, "precision": precision, "box": "unit cube",
                    "sort_config": list(tb.tb_sort_configs()[k]), "cells": cells,
                    "leaves": leaves,
-                   "cell_build": "subtree-rooted blocks" if args.subtrees else "tiles + parents"},
+                   "cell_build": "subtree-rooted blocks" if args.subtrees else "tiles + parents",
+                   "sort_counted_all_passes": bool(args.sort_counted)},
         "roofline": roofline(trace, alg, key_passes, args.workload),
         "build_method_bytes": total_method,
         "build_alg_GBps": round(total_method / sec / 1e9, 1),
@@ -323,7 +327,8 @@ def run_single(args, tb, dg, torch, np):
     }
     if not args.no_compare:
         # the other cell build on the same data (the tree is the same either way)
-        alt_b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=not args.subtrees)
+        alt_b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=not args.subtrees,
+                           counted=args.sort_counted)
         alt_run = lambda: alt_b.launch(pos, mass, box)
         sec_alt = time_steps(alt_run, args.steps, args.warmup)
         alt = alt_b.result()

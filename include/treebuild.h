@@ -103,6 +103,11 @@ extern "C" {
  * Results are bit-identical either way; the flag exists for tuning and tests. */
 #define TB_SORT_LOOKBACK (1u << 17)
 
+/* Count the tiles' digits in every key pass, the passes over the low 32 key
+ * bits too (they re-read 8 bytes a key), when the sort has at most 4096 tiles.
+ * Not with TB_SORT_LOOKBACK (TB_ERR_ARG).  Results are bit-identical. */
+#define TB_SORT_COUNTED (1u << 19)
+
 /* Build the cells subtree by subtree (Sec. 2.3.3, eq. 2): the sorted keys are
  * divided into blocks of at most 2048 particles that share no cell (the leaves
  * of the tree n_leaf = 2048 would give); one workgroup builds each block's

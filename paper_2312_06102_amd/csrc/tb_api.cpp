@@ -50,10 +50,11 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   // the tiles through the look-back.  The extra read grows with N while the
   // look-back's cost does not: measured faster at N = 2^24 (2979 tiles), much
   // slower at 1.6e8 keys (28K tiles).
+  // TB_SORT_COUNTED counts every key pass (a 64-bit pass re-reads 8 bytes a key).
   p->counted = 0;
   if (p->sort_tiles <= kCountedMaxTiles && !(flags & TB_SORT_LOOKBACK))
     for (int k = 0; k < p->key_passes; ++k)
-      if (k * sc.bits >= 32) p->counted |= 1u << k;
+      if (k * sc.bits >= 32 || (flags & TB_SORT_COUNTED)) p->counted |= 1u << k;
   // tiles never straddle two sets: at most one partial tile per set
   p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;
   p->bbox_chunks = (flags & kAutoBoxFlag) ? (n + kBboxChunk - 1) / kBboxChunk + nsets : 1;
@@ -207,7 +208,8 @@ static int check_sizes(int64_t n, int32_t n_leaf) {
 static int config_from_flags(uint32_t flags, SortConfig *sc) {
   const uint32_t prec = flags & 0xffu;
   if (prec != TB_FP64 && prec != TB_MIXED) return TB_ERR_ARG;
-  if (flags & ~(0xffffu | TB_SORT_LOOKBACK | TB_SUBTREES)) return TB_ERR_ARG;
+  if (flags & ~(0xffffu | TB_SORT_LOOKBACK | TB_SUBTREES | TB_SORT_COUNTED)) return TB_ERR_ARG;
+  if ((flags & TB_SORT_LOOKBACK) && (flags & TB_SORT_COUNTED)) return TB_ERR_ARG;
   const int k = (int)((flags >> 8) & 0xffu);
   if (k >= kSortTableSize) return TB_ERR_ARG;
   *sc = kSortTable[k];

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kCellThreads) void k_reorder(
     int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
   const WindowLds s = carve_window(lds, nl);
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= tile_start[nsets]) return;
   const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
   const int64_t t0 = tr.t0, t1 = tr.t1;
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     int64_t c_max, int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
   const EmitLds s = carve_emit(lds, nl);
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= tile_start[nsets]) return;
   const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
   const int64_t t0 = tr.t0, t1 = tr.t1, n = tr.E;  // n: end of this tile's set

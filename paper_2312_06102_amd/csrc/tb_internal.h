@@ -30,6 +30,10 @@ constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
 
 constexpr int64_t kCountedMaxTiles = 4096;  // largest sort grid with counted passes
 
+// The chip's eight XCDs each have their own L2, and workgroups of a launch are
+// dispatched to them in turn (workgroup b to XCD b mod 8).
+constexpr uint32_t kXcds = 8;
+
 // Parent kernel: children staged per workgroup step.
 constexpr int kParentThreads = 256;
 constexpr int kParentChunk = kParentThreads;
@@ -218,6 +222,14 @@ inline uint64_t *sorted_keys(const Plan &, const Work &w) { return w.keys0; }
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Tile of workgroup b in a grid of nb: XCD x takes a contiguous run of the
+// tiles, in order, so that the partial cache lines where consecutive tiles'
+// output runs meet are written through one L2.  A bijection of [0, nb).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+  const uint32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   return (uint64_t(1) << lane_id()) - 1u;

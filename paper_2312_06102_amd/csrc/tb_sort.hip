@@ -219,7 +219,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     if (!COUNTED && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
     __syncthreads();
-    const uint32_t tile = COUNTED ? blockIdx.x : s_tile;
+    const uint32_t tile = COUNTED ? xcd_tile(blockIdx.x, gridDim.x) : s_tile;
     if (tile >= n_tiles) {
       // one tile per workgroup: the counter was not reset (never after k_init)
       if (!SETID && threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);

@@ -45,6 +45,7 @@ TB_FP64 = 0
 TB_MIXED = 1
 TB_SORT_LOOKBACK = 1 << 17  # keep the decoupled look-back in every radix pass
 TB_SUBTREES = 1 << 18  # build the cells subtree by subtree (Sec. 2.3.3, eq. 2)
+TB_SORT_COUNTED = 1 << 19  # count the tiles' digits in every radix pass
 TB_MAX_DEPTH = 21
 TB_MAX_NLEAF = 1024
 TB_MAX_SETS = 16383
@@ -394,12 +395,13 @@ class Builder(_Graphable):
 
     def __init__(self, n: int, n_leaf: int = 16, precision: str = "fp64", sort_config: int = 0,
                  device="cuda", sorted_particles: bool = False, sorted_keys: bool = False,
-                 lookback: bool = False, subtrees: bool = False):
+                 lookback: bool = False, subtrees: bool = False, counted: bool = False):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         self.n, self.n_leaf, self.precision = int(n), int(n_leaf), precision
         self.flags = ((TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
-                      | (TB_SORT_LOOKBACK if lookback else 0) | (TB_SUBTREES if subtrees else 0))
+                      | (TB_SORT_LOOKBACK if lookback else 0) | (TB_SUBTREES if subtrees else 0)
+                      | (TB_SORT_COUNTED if counted else 0))
         self.ws_bytes = tb_workspace_bytes(self.n, self.n_leaf, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
@@ -468,16 +470,18 @@ class Builder(_Graphable):
 
 def build(pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 16, box=None,
           precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
-          sorted_keys: bool = False, lookback: bool = False, subtrees: bool = False) -> dict:
+          sorted_keys: bool = False, lookback: bool = False, subtrees: bool = False,
+          counted: bool = False) -> dict:
     """One-shot build; returns device tensors trimmed to n_cells.
 
     box: None (derive from data) or (lo[3], side) with side a power of two.
     lookback: keep the decoupled look-back in every radix pass (TB_SORT_LOOKBACK).
     subtrees: build the cells block by block from subtree roots (TB_SUBTREES); the
     tree is the same.
+    counted: count the tiles' digits in every radix pass (TB_SORT_COUNTED).
     cell_key is returned as int64 holding the uint64 bit pattern."""
     b = Builder(pos.shape[0], n_leaf, precision, sort_config, pos.device, sorted_particles,
-                sorted_keys, lookback, subtrees)
+                sorted_keys, lookback, subtrees, counted)
     b.launch(pos, mass, box)
     return b.result()
 
@@ -489,12 +493,14 @@ class BatchBuilder(_Graphable):
 
     def __init__(self, n_total: int, nsets: int, n_leaf: int = 16, precision: str = "fp64",
                  sort_config: int = 0, device="cuda", sorted_particles: bool = False,
-                 sorted_keys: bool = False, lookback: bool = False, subtrees: bool = False):
+                 sorted_keys: bool = False, lookback: bool = False, subtrees: bool = False,
+                 counted: bool = False):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         self.n, self.nsets, self.n_leaf, self.precision = int(n_total), int(nsets), int(n_leaf), precision
         self.flags = ((TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
-                      | (TB_SORT_LOOKBACK if lookback else 0) | (TB_SUBTREES if subtrees else 0))
+                      | (TB_SORT_LOOKBACK if lookback else 0) | (TB_SUBTREES if subtrees else 0)
+                      | (TB_SORT_COUNTED if counted else 0))
         self.ws_bytes = tb_workspace_bytes_batched(self.n, self.nsets, self.n_leaf, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
@@ -551,9 +557,9 @@ def build_batched(pos: torch.Tensor, mass: torch.Tensor, set_offsets: torch.Tens
                   n_leaf: int = 16, boxes: Optional[torch.Tensor] = None,
                   precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
                   sorted_keys: bool = False, lookback: bool = False,
-                  subtrees: bool = False) -> dict:
+                  subtrees: bool = False, counted: bool = False) -> dict:
     """One-shot batched build; returns device tensors trimmed to n_cells."""
     b = BatchBuilder(pos.shape[0], set_offsets.shape[0] - 1, n_leaf, precision, sort_config,
-                     pos.device, sorted_particles, sorted_keys, lookback, subtrees)
+                     pos.device, sorted_particles, sorted_keys, lookback, subtrees, counted)
     b.launch(pos, mass, set_offsets, boxes)
     return b.result()

@@ -67,7 +67,10 @@ def test_workspace_bytes_grows_with_n():
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_LOOKBACK) == tb.tb_workspace_bytes(10000, 16)
     # the subtree-rooted cell build is a known flag too
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SUBTREES) > 0
-    for bit in (16, 19, 31):
+    assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED) > 0
+    with pytest.raises(tb.TreeBuildArgError):
+        tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED | tb.TB_SORT_LOOKBACK)
+    for bit in (16, 20, 31):
         with pytest.raises(tb.TreeBuildArgError):
             tb.tb_workspace_bytes(10, 16, flags=1 << bit)
 

@@ -258,13 +258,14 @@ def test_mixed_nonunit_box_and_duplicates():
 
 def test_every_sort_config_identical():
     """Every sort shape, with the passes over 32-bit keys counted (the default on
-    small grids) and with the look-back kept in every pass, gives the same tree."""
+    small grids), with the look-back kept in every pass and with every pass
+    counted, gives the same tree."""
     pos, mass = dg.plummer(150000, seed=9)
     o = oracle.build(pos, mass, 16)
     ref = None
     for k in range(len(tb.tb_sort_configs())):
-        for lookback in (False, True):
-            g = gpu_build(pos, mass, 16, sort_config=k, lookback=lookback)
+        for lookback, counted in ((False, False), (True, False), (False, True)):
+            g = gpu_build(pos, mass, 16, sort_config=k, lookback=lookback, counted=counted)
             compare_structure(g, o)
             if ref is None:
                 ref = g
