@@ -55,12 +55,21 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     i64 = ctypes.c_int64
     lib.tbo_keys.argtypes = [P, i64, P, ctypes.c_double, P, P]
     lib.tbo_keys.restype = ctypes.c_int
+    lib.tbo_keys_curve.argtypes = [P, i64, P, ctypes.c_double, ctypes.c_int, P, P]
+    lib.tbo_keys_curve.restype = ctypes.c_int
+    lib.tbo_hilbert_encode.argtypes = [P, i64, ctypes.c_int, P]
+    lib.tbo_hilbert_encode.restype = None
+    lib.tbo_hilbert_decode.argtypes = [P, i64, ctypes.c_int, P]
+    lib.tbo_hilbert_decode.restype = None
     lib.tbo_max_cells.argtypes = [i64, ctypes.c_int32]
     lib.tbo_max_cells.restype = i64
     lib.tbo_build.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double] + [P] * 11
     lib.tbo_build.restype = ctypes.c_int
     lib.tbo_build_timed.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double] + [P] * 12
     lib.tbo_build_timed.restype = ctypes.c_int
+    lib.tbo_build_curve.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double,
+                                    ctypes.c_int] + [P] * 12
+    lib.tbo_build_curve.restype = ctypes.c_int
     lib.tbl_build.argtypes = [P, P, i64, ctypes.c_int32, P, ctypes.c_double] + [P] * 11
     lib.tbl_build.restype = ctypes.c_int
     lib.tbo_cell_moments.argtypes = [P, P, P, ctypes.c_double, P, i64, i64,
@@ -74,6 +83,10 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
                                                              ctypes.c_int32, ctypes.c_double,
                                                              ctypes.c_int, P, P]
     lib.tbg_walk_tree.restype = ctypes.c_int
+    lib.tbg_walk_tree_curve.argtypes = [P, P, P, i64] + [P] * 7 + [
+        P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int,
+        ctypes.c_int, P, P]
+    lib.tbg_walk_tree_curve.restype = ctypes.c_int
     lib.tbo_auto_box.argtypes = [P, i64, P, P]
     lib.tbo_auto_box.restype = ctypes.c_int
     return lib
@@ -108,18 +121,51 @@ def _box(lo, side):
     return lo, float(side)
 
 
-def keys(pos: np.ndarray, lo=(0.0, 0.0, 0.0), side: float = 1.0, lib=None):
-    """Quantised coordinates [N,3] (uint32) and 64-bit Morton keys [N] (uint64)."""
+CURVES = {"morton": 0, "hilbert": 1}
+
+
+def _curve(curve: str) -> int:
+    if curve not in CURVES:
+        raise ValueError(f"curve must be one of {sorted(CURVES)}")
+    return CURVES[curve]
+
+
+def keys(pos: np.ndarray, lo=(0.0, 0.0, 0.0), side: float = 1.0, lib=None,
+         curve: str = "morton"):
+    """Quantised coordinates [N,3] (uint32) and 64-bit keys [N] (uint64): Morton
+    keys, or Peano-Hilbert keys with curve="hilbert"."""
     lib = lib or load()
     pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
     n = pos.shape[0]
     lo, side = _box(lo, side)
     q = np.empty((n, 3), dtype=np.uint32)
     k = np.empty(n, dtype=np.uint64)
-    rc = lib.tbo_keys(_ptr(pos), n, _ptr(lo), side, _ptr(q), _ptr(k))
+    if curve == "morton":
+        rc = lib.tbo_keys(_ptr(pos), n, _ptr(lo), side, _ptr(q), _ptr(k))
+    else:
+        rc = lib.tbo_keys_curve(_ptr(pos), n, _ptr(lo), side, _curve(curve), _ptr(q), _ptr(k))
     if rc:
         raise OracleError(rc)
     return q, k
+
+
+def hilbert_encode(q: np.ndarray, bits: int, lib=None) -> np.ndarray:
+    """Index [N] (uint64, 3*bits bits, no leading 1) of cells q [N,3] on the
+    Hilbert curve of `bits` levels."""
+    lib = lib or load()
+    q = np.ascontiguousarray(q, dtype=np.uint32).reshape(-1, 3)
+    h = np.empty(q.shape[0], dtype=np.uint64)
+    lib.tbo_hilbert_encode(_ptr(q), q.shape[0], int(bits), _ptr(h))
+    return h
+
+
+def hilbert_decode(h: np.ndarray, bits: int, lib=None) -> np.ndarray:
+    """Cells [N,3] (uint32) of Hilbert indices h on the curve of `bits` levels."""
+    lib = lib or load()
+    h = np.ascontiguousarray(h, dtype=np.uint64).reshape(-1)
+    q = np.empty((h.shape[0], 3), dtype=np.uint32)
+    lib.tbo_hilbert_decode(_ptr(h), h.shape[0], int(bits), _ptr(q))
+    return q
 
 
 def max_cells(n: int, n_leaf: int, lib=None) -> int:
@@ -132,12 +178,12 @@ LEAF_FIRST_STAGES = ("keys", "sort", "reorder", "leaves", "parents", "output")
 
 
 def build(pos: np.ndarray, mass: np.ndarray, n_leaf: int, lo=(0.0, 0.0, 0.0), side: float = 1.0,
-          moments: bool = True, lib=None) -> dict:
+          moments: bool = True, lib=None, curve: str = "morton") -> dict:
     """Reference tree.  Returns a dict of numpy arrays trimmed to n_cells:
     perm, dfs_perm, cell_key, cell_level, cell_first, cell_count, child_ptr [C,2],
     com [C,4] (dx, dy, dz relative to the cell centre, M), quad [C,6]
     (xx, xy, xz, yy, yz, zz), level_offset [23], n_cells, and stage_s: seconds
-    of each step named in ORACLE_STAGES."""
+    of each step named in ORACLE_STAGES.  curve="hilbert": Peano-Hilbert keys."""
     lib = lib or load()
     pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
     mass = np.ascontiguousarray(mass, dtype=np.float32).reshape(-1)
@@ -159,10 +205,14 @@ def build(pos: np.ndarray, mass: np.ndarray, n_leaf: int, lo=(0.0, 0.0, 0.0), si
     nc = np.zeros(1, dtype=np.int64)
     stage = np.zeros(len(ORACLE_STAGES), dtype=np.float64)
     null = ctypes.c_void_p(0)
-    rc = lib.tbo_build_timed(_ptr(pos), _ptr(mass), n, n_leaf, _ptr(lo), side, _ptr(perm),
-                             _ptr(dfs), _ptr(key), _ptr(level), _ptr(first), _ptr(count),
-                             _ptr(child), _ptr(com) if moments else null,
-                             _ptr(quad) if moments else null, _ptr(loff), _ptr(nc), _ptr(stage))
+    outs = (_ptr(perm), _ptr(dfs), _ptr(key), _ptr(level), _ptr(first), _ptr(count), _ptr(child),
+            _ptr(com) if moments else null, _ptr(quad) if moments else null, _ptr(loff), _ptr(nc),
+            _ptr(stage))
+    if curve == "morton":
+        rc = lib.tbo_build_timed(_ptr(pos), _ptr(mass), n, n_leaf, _ptr(lo), side, *outs)
+    else:
+        rc = lib.tbo_build_curve(_ptr(pos), _ptr(mass), n, n_leaf, _ptr(lo), side,
+                                 _curve(curve), *outs)
     if rc:
         raise OracleError(rc)
     c = int(nc[0])
@@ -257,7 +307,8 @@ def direct_forces_at(pos, mass, idx, eps: float = 0.0, lib=None) -> np.ndarray:
 
 
 def walk_forces(pos, mass, tree: dict, theta: float = 0.75, n_crit: int = 512, eps: float = 0.0,
-                quadrupole: bool = True, lo=(0.0, 0.0, 0.0), side: float = 1.0, lib=None):
+                quadrupole: bool = True, lo=(0.0, 0.0, 0.0), side: float = 1.0, lib=None,
+                curve: str = "morton"):
     """Sequential Barnes-Hut group walk over an oracle tree (build() output).
     Returns (acc [N][5] in sorted order: ax, ay, az, phi, sum of |terms|,
     stats dict with the number of groups and interactions)."""
@@ -270,9 +321,10 @@ def walk_forces(pos, mass, tree: dict, theta: float = 0.75, n_crit: int = 512, e
     stats = np.zeros(2, dtype=np.int64)
     arrs = [np.ascontiguousarray(tree[k]) for k in ("perm", "cell_key", "cell_level", "cell_first",
                                                     "cell_count", "child_ptr", "com", "quad")]
-    rc = lib.tbg_walk_tree(_ptr(pos), _ptr(mass), _ptr(arrs[0]), n, *[_ptr(a) for a in arrs[1:]],
-                           _ptr(lo), side, float(theta), int(n_crit), float(eps),
-                           1 if quadrupole else 0, _ptr(acc), _ptr(stats))
+    rc = lib.tbg_walk_tree_curve(_ptr(pos), _ptr(mass), _ptr(arrs[0]), n,
+                                 *[_ptr(a) for a in arrs[1:]], _ptr(lo), side, float(theta),
+                                 int(n_crit), float(eps), 1 if quadrupole else 0, _curve(curve),
+                                 _ptr(acc), _ptr(stats))
     if rc:
         raise OracleError(rc)
     return acc, {"groups": int(stats[0]), "interactions": int(stats[1])}

@@ -103,7 +103,11 @@ int tbg_direct_subset(const float *pos, const float *mass, int64_t n, double eps
   return TBG_OK;
 }
 
+/* tb_oracle.c: cell coordinates of a Peano-Hilbert index */
+void tbo_hilbert_decode(const uint64_t *h, int64_t n, int bits, uint32_t *q);
+
 typedef struct {
+  int curve; /* 0: Morton keys, 1: Peano-Hilbert keys */
   const uint64_t *key;
   const uint8_t *level;
   const int32_t *first, *count, *child;
@@ -127,11 +131,16 @@ static void cell_geometry(const tbg_walk *w, int64_t c, double cen[3], double *l
   int d = w->level[c], k, a;
   uint64_t key = w->key[c];
   double h = ldexp(w->side, -d);
-  for (k = d - 1; k >= 0; --k) {
-    uint32_t oct = (uint32_t)((key >> (3 * k)) & 7u);
-    ijk[0] = (ijk[0] << 1) | ((oct >> 2) & 1u);
-    ijk[1] = (ijk[1] << 1) | ((oct >> 1) & 1u);
-    ijk[2] = (ijk[2] << 1) | (oct & 1u);
+  if (w->curve) {
+    const uint64_t idx = key & (((uint64_t)1 << (3 * d)) - 1u);
+    tbo_hilbert_decode(&idx, 1, d, ijk);
+  } else {
+    for (k = d - 1; k >= 0; --k) {
+      uint32_t oct = (uint32_t)((key >> (3 * k)) & 7u);
+      ijk[0] = (ijk[0] << 1) | ((oct >> 2) & 1u);
+      ijk[1] = (ijk[1] << 1) | ((oct >> 1) & 1u);
+      ijk[2] = (ijk[2] << 1) | (oct & 1u);
+    }
   }
   for (a = 0; a < 3; ++a) cen[a] = w->lo[a] + ((double)ijk[a] + 0.5) * h;
   *l = h;
@@ -265,16 +274,19 @@ static void walk_groups(tbg_walk *w, int64_t c, int32_t n_crit, double *acc, int
  *   acc [n][5]      out: (ax, ay, az, phi, sum of |term|) in sorted order
  *   stats [2]       out (may be NULL): groups, and interactions (cells +
  *                   particle pairs) summed over particles
+ *   curve           0: the cell keys are Morton keys, 1: Peano-Hilbert keys
  */
-int tbg_walk_tree(const float *pos, const float *mass, const int32_t *perm, int64_t n,
-                  const uint64_t *cell_key, const uint8_t *cell_level, const int32_t *cell_first,
-                  const int32_t *cell_count, const int32_t *child_ptr, const double *com,
-                  const double *quad, const double lo[3], double side, double theta,
-                  int32_t n_crit, double eps, int quad_on, double *acc, int64_t *stats) {
+int tbg_walk_tree_curve(const float *pos, const float *mass, const int32_t *perm, int64_t n,
+                        const uint64_t *cell_key, const uint8_t *cell_level,
+                        const int32_t *cell_first, const int32_t *cell_count,
+                        const int32_t *child_ptr, const double *com, const double *quad,
+                        const double lo[3], double side, double theta, int32_t n_crit,
+                        double eps, int quad_on, int curve, double *acc, int64_t *stats) {
   tbg_walk w;
   double *x = NULL, *m = NULL;
   int64_t s, groups = 0;
-  if (n < 0 || n_crit < 1 || !(theta >= 0.0) || !(eps >= 0.0)) return TBG_ERR_ARG;
+  if (n < 0 || n_crit < 1 || !(theta >= 0.0) || !(eps >= 0.0) || curve < 0 || curve > 1)
+    return TBG_ERR_ARG;
   if (n == 0) return TBG_OK;
   if (!pos || !mass || !perm || !cell_key || !cell_level || !cell_first || !cell_count ||
       !child_ptr || !com || !quad || !lo || !acc)
@@ -293,6 +305,7 @@ int tbg_walk_tree(const float *pos, const float *mass, const int32_t *perm, int6
     x[3 * s + 2] = pos[3 * (int64_t)p + 2];
     m[s] = mass[p];
   }
+  w.curve = curve;
   w.key = cell_key;
   w.level = cell_level;
   w.first = cell_first;
@@ -321,4 +334,14 @@ int tbg_walk_tree(const float *pos, const float *mass, const int32_t *perm, int6
   free(x);
   free(m);
   return w.failed ? TBG_ERR_NOMEM : TBG_OK;
+}
+
+int tbg_walk_tree(const float *pos, const float *mass, const int32_t *perm, int64_t n,
+                  const uint64_t *cell_key, const uint8_t *cell_level, const int32_t *cell_first,
+                  const int32_t *cell_count, const int32_t *child_ptr, const double *com,
+                  const double *quad, const double lo[3], double side, double theta,
+                  int32_t n_crit, double eps, int quad_on, double *acc, int64_t *stats) {
+  return tbg_walk_tree_curve(pos, mass, perm, n, cell_key, cell_level, cell_first, cell_count,
+                             child_ptr, com, quad, lo, side, theta, n_crit, eps, quad_on, 0, acc,
+                             stats);
 }

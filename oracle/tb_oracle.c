@@ -14,7 +14,13 @@
  *   2. key        -- the three integers are bit-interleaved below a leading 1
  *                    bit (Sec. 2.2); x is the most significant bit of each
  *                    3-bit octant digit (a reading: the paper does not fix the
- *                    axis order).
+ *                    axis order).  The Peano-Hilbert variant (footnote of
+ *                    Sec. 2.2) takes instead the index of the cell on the 3-D
+ *                    Hilbert curve of Skilling's transpose method (J. Skilling,
+ *                    "Programming the Hilbert curve", AIP Conf. Proc. 707, 381,
+ *                    2004), in the same layout: a cell's key is still the upper
+ *                    3d + 1 bits of its particles' keys, but a child's 3-bit digit
+ *                    is its place along the curve rather than its octant.
  *   3. insertion  -- the classic Barnes-Hut top-down build (Sec. 2.1): particles
  *                    are inserted one at a time from the root; a cell that holds
  *                    more than n_leaf particles is halved along every axis and
@@ -98,11 +104,92 @@ static uint64_t interleave_key(uint32_t qx, uint32_t qy, uint32_t qz) {
   return k;
 }
 
-int tbo_keys(const float *pos, int64_t n, const double lo[3], double side,
-             uint32_t *q_out /* [n][3] or NULL */, uint64_t *key_out /* [n] */) {
+/* Peano-Hilbert index of cell (x, y, z) on the curve of `bits` levels
+ * (Skilling's method).  First the coordinates become the curve's "transposed"
+ * index: from the top level down, a coordinate whose bit at this level is set
+ * inverts the lower bits of x, and one whose bit is clear exchanges its lower
+ * bits with those of x; then a Gray-code decode along x, y, z.  The index's
+ * digit at each level is (x, y, z) of the transposed form at that level, x the
+ * most significant.  Bits 3*bits-1 .. 0 of the result; no leading 1. */
+static uint64_t hilbert_encode(uint32_t x, uint32_t y, uint32_t z, int bits) {
+  uint32_t X[3], Q, P, t;
+  uint64_t h = 0;
+  int i, b;
+  X[0] = x;
+  X[1] = y;
+  X[2] = z;
+  if (bits <= 0) return 0;
+  for (Q = 1u << (bits - 1); Q > 1u; Q >>= 1) {
+    P = Q - 1u;
+    for (i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  t = 0;
+  for (Q = 1u << (bits - 1); Q > 1u; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1u;
+  for (i = 0; i < 3; ++i) X[i] ^= t;
+  for (b = bits - 1; b >= 0; --b)
+    for (i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> b) & 1u);
+  return h;
+}
+
+/* Inverse of hilbert_encode: cell coordinates of index h on the curve of
+ * `bits` levels. */
+static void hilbert_decode(uint64_t h, int bits, uint32_t q[3]) {
+  uint32_t X[3] = {0u, 0u, 0u}, N, Q, P, t;
+  int i, b;
+  for (b = bits - 1; b >= 0; --b)
+    for (i = 0; i < 3; ++i) X[i] |= (uint32_t)((h >> (3 * b + 2 - i)) & 1u) << b;
+  if (bits > 0) {
+    N = 2u << (bits - 1);
+    t = X[2] >> 1;
+    X[2] ^= X[1];
+    X[1] ^= X[0];
+    X[0] ^= t;
+    for (Q = 2u; Q != N; Q <<= 1) {
+      P = Q - 1u;
+      for (i = 2; i >= 0; --i) {
+        if (X[i] & Q) {
+          X[0] ^= P;
+        } else {
+          t = (X[0] ^ X[i]) & P;
+          X[0] ^= t;
+          X[i] ^= t;
+        }
+      }
+    }
+  }
+  q[0] = X[0];
+  q[1] = X[1];
+  q[2] = X[2];
+}
+
+void tbo_hilbert_encode(const uint32_t *q /* [n][3] */, int64_t n, int bits, uint64_t *h) {
+  int64_t i;
+  for (i = 0; i < n; ++i) h[i] = hilbert_encode(q[3 * i], q[3 * i + 1], q[3 * i + 2], bits);
+}
+
+void tbo_hilbert_decode(const uint64_t *h, int64_t n, int bits, uint32_t *q /* [n][3] */) {
+  int64_t i;
+  for (i = 0; i < n; ++i) hilbert_decode(h[i], bits, &q[3 * i]);
+}
+
+/* curve 0: Morton keys; 1: Peano-Hilbert keys, each below a leading 1. */
+int tbo_keys_curve(const float *pos, int64_t n, const double lo[3], double side, int curve,
+                   uint32_t *q_out /* [n][3] or NULL */, uint64_t *key_out /* [n] */) {
   double scale;
   int64_t i;
-  if (n < 0 || (n > 0 && (!pos || !key_out)) || !lo) return TBO_ERR_ARG;
+  if (n < 0 || (n > 0 && (!pos || !key_out)) || !lo || curve < 0 || curve > 1)
+    return TBO_ERR_ARG;
   if (!side_is_pow2(side) || !isfinite(lo[0]) || !isfinite(lo[1]) || !isfinite(lo[2]))
     return TBO_ERR_BOX;
   scale = ldexp(1.0, 21) / side;
@@ -115,9 +202,15 @@ int tbo_keys(const float *pos, int64_t n, const double lo[3], double side,
       q_out[3 * i + 1] = q1;
       q_out[3 * i + 2] = q2;
     }
-    key_out[i] = interleave_key(q0, q1, q2);
+    key_out[i] = curve ? ((uint64_t)1 << 63) | hilbert_encode(q0, q1, q2, TBO_MAX_DEPTH)
+                       : interleave_key(q0, q1, q2);
   }
   return TBO_OK;
+}
+
+int tbo_keys(const float *pos, int64_t n, const double lo[3], double side,
+             uint32_t *q_out /* [n][3] or NULL */, uint64_t *key_out /* [n] */) {
+  return tbo_keys_curve(pos, n, lo, side, 0, q_out, key_out);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -140,6 +233,7 @@ typedef struct {
   tbo_node *v;
   int64_t n, cap;
   const uint32_t *q;
+  const uint64_t *keys; /* particle keys: a child's key is their prefix */
   int32_t n_leaf;
   int failed;
 } tbo_tree;
@@ -190,11 +284,14 @@ static int octant_of(const tbo_tree *t, int32_t p, int level) {
   return (int)((((q[0] >> b) & 1u) << 2) | (((q[1] >> b) & 1u) << 1) | ((q[2] >> b) & 1u));
 }
 
-static int64_t child_for(tbo_tree *t, int64_t node, int oct) {
+/* The child of `node` in octant `oct`, created for particle p if missing.  Its
+ * key is the prefix of p's key (for Morton keys, the parent's key followed by
+ * the octant). */
+static int64_t child_for(tbo_tree *t, int64_t node, int oct, int32_t p) {
   int64_t c = t->v[node].child[oct];
   if (c < 0) {
     int lvl = t->v[node].level + 1;
-    uint64_t key = (t->v[node].key << 3) | (uint64_t)oct;
+    uint64_t key = t->keys[p] >> (3 * (TBO_MAX_DEPTH - lvl));
     c = new_node(t, lvl, key); /* may move t->v */
     if (c < 0) return -1;
     t->v[node].child[oct] = (int)c;
@@ -217,7 +314,7 @@ static void split(tbo_tree *t, int64_t node) {
   t->v[node].is_leaf = 0;
   for (k = 0; k < cnt && !t->failed; ++k) {
     int32_t p = mem[k];
-    int64_t c = child_for(t, node, octant_of(t, p, t->v[node].level));
+    int64_t c = child_for(t, node, octant_of(t, p, t->v[node].level), p);
     if (c < 0) break;
     push_member(t, c, p);
   }
@@ -231,7 +328,7 @@ static void split(tbo_tree *t, int64_t node) {
 static void insert(tbo_tree *t, int32_t p) {
   int64_t node = 0;
   while (!t->v[node].is_leaf) {
-    node = child_for(t, node, octant_of(t, p, t->v[node].level));
+    node = child_for(t, node, octant_of(t, p, t->v[node].level), p);
     if (node < 0) return;
   }
   if (push_member(t, node, p) < 0) return;
@@ -261,19 +358,34 @@ static int cmp_idx_by_key(const void *a, const void *b) {
   return (i > j) - (i < j);
 }
 
-/* Depth-first walk: children in octant order; a leaf's particles by (key, index). */
+/* The children of a node in key order (for Morton keys, octant order); returns
+ * how many. */
+static int children_by_key(const tbo_tree *t, int64_t node, int64_t out[8]) {
+  int n = 0, oct, k;
+  for (oct = 0; oct < 8; ++oct) {
+    int64_t c = t->v[node].child[oct];
+    if (c < 0) continue;
+    for (k = n; k > 0 && t->v[out[k - 1]].key > t->v[c].key; --k) out[k] = out[k - 1];
+    out[k] = c;
+    ++n;
+  }
+  return n;
+}
+
+/* Depth-first walk: children in key order; a leaf's particles by (key, index). */
 static void dfs_emit(tbo_tree *t, int64_t node, const uint64_t *keys, int32_t *out, int64_t *w) {
   tbo_node *nd = &t->v[node];
-  int oct;
+  int64_t ch[8];
+  int k, nch;
   if (nd->is_leaf) {
-    int64_t k;
+    int64_t j;
     g_keys_for_cmp = keys;
     qsort(nd->mem, (size_t)nd->cnt, sizeof(int32_t), cmp_idx_by_key);
-    for (k = 0; k < nd->cnt; ++k) out[(*w)++] = nd->mem[k];
+    for (j = 0; j < nd->cnt; ++j) out[(*w)++] = nd->mem[j];
     return;
   }
-  for (oct = 0; oct < 8; ++oct)
-    if (nd->child[oct] >= 0) dfs_emit(t, nd->child[oct], keys, out, w);
+  nch = children_by_key(t, node, ch);
+  for (k = 0; k < nch; ++k) dfs_emit(t, ch[k], keys, out, w);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -308,16 +420,21 @@ static void nsum_add(tbo_sum *a, double x) {
 static double nsum_val(const tbo_sum *a) { return a->s + a->c; }
 
 /* Cell centre in the box frame: (ijk + 1/2) * side * 2^-level per axis, with
- * ijk read back out of the cell key. */
-static void cell_offset(uint64_t key, int level, double side, double off[3]) {
+ * ijk read back out of the cell key (curve 1: decoded from the Hilbert index
+ * below the leading 1). */
+static void cell_offset(uint64_t key, int level, double side, int curve, double off[3]) {
   uint32_t ijk[3] = {0u, 0u, 0u};
   int l;
   double h = ldexp(side, -level);
-  for (l = 0; l < level; ++l) {
-    int sh = 3 * (level - 1 - l);
-    ijk[0] = (ijk[0] << 1) | (uint32_t)((key >> (sh + 2)) & 1u);
-    ijk[1] = (ijk[1] << 1) | (uint32_t)((key >> (sh + 1)) & 1u);
-    ijk[2] = (ijk[2] << 1) | (uint32_t)((key >> sh) & 1u);
+  if (curve) {
+    hilbert_decode(key & (((uint64_t)1 << (3 * level)) - 1u), level, ijk);
+  } else {
+    for (l = 0; l < level; ++l) {
+      int sh = 3 * (level - 1 - l);
+      ijk[0] = (ijk[0] << 1) | (uint32_t)((key >> (sh + 2)) & 1u);
+      ijk[1] = (ijk[1] << 1) | (uint32_t)((key >> (sh + 1)) & 1u);
+      ijk[2] = (ijk[2] << 1) | (uint32_t)((key >> sh) & 1u);
+    }
   }
   off[0] = ((double)ijk[0] + 0.5) * h;
   off[1] = ((double)ijk[1] + 0.5) * h;
@@ -326,13 +443,13 @@ static void cell_offset(uint64_t key, int level, double side, double off[3]) {
 
 static void cell_moments(const float *pos, const float *mass, const double lo[3], double side,
                          const int32_t *perm, int64_t first, int64_t count, uint64_t key,
-                         int level, double com_out[4], double quad_out[6]) {
+                         int level, int curve, double com_out[4], double quad_out[6]) {
   double off[3], M, c[3];
   tbo_sum sm = {0, 0}, s1[3] = {{0, 0}, {0, 0}, {0, 0}};
   tbo_sum s2[6] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
   int64_t k;
   int a;
-  cell_offset(key, level, side, off);
+  cell_offset(key, level, side, curve, off);
   /* pass 1: mass and centre of mass */
   for (k = first; k < first + count; ++k) {
     int32_t p = perm[k];
@@ -398,8 +515,8 @@ int64_t tbo_max_cells(int64_t n, int32_t n_leaf) {
  * 3 (insertion), 4 (perm and its DFS cross-check), 5 (canonical order, ranges,
  * child links) and 6 (moments).
  */
-int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
-                    const double lo[3], double side, int32_t *perm, int32_t *dfs_perm,
+int tbo_build_curve(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                    const double lo[3], double side, int curve, int32_t *perm, int32_t *dfs_perm,
                     uint64_t *cell_key, uint8_t *cell_level, int32_t *cell_first,
                     int32_t *cell_count, int32_t *child_ptr, double *com, double *quad,
                     int64_t *level_offset, int64_t *n_cells, double *stage_s) {
@@ -415,7 +532,8 @@ int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_le
 
   if (stage_s)
     for (lvl = 0; lvl < 5; ++lvl) stage_s[lvl] = 0.0;
-  if (n < 0 || n > 2147483647LL || n_leaf < 1 || !lo || !n_cells || !level_offset)
+  if (n < 0 || n > 2147483647LL || n_leaf < 1 || !lo || !n_cells || !level_offset || curve < 0 ||
+      curve > 1)
     return TBO_ERR_ARG;
   if (n > 0 && (!pos || !mass || !perm || !cell_key || !cell_level || !cell_first ||
                 !cell_count || !child_ptr))
@@ -440,7 +558,7 @@ int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_le
     rc = TBO_ERR_NOMEM;
     goto done;
   }
-  rc = tbo_keys(pos, n, lo, side, q, keys);
+  rc = tbo_keys_curve(pos, n, lo, side, curve, q, keys);
   if (rc) goto done;
   t1 = now_s();
   if (stage_s) stage_s[0] = t1 - t0;
@@ -448,6 +566,7 @@ int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_le
 
   /* step 3: top-down insertion in index order */
   t.q = q;
+  t.keys = keys;
   t.n_leaf = n_leaf;
   if (new_node(&t, 0, 1u) < 0) {
     rc = TBO_ERR_NOMEM;
@@ -523,11 +642,10 @@ int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_le
         goto done;
       }
     } else {
-      int64_t first = -1, end = -1, cnt = 0;
-      int oct;
-      for (oct = 0; oct < 8; ++oct) {
-        int64_t ch = nd->child[oct];
-        if (ch < 0) continue;
+      int64_t first = -1, end = -1, cnt = 0, chs[8];
+      int k, nch = children_by_key(&t, order[c], chs);
+      for (k = 0; k < nch; ++k) {
+        int64_t ch = chs[k];
         if (first < 0) {
           first = t.v[ch].first;
         } else if (t.v[ch].first != end) {
@@ -544,18 +662,13 @@ int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_le
 
   for (c = 0; c < nc; ++c) {
     tbo_node *nd = &t.v[order[c]];
-    int oct, nchild = 0;
-    int64_t first_child = -1;
+    int64_t chs[8];
+    int nchild = children_by_key(&t, order[c], chs);
+    int64_t first_child = nchild > 0 ? t.v[chs[0]].canon : -1;
     cell_key[c] = nd->key;
     cell_level[c] = (uint8_t)nd->level;
     cell_first[c] = (int32_t)nd->first;
     cell_count[c] = (int32_t)nd->count;
-    for (oct = 0; oct < 8; ++oct) {
-      int64_t ch = nd->child[oct];
-      if (ch < 0) continue;
-      if (first_child < 0) first_child = t.v[ch].canon;
-      ++nchild;
-    }
     child_ptr[2 * c] = nd->is_leaf ? -1 : (int32_t)first_child;
     child_ptr[2 * c + 1] = nd->is_leaf ? 0 : nchild;
   }
@@ -572,7 +685,7 @@ int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_le
   if (com && quad) {
     for (c = 0; c < nc; ++c)
       cell_moments(pos, mass, lo, side, perm, cell_first[c], cell_count[c], cell_key[c],
-                   cell_level[c], &com[4 * c], &quad[6 * c]);
+                   cell_level[c], curve, &com[4 * c], &quad[6 * c]);
   }
   if (stage_s) stage_s[4] = now_s() - t0;
 
@@ -586,6 +699,16 @@ done:
   free(pos_of);
   free(order);
   return rc;
+}
+
+int tbo_build_timed(const float *pos, const float *mass, int64_t n, int32_t n_leaf,
+                    const double lo[3], double side, int32_t *perm, int32_t *dfs_perm,
+                    uint64_t *cell_key, uint8_t *cell_level, int32_t *cell_first,
+                    int32_t *cell_count, int32_t *child_ptr, double *com, double *quad,
+                    int64_t *level_offset, int64_t *n_cells, double *stage_s) {
+  return tbo_build_curve(pos, mass, n, n_leaf, lo, side, 0, perm, dfs_perm, cell_key, cell_level,
+                         cell_first, cell_count, child_ptr, com, quad, level_offset, n_cells,
+                         stage_s);
 }
 
 int tbo_build(const float *pos, const float *mass, int64_t n, int32_t n_leaf, const double lo[3],
@@ -607,7 +730,7 @@ int tbo_cell_moments(const float *pos, const float *mass, const double lo[3], do
       level < 0 || level > TBO_MAX_DEPTH)
     return TBO_ERR_ARG;
   if (!side_is_pow2(side)) return TBO_ERR_BOX;
-  cell_moments(pos, mass, lo, side, perm, first, count, key, level, com_out, quad_out);
+  cell_moments(pos, mass, lo, side, perm, first, count, key, level, 0, com_out, quad_out);
   return TBO_OK;
 }
 

@@ -35,12 +35,21 @@ MUTANTS = {
     "depth_cap": ("#define TBO_MAX_DEPTH 21", "#define TBO_MAX_DEPTH 20"),
     # the single-cell entry point used by the sampled full-size checks
     "cell_moments_first_count": (
-        "cell_moments(pos, mass, lo, side, perm, first, count, key, level, com_out, quad_out);",
-        "cell_moments(pos, mass, lo, side, perm, count, first, key, level, com_out, quad_out);"),
+        "cell_moments(pos, mass, lo, side, perm, first, count, key, level, 0, com_out, quad_out);",
+        "cell_moments(pos, mass, lo, side, perm, count, first, key, level, 0, com_out, quad_out);"),
     "cell_moments_frame": (
-        "cell_moments(pos, mass, lo, side, perm, first, count, key, level, com_out, quad_out);",
-        "cell_moments(pos, mass, lo, side, perm, first, count, key >> 3, level - 1, com_out,"
+        "cell_moments(pos, mass, lo, side, perm, first, count, key, level, 0, com_out, quad_out);",
+        "cell_moments(pos, mass, lo, side, perm, first, count, key >> 3, level - 1, 0, com_out,"
         " quad_out);"),
+    # Peano-Hilbert keys
+    "hilbert_gray_step": ("  X[1] ^= X[0];\n  X[2] ^= X[1];\n  t = 0;", "  X[2] ^= X[1];\n  t = 0;"),
+    "hilbert_last_level": ("for (Q = 1u << (bits - 1); Q > 1u; Q >>= 1) {\n    P = Q - 1u;",
+                           "for (Q = 1u << (bits - 1); Q > 2u; Q >>= 1) {\n    P = Q - 1u;"),
+    "hilbert_digit_order": ("h = (h << 1) | ((X[i] >> b) & 1u);",
+                            "h = (h << 1) | ((X[2 - i] >> b) & 1u);"),
+    "hilbert_decode_gray": ("    X[0] ^= t;\n    for (Q = 2u;", "    for (Q = 2u;"),
+    "hilbert_child_key": ("uint64_t key = t->keys[p] >> (3 * (TBO_MAX_DEPTH - lvl));",
+                          "uint64_t key = (t->v[node].key << 3) | (uint64_t)oct;"),
 }
 
 
@@ -116,7 +125,34 @@ def _pin_checks(lib):
             assert max(abs(com[a] - float(cx[a])) for a in range(3)) <= 1e-15 * l
             assert max(abs(quad[i] - float(qx[i])) for i in range(6)) <= 1e-14 * float(M) * l * l
 
+    def hilbert_curve():
+        for bits in (1, 2, 3):
+            n = 8 ** bits
+            q = oracle.hilbert_decode(np.arange(n, dtype=np.uint64), bits, lib=lib).astype(np.int64)
+            assert len({tuple(r) for r in q}) == n and not q[0].any()
+            assert np.all(np.abs(np.diff(q, axis=0)).sum(1) == 1)
+            h = oracle.hilbert_encode(q.astype(np.uint32), bits, lib=lib)
+            assert np.array_equal(h, np.arange(n, dtype=np.uint64))
+        q = _rng(401).integers(0, 2 ** 21, (500, 3), dtype=np.uint32)
+        h = oracle.hilbert_encode(q, 21, lib=lib)
+        for d in (1, 5, 20):
+            assert np.array_equal(h >> np.uint64(3 * (21 - d)),
+                                  oracle.hilbert_encode(q >> np.uint32(21 - d), d, lib=lib))
+
+    def hilbert_tree():
+        rng = _rng(402)
+        pos = rng.random((300, 3), dtype=np.float32)
+        m = np.ones(300, np.float32)
+        tm = oracle.build(pos, m, 4, lib=lib)
+        th = oracle.build(pos, m, 4, lib=lib, curve="hilbert")
+        assert th["n_cells"] == tm["n_cells"]
+        _, k = oracle.keys(pos, lib=lib, curve="hilbert")
+        tc.check_invariants(th, k[th["perm"]], 4)
+        assert np.allclose(np.sort(th["com"][:, 3]), np.sort(tm["com"][:, 3]), rtol=1e-14)
+
     check("hand_keys", hand_keys)
+    check("hilbert_curve", hilbert_curve)
+    check("hilbert_tree", hilbert_tree)
     check("set_definition", set_definition)
     check("coincident", coincident)
     check("exact_moments", exact_moments)
