@@ -73,6 +73,8 @@ def parse():
                          "timing the subtree-rooted cell build on the same data")
     ap.add_argument("--sort-counted", action="store_true",
                     help="count the tiles' digits in every radix pass (TB_SORT_COUNTED)")
+    ap.add_argument("--curve", default="morton", choices=["morton", "hilbert"],
+                    help="particle keys: Morton (default) or Peano-Hilbert (TB_HILBERT)")
     ap.add_argument("--subtrees", action="store_true",
                     help="time the subtree-rooted cell build (TB_SUBTREES) as the step")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -294,7 +296,7 @@ def run_single(args, tb, dg, torch, np):
     mass = torch.from_numpy(mass_np).to(dev)
     box = ((0.0, 0.0, 0.0), 1.0)
     b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=args.subtrees,
-                   counted=args.sort_counted)
+                   counted=args.sort_counted, curve=args.curve)
     run = lambda: b.launch(pos, mass, box)
     sec = time_steps(run, args.steps, args.warmup)
     print(f"[bench] {args.steps} builds, {sec * 1e3:.3f} ms/build", file=sys.stderr, flush=True)
@@ -316,7 +318,7 @@ def run_single(args, tb, dg, torch, np):
                    "sort_config": list(tb.tb_sort_configs()[k]), "cells": cells,
                    "leaves": leaves,
                    "cell_build": "subtree-rooted blocks" if args.subtrees else "tiles + parents",
-                   "sort_counted_all_passes": bool(args.sort_counted)},
+                   "sort_counted_all_passes": bool(args.sort_counted), "keys": args.curve},
         "roofline": roofline(trace, alg, key_passes, args.workload),
         "build_method_bytes": total_method,
         "build_alg_GBps": round(total_method / sec / 1e9, 1),
@@ -328,7 +330,7 @@ def run_single(args, tb, dg, torch, np):
     if not args.no_compare:
         # the other cell build on the same data (the tree is the same either way)
         alt_b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=not args.subtrees,
-                           counted=args.sort_counted)
+                           counted=args.sort_counted, curve=args.curve)
         alt_run = lambda: alt_b.launch(pos, mass, box)
         sec_alt = time_steps(alt_run, args.steps, args.warmup)
         alt = alt_b.result()

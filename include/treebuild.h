@@ -119,6 +119,19 @@ extern "C" {
  * differ. */
 #define TB_SUBTREES (1u << 18)
 
+/* Peano-Hilbert keys in place of Morton keys (footnote of Sec. 2.2).  The key
+ * keeps its layout (a leading 1, then 21 3-bit digits), but the digits are the
+ * index of the particle's depth-21 cell along the 3-D Hilbert curve of
+ * Skilling's transpose method (J. Skilling, AIP Conf. Proc. 707, 381, 2004);
+ * the curve starts at the box corner lo and steps between face neighbours, and
+ * the top 3d bits of a key are the index of the depth-d cell on the d-level
+ * curve, so cell keys are still prefixes of their particles' keys.  The cells,
+ * their particles and moments are those of the Morton tree; cell_key holds the
+ * Hilbert prefixes, cells and particles follow Hilbert order within a depth,
+ * and a child's octant is no longer its key's last digit.  Pass the same bit
+ * to tb_gravity for a tree built with it. */
+#define TB_HILBERT (1u << 20)
+
 #define TB_MAX_DEPTH 21
 #define TB_MAX_NLEAF 1024 /* largest supported n_leaf */
 #define TB_MAX_N 2147483647LL
@@ -279,7 +292,8 @@ int tb_build_batched_sync(const float *pos, const float *mass, int64_t n_total, 
  *   theta       opening angle (>= 0; 0 opens everything: direct summation)
  *   n_crit      group size (>= 1)
  *   eps         Plummer softening of the particle terms (>= 0)
- *   flags       0 or TB_GRAV_QUADRUPOLE
+ *   flags       0 or TB_GRAV_QUADRUPOLE, plus TB_HILBERT for a tree built on
+ *               Peano-Hilbert keys
  *   acc         [N][4] double, DEVICE, out: ax, ay, az, phi in key order
  *   stats       [2] int64, DEVICE, or NULL: number of groups, and number of
  *               interactions (cell terms plus particle pairs) over all particles

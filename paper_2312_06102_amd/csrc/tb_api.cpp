@@ -208,7 +208,8 @@ static int check_sizes(int64_t n, int32_t n_leaf) {
 static int config_from_flags(uint32_t flags, SortConfig *sc) {
   const uint32_t prec = flags & 0xffu;
   if (prec != TB_FP64 && prec != TB_MIXED) return TB_ERR_ARG;
-  if (flags & ~(0xffffu | TB_SORT_LOOKBACK | TB_SUBTREES | TB_SORT_COUNTED)) return TB_ERR_ARG;
+  if (flags & ~(0xffffu | TB_SORT_LOOKBACK | TB_SUBTREES | TB_SORT_COUNTED | TB_HILBERT))
+    return TB_ERR_ARG;
   if ((flags & TB_SORT_LOOKBACK) && (flags & TB_SORT_COUNTED)) return TB_ERR_ARG;
   const int k = (int)((flags >> 8) & 0xffu);
   if (k >= kSortTableSize) return TB_ERR_ARG;
@@ -424,7 +425,7 @@ int tb_gravity(const float *pos_sorted, const float *mass_sorted, int64_t n, con
   if (n < 0 || n > TB_MAX_N || c_max < 0 || c_max > 2147483647LL || n_crit < 1) return TB_ERR_ARG;
   if (!(theta >= 0.0) || !std::isfinite(theta) || !(eps >= 0.0) || !std::isfinite(eps))
     return TB_ERR_ARG;
-  if (flags & ~TB_GRAV_QUADRUPOLE) return TB_ERR_ARG;
+  if (flags & ~(TB_GRAV_QUADRUPOLE | TB_HILBERT)) return TB_ERR_ARG;
   if (!tree) return TB_ERR_ARG;
   if (n == 0) return TB_OK;
   if (!pos_sorted || !mass_sorted || !acc || !tree->cell_key || !tree->cell_level ||
@@ -433,7 +434,8 @@ int tb_gravity(const float *pos_sorted, const float *mass_sorted, int64_t n, con
     return TB_ERR_ARG;
   if (!workspace || ws_bytes < tb::gravity_workspace_bytes(c_max)) return TB_ERR_WORKSPACE;
   tb::GravIn in{pos_sorted, mass_sorted, n, tree, c_max, theta, eps, n_crit,
-                (flags & TB_GRAV_QUADRUPOLE) != 0, acc, stats, workspace};
+                (flags & TB_GRAV_QUADRUPOLE) != 0, (flags & TB_HILBERT) != 0, acc, stats,
+                workspace};
   return tb::launch_gravity(in, static_cast<hipStream_t>(stream)) == hipSuccess ? TB_OK
                                                                                : TB_ERR_HIP;
 }

@@ -200,6 +200,7 @@ struct BlockOut {
   uint32_t *upper_cnt;  // [kLevels]
   int64_t upper_cap;
   int64_t c_max;
+  bool hilbert;  // Peano-Hilbert keys
 };
 
 template <bool MIXED>
@@ -207,8 +208,8 @@ __device__ inline void leaf_moments(const BlockOut &o, int64_t ci, const float4 
                                     int64_t i, int64_t e, uint64_t key, int dl, const double lo[3],
                                     double side) {
   const int sh = kMaxDepth - dl;
-  const uint32_t ijk[3] = {compact3(key >> 2) >> sh, compact3(key >> 1) >> sh,
-                           compact3(key) >> sh};
+  uint32_t ijk[3];
+  cell_coords(key >> (3 * sh), dl, o.hilbert, ijk);
   if constexpr (!MIXED) {
     const double h = ldexp(side, -dl);
     const double off[3] = {((double)ijk[0] + 0.5) * h, ((double)ijk[1] + 0.5) * h,
@@ -239,10 +240,12 @@ __device__ inline void parent_moments(const BlockOut &o, int64_t pc, int64_t c0,
                                       double side) {
   if constexpr (!MIXED)
     parent_from_children_fp64(pc, c0, nch, dp, side, o.cell_key, o.cell_count, o.child_ptr,
-                              static_cast<double *>(o.com), static_cast<double *>(o.quad));
+                              static_cast<double *>(o.com), static_cast<double *>(o.quad),
+                              o.hilbert);
   else
     parent_from_children_mixed(pc, c0, nch, dp, side, o.cell_key, o.cell_count, o.child_ptr,
-                               static_cast<float *>(o.com), static_cast<float *>(o.quad), o.m_lo);
+                               static_cast<float *>(o.com), static_cast<float *>(o.quad), o.m_lo,
+                               o.hilbert);
 }
 
 // The structure of cell (d, key) with first particle i; nch and count of
@@ -728,6 +731,7 @@ static BlockOut block_out(const Plan &p, const Work &w, const tb_tree &out) {
   o.upper_cnt = w.counters + kUpperCounter;
   o.upper_cap = p.upper_cap;
   o.c_max = p.c_max;
+  o.hilbert = (p.flags & TB_HILBERT) != 0;
   return o;
 }
 

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kCellThreads) void k_reorder(
     int64_t cell_tiles, float4 *__restrict__ sorted, uint64_t *__restrict__ keys,
     uint64_t *__restrict__ key_out, float *__restrict__ pos_sorted,
     float *__restrict__ mass_sorted, uint16_t *__restrict__ ad, uint32_t *__restrict__ tile_cnt,
-    int32_t *__restrict__ status_word) {
+    int hilbert, int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
   const WindowLds s = carve_window(lds, nl);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -234,7 +234,8 @@ __global__ __launch_bounds__(kCellThreads) void k_reorder(
       const int64_t g = ws + i;
       const bool in = i < wn && g >= tr.S && g < tr.E;
       const uint64_t key =
-          in ? morton_key(rec[r].x, rec[r].y, rec[r].z, lo0, lo1, lo2, scale) : 0ull;
+          in ? particle_key(rec[r].x, rec[r].y, rec[r].z, lo0, lo1, lo2, scale, hilbert != 0)
+             : 0ull;
       if (i < wn) s.keys[i] = key;
       if (g >= t0 && g < t1 && i < wn) {
         sorted[g] = rec[r];
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     uint8_t *__restrict__ cell_level, int32_t *__restrict__ cell_first,
     int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr, void *__restrict__ com_v,
     void *__restrict__ quad_v, float *__restrict__ m_lo, int32_t *__restrict__ head_parent,
-    int64_t c_max, int32_t *__restrict__ status_word) {
+    int64_t c_max, int hilbert, int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
   const EmitLds s = carve_emit(lds, nl);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -614,7 +615,14 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     const int64_t e = leaf_end_fast(s, keys, n, nl, t0, T, li, dl);
     cell_count[ci] = (int32_t)(e - i);
     const int sh = kMaxDepth - dl;
-    const uint32_t ijk[3] = {compact3(key >> 2) >> sh, compact3(key >> 1) >> sh, compact3(key) >> sh};
+    uint32_t ijk[3];
+    if (hilbert) {
+      cell_coords(key >> (3 * sh), dl, true, ijk);
+    } else {
+      ijk[0] = compact3(key >> 2) >> sh;
+      ijk[1] = compact3(key >> 1) >> sh;
+      ijk[2] = compact3(key) >> sh;
+    }
     const int64_t e_lds = min(e, t0 + (int64_t)span);
     if constexpr (!MIXED) {
       double *com = static_cast<double *>(com_v);
@@ -685,7 +693,7 @@ hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipS
   k_reorder<<<(unsigned)p.cell_tiles, kCellThreads, window_lds_bytes(p.n_leaf), s>>>(
       out.perm, w.packed, p.n, p.n_leaf, w.tile_start, w.tile_set, w.set_off, p.nsets, w.box,
       p.cell_tiles, w.sorted, sorted_keys(p, w), out.key_sorted, out.pos_sorted, out.mass_sorted,
-      w.ad, w.cell_cnt, out.status);
+      w.ad, w.cell_cnt, (p.flags & TB_HILBERT) ? 1 : 0, out.status);
   return hipGetLastError();
 }
 
@@ -720,7 +728,7 @@ hipError_t launch_cell_emit(const Plan &p, const Work &w, const tb_tree &out, hi
       sorted_keys(p, w), w.ad, p.n_leaf, w.cell_excl, p.cell_tiles, w.tile_start, w.tile_set,
       w.set_off, p.nsets, w.lvl_off, w.box, w.sorted, out.cell_key, out.cell_level,
       out.cell_first, out.cell_count, out.child_ptr, out.com, out.quad, w.m_lo, w.head_parent,
-      p.c_max, out.status);
+      p.c_max, (p.flags & TB_HILBERT) ? 1 : 0, out.status);
   return hipGetLastError();
 }
 

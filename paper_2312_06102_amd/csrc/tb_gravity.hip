@@ -20,6 +20,7 @@
 //                  run), then every thread adds the round's cell and particle
 //                  terms to its own group particles.  FP64 throughout.
 #include "tb_internal.h"
+#include "tb_moments.h"
 
 namespace tb {
 
@@ -39,19 +40,14 @@ struct GravArgs {
   const float *mass;  // sorted masses [n]
   double theta2, eps2;
   int quad_on;
+  int hilbert;  // the cell keys are Peano-Hilbert keys
 };
 
 // Geometric centre (absolute) and side of cell c.
 __device__ inline void cell_centre(const GravArgs &g, int64_t c, double cen[3], double &l) {
   const int d = g.level[c];
-  const uint64_t key = g.key[c];
-  uint32_t ijk[3] = {0u, 0u, 0u};
-  for (int k = d - 1; k >= 0; --k) {
-    const uint32_t oct = (uint32_t)((key >> (3 * k)) & 7u);
-    ijk[0] = (ijk[0] << 1) | ((oct >> 2) & 1u);
-    ijk[1] = (ijk[1] << 1) | ((oct >> 1) & 1u);
-    ijk[2] = (ijk[2] << 1) | (oct & 1u);
-  }
+  uint32_t ijk[3];
+  cell_coords(g.key[c], d, g.hilbert != 0, ijk);
   l = ldexp(g.box[3], -d);
 #pragma unroll
   for (int a = 0; a < 3; ++a) cen[a] = g.box[a] + ((double)ijk[a] + 0.5) * l;
@@ -328,6 +324,7 @@ hipError_t launch_gravity(const GravIn &in, hipStream_t s) {
   g.theta2 = in.theta * in.theta;
   g.eps2 = in.eps * in.eps;
   g.quad_on = in.quadrupole ? 1 : 0;
+  g.hilbert = in.hilbert ? 1 : 0;
   int32_t *groups = static_cast<int32_t *>(in.workspace);
   uint32_t *n_groups = reinterpret_cast<uint32_t *>(groups + in.c_max);
   k_grav_init<<<1, 64, 0, s>>>(n_groups, reinterpret_cast<unsigned long long *>(in.stats));

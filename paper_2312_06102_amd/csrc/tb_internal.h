@@ -205,6 +205,7 @@ struct GravIn {
   double theta, eps;
   int32_t n_crit;
   bool quadrupole;
+  bool hilbert;             // the tree was built on Peano-Hilbert keys
   double *acc;              // [n][4] device: ax, ay, az, phi in key order
   int64_t *stats;           // [2] device or NULL: groups, interactions
   void *workspace;          // int32 [c_max] groups + u32 counter
@@ -323,6 +324,57 @@ __device__ __forceinline__ uint64_t morton_key(float x, float y, float z, double
   const uint64_t qy = quantise(y, lo1, scale);
   const uint64_t qz = quantise(z, lo2, scale);
   return (1ull << 63) | (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+}
+
+// Peano-Hilbert variant of the key (footnote of Sec. 2.2): the same layout,
+// but the 63 bits below the leading 1 are the cell's index on the 3-D Hilbert
+// curve of Skilling's transpose method (AIP Conf. Proc. 707, 381, 2004).  From
+// the top level down, an axis whose bit is set inverts the lower bits of x and
+// an axis whose bit is clear swaps its lower bits with x's; a Gray-code decode
+// along (x, y, z) follows.  Each level's bits of the transposed (x, y, z) are
+// that level's 3-bit digit, x the most significant, so the top 3d bits are the
+// index of the particle's depth-d cell on the d-level curve.
+__device__ __forceinline__ uint64_t hilbert_index21(uint32_t x, uint32_t y, uint32_t z) {
+  for (uint32_t bit = 1u << 20; bit > 1u; bit >>= 1) {
+    const uint32_t low = bit - 1u;
+    if (x & bit) x ^= low;
+    if (y & bit) {
+      x ^= low;
+    } else {
+      const uint32_t t = (x ^ y) & low;
+      x ^= t;
+      y ^= t;
+    }
+    if (z & bit) {
+      x ^= low;
+    } else {
+      const uint32_t t = (x ^ z) & low;
+      x ^= t;
+      z ^= t;
+    }
+  }
+  y ^= x;
+  z ^= y;
+  // bit j of the correction: parity of z's bits above j
+  uint32_t t = z >> 1;
+  t ^= t >> 1;
+  t ^= t >> 2;
+  t ^= t >> 4;
+  t ^= t >> 8;
+  t ^= t >> 16;
+  x ^= t;
+  y ^= t;
+  z ^= t;
+  return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
+// Key of a particle: Morton (interleaved coordinates) or Peano-Hilbert, each
+// below a leading 1.
+__device__ __forceinline__ uint64_t particle_key(float x, float y, float z, double lo0, double lo1,
+                                                 double lo2, double scale, bool hilbert) {
+  if (!hilbert) return morton_key(x, y, z, lo0, lo1, lo2, scale);
+  return (1ull << 63) | hilbert_index21(quantise(x, lo0, scale), quantise(y, lo1, scale),
+                                        quantise(z, lo2, scale));
 }
 
 // Minimum distinguished depth of two particle keys (Sec. 2.3.1): leading zeros

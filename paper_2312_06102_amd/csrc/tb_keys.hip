@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
     const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
     const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
     uint64_t *__restrict__ keys, float4 *__restrict__ packed, uint32_t *__restrict__ hist_part,
-    int passes, const uint32_t *__restrict__ coarse, int coarse_shift,
+    int passes, const uint32_t *__restrict__ coarse, int coarse_shift, int hilbert,
     int32_t *__restrict__ status_word) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
         scale = 2097152.0 / box[4 * b + 3];
       }
       bad |= valid && !(isfinite(x[r]) && isfinite(y[r]) && isfinite(z[r]));
-      const uint64_t key = morton_key(x[r], y[r], z[r], lo0, lo1, lo2, scale);
+      const uint64_t key = particle_key(x[r], y[r], z[r], lo0, lo1, lo2, scale, hilbert != 0);
       if (valid) {
         keys[i] = key;
         // (x, y, z, m) in one 16-byte record: the reorder step gathers one line each
@@ -473,7 +473,8 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const f
 #define TB_KEYGEN(B)                                                                          \
   k_keygen<B><<<blocks, kKeygenThreads, lds, s>>>(pos, mass, p.n, w.set_off, p.nsets, w.box, \
                                                   w.keys0, w.packed, w.hist_part, passes,    \
-                                                  w.coarse, p.coarse_shift, out.status)
+                                                  w.coarse, p.coarse_shift,                 \
+                                                  (p.flags & TB_HILBERT) ? 1 : 0, out.status)
   switch (p.sort.bits) {
     case 8: TB_KEYGEN(8); break;
     case 9: TB_KEYGEN(9); break;

@@ -30,6 +30,52 @@ __device__ __forceinline__ uint32_t compact3(uint64_t v) {
   return (uint32_t)v;
 }
 
+// Cell coordinates (i, j, k) at depth d of the cell whose key is `ckey` (its
+// leading 1 at bit 3d).  Morton keys interleave them directly; a Peano-Hilbert
+// key is decoded with the inverse of the encoding of tb_internal.h: the Gray
+// code undone, then the levels' inversions and swaps undone bottom-up.
+__device__ __forceinline__ void cell_coords(uint64_t ckey, int d, bool hilbert, uint32_t c[3]) {
+  const uint64_t idx = ckey & ((1ull << (3 * d)) - 1ull);
+  uint32_t x = compact3(idx >> 2), y = compact3(idx >> 1), z = compact3(idx);
+  if (hilbert && d > 0) {
+    const uint32_t t = z >> 1;
+    z ^= y;
+    y ^= x;
+    x ^= t;
+    const uint32_t top = 1u << d;
+    for (uint32_t bit = 2u; bit != top; bit <<= 1) {
+      const uint32_t low = bit - 1u;
+      if (z & bit) {
+        x ^= low;
+      } else {
+        const uint32_t u = (x ^ z) & low;
+        x ^= u;
+        z ^= u;
+      }
+      if (y & bit) {
+        x ^= low;
+      } else {
+        const uint32_t u = (x ^ y) & low;
+        x ^= u;
+        y ^= u;
+      }
+      if (x & bit) x ^= low;
+    }
+  }
+  c[0] = x;
+  c[1] = y;
+  c[2] = z;
+}
+
+// Octant (x, y, z bits, x the most significant) of a depth-d cell inside its
+// parent; for Morton keys simply the key's last digit.
+__device__ __forceinline__ uint32_t child_octant(uint64_t ckey, int d, bool hilbert) {
+  if (!hilbert) return (uint32_t)(ckey & 7u);
+  uint32_t c[3];
+  cell_coords(ckey, d, true, c);
+  return ((c[0] & 1u) << 2) | ((c[1] & 1u) << 1) | (c[2] & 1u);
+}
+
 // ---- FP64 leaves: one pass of m, m r, m r r relative to the leaf centre ----
 struct LeafSums {
   double s0, s1[3], s2[6];
@@ -182,13 +228,15 @@ __device__ __forceinline__ void store_moments_mixed(float *com, float *quad, flo
 __device__ inline void parent_from_children_fp64(int64_t pc, int64_t c0, int nch, int dp,
                                                  double side, const uint64_t *cell_key,
                                                  int32_t *cell_count, int32_t *child_ptr,
-                                                 double *com, double *quad) {
+                                                 double *com, double *quad, bool hilbert) {
   const double q = ldexp(side, -(dp + 2));  // a quarter of the parent side
   double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
   int64_t cnt = 0;
+  uint32_t octs = 0;  // 3 bits per child
   for (int k = 0; k < nch; ++k) {
     const int64_t x = c0 + k;
-    const uint32_t o = (uint32_t)(cell_key[x] & 7u);
+    const uint32_t o = child_octant(cell_key[x], dp + 1, hilbert);
+    octs |= o << (3 * k);
     const double4 cm = *reinterpret_cast<const double4 *>(com + 4 * x);
     M += cm.w;
     S0 += cm.w * (cm.x + ((o & 4u) ? q : -q));
@@ -200,7 +248,7 @@ __device__ inline void parent_from_children_fp64(int64_t pc, int64_t c0, int nch
   double Q[6] = {0, 0, 0, 0, 0, 0};
   for (int k = 0; k < nch; ++k) {
     const int64_t x = c0 + k;
-    const uint32_t o = (uint32_t)(cell_key[x] & 7u);
+    const uint32_t o = (octs >> (3 * k)) & 7u;
     const double4 cm = *reinterpret_cast<const double4 *>(com + 4 * x);
     const double *qc = quad + 6 * x;
     const double d0 = cm.x + ((o & 4u) ? q : -q) - cx;
@@ -223,15 +271,18 @@ __device__ inline void parent_from_children_fp64(int64_t pc, int64_t c0, int nch
 __device__ inline void parent_from_children_mixed(int64_t pc, int64_t c0, int nch, int dp,
                                                   double side, const uint64_t *cell_key,
                                                   int32_t *cell_count, int32_t *child_ptr,
-                                                  float *com, float *quad, float *m_lo) {
+                                                  float *com, float *quad, float *m_lo,
+                                                  bool hilbert) {
   const float lc = ldexpf((float)side, -(dp + 1));  // child side
   const float lp = 2.0f * lc;                       // parent side
   const float inv_lc = 1.0f / lc, inv_lc2 = inv_lc * inv_lc;
   float M = 0.f, Mc = 0.f, S[3] = {0.f, 0.f, 0.f}, Sc[3] = {0.f, 0.f, 0.f};
   int64_t cnt = 0;
+  uint32_t octs = 0;  // 3 bits per child
   for (int k = 0; k < nch; ++k) {
     const int64_t x = c0 + k;
-    const uint32_t o = (uint32_t)(cell_key[x] & 7u);
+    const uint32_t o = child_octant(cell_key[x], dp + 1, hilbert);
+    octs |= o << (3 * k);
     const float4 cm = reinterpret_cast<const float4 *>(com)[x];
     const float up[3] = {0.5f * (cm.x * inv_lc) + ((o & 4u) ? 0.25f : -0.25f),
                          0.5f * (cm.y * inv_lc) + ((o & 2u) ? 0.25f : -0.25f),
@@ -247,7 +298,7 @@ __device__ inline void parent_from_children_mixed(int64_t pc, int64_t c0, int nc
   const float qs = 0.25f * inv_lc2;  // child units -> parent units
   for (int k = 0; k < nch; ++k) {
     const int64_t x = c0 + k;
-    const uint32_t o = (uint32_t)(cell_key[x] & 7u);
+    const uint32_t o = (octs >> (3 * k)) & 7u;
     const float4 cm = reinterpret_cast<const float4 *>(com)[x];
     const float *qc = quad + 6 * x;
     const float mc = cm.w;

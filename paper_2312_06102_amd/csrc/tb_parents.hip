@@ -23,6 +23,7 @@
 // (l the parent side; the octant bit picks the sign), so every quantity stays
 // in a cell-relative frame.
 #include "tb_internal.h"
+#include "tb_moments.h"
 
 namespace tb {
 
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
     int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr,
     double *__restrict__ com, double *__restrict__ quad, const int32_t *__restrict__ head_parent,
     const double *__restrict__ box, int32_t *__restrict__ status_word, int32_t nsets,
-    const int64_t *__restrict__ par_start) {
+    const int64_t *__restrict__ par_start, int hilbert) {
   __shared__ uint64_t s_key[kChunk + kHalo + 1];  // keys of [base - 1, base + kChunk + kHalo)
   __shared__ int32_t s_cnt[kChunk + kHalo];
   __shared__ int32_t s_hp[kChunk];  // parent slot of each staged first child
@@ -167,9 +168,11 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
       } else {
         double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0;
         int64_t cnt = 0;
+        uint32_t octs = 0;  // 3 bits per child
         for (int k = 0; k < nch; ++k) {
           const int x = t + k;
-          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const uint32_t o = child_octant(s_key[x + 1], depth + 1, hilbert != 0);
+          octs |= o << (3 * k);
           const double mc = s_com[4 * x + 3];
           M += mc;
           S0 += mc * (s_com[4 * x + 0] + ((o & 4u) ? q : -q));
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_fp64(
         double Q[6] = {0, 0, 0, 0, 0, 0};
         for (int k = 0; k < nch; ++k) {
           const int x = t + k;
-          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const uint32_t o = (octs >> (3 * k)) & 7u;
           const double mc = s_com[4 * x + 3];
           const double d0 = s_com[4 * x + 0] + ((o & 4u) ? q : -q) - cx;
           const double d1 = s_com[4 * x + 1] + ((o & 2u) ? q : -q) - cy;
@@ -228,7 +231,8 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
     int32_t *__restrict__ cell_count, int32_t *__restrict__ child_ptr,
     float *__restrict__ com, float *__restrict__ quad, float *__restrict__ m_lo,
     const int32_t *__restrict__ head_parent, const double *__restrict__ box,
-    int32_t *__restrict__ status_word, int32_t nsets, const int64_t *__restrict__ par_start) {
+    int32_t *__restrict__ status_word, int32_t nsets, const int64_t *__restrict__ par_start,
+    int hilbert) {
   __shared__ uint64_t s_key[kChunk + kHalo + 1];
   __shared__ int32_t s_cnt[kChunk + kHalo];
   __shared__ int32_t s_hp[kChunk];
@@ -320,9 +324,11 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
       } else {
         float M = 0.f, Mc = 0.f, S[3] = {0.f, 0.f, 0.f}, Sc[3] = {0.f, 0.f, 0.f};
         int64_t cnt = 0;
+        uint32_t octs = 0;  // 3 bits per child
         for (int k = 0; k < nch; ++k) {
           const int x = t + k;
-          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const uint32_t o = child_octant(s_key[x + 1], depth + 1, hilbert != 0);
+          octs |= o << (3 * k);
           const float4 cm = s_com[x];
           const float up[3] = {0.5f * (cm.x * inv_lc) + ((o & 4u) ? 0.25f : -0.25f),
                                0.5f * (cm.y * inv_lc) + ((o & 2u) ? 0.25f : -0.25f),
@@ -337,7 +343,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parents_mixed(
         float Q[6] = {0, 0, 0, 0, 0, 0}, Qc[6] = {0, 0, 0, 0, 0, 0};
         for (int k = 0; k < nch; ++k) {
           const int x = t + k;
-          const uint32_t o = (uint32_t)(s_key[x + 1] & 7u);
+          const uint32_t o = (octs >> (3 * k)) & 7u;
           const float4 cm = s_com[x];
           const float mc = cm.w;
           const float d0 = 0.5f * (cm.x * inv_lc) + ((o & 4u) ? 0.25f : -0.25f) - cx;
@@ -383,12 +389,12 @@ hipError_t launch_parents(const Plan &p, const Work &w, int depth, const tb_tree
     k_parents_mixed<<<(unsigned)blocks, kParentThreads, 0, s>>>(
         depth, w.lvl_off, out.cell_key, out.cell_count, out.child_ptr,
         static_cast<float *>(out.com), static_cast<float *>(out.quad), w.m_lo, w.head_parent,
-        w.box, out.status, p.nsets, w.par_start);
+        w.box, out.status, p.nsets, w.par_start, (p.flags & TB_HILBERT) ? 1 : 0);
   else
     k_parents_fp64<<<(unsigned)blocks, kParentThreads, 0, s>>>(
         depth, w.lvl_off, out.cell_key, out.cell_count, out.child_ptr,
         static_cast<double *>(out.com), static_cast<double *>(out.quad), w.head_parent, w.box,
-        out.status, p.nsets, w.par_start);
+        out.status, p.nsets, w.par_start, (p.flags & TB_HILBERT) ? 1 : 0);
   return hipGetLastError();
 }
 

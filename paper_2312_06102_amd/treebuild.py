@@ -46,6 +46,14 @@ TB_MIXED = 1
 TB_SORT_LOOKBACK = 1 << 17  # keep the decoupled look-back in every radix pass
 TB_SUBTREES = 1 << 18  # build the cells subtree by subtree (Sec. 2.3.3, eq. 2)
 TB_SORT_COUNTED = 1 << 19  # count the tiles' digits in every radix pass
+TB_HILBERT = 1 << 20  # Peano-Hilbert keys (footnote of Sec. 2.2)
+CURVES = ("morton", "hilbert")
+
+
+def _curve_flag(curve: str) -> int:
+    if curve not in CURVES:
+        raise ValueError(f"curve must be one of {CURVES}")
+    return TB_HILBERT if curve == "hilbert" else 0
 TB_MAX_DEPTH = 21
 TB_MAX_NLEAF = 1024
 TB_MAX_SETS = 16383
@@ -395,13 +403,14 @@ class Builder(_Graphable):
 
     def __init__(self, n: int, n_leaf: int = 16, precision: str = "fp64", sort_config: int = 0,
                  device="cuda", sorted_particles: bool = False, sorted_keys: bool = False,
-                 lookback: bool = False, subtrees: bool = False, counted: bool = False):
+                 lookback: bool = False, subtrees: bool = False, counted: bool = False,
+                 curve: str = "morton"):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         self.n, self.n_leaf, self.precision = int(n), int(n_leaf), precision
         self.flags = ((TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
                       | (TB_SORT_LOOKBACK if lookback else 0) | (TB_SUBTREES if subtrees else 0)
-                      | (TB_SORT_COUNTED if counted else 0))
+                      | (TB_SORT_COUNTED if counted else 0) | _curve_flag(curve))
         self.ws_bytes = tb_workspace_bytes(self.n, self.n_leaf, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
@@ -457,7 +466,8 @@ class Builder(_Graphable):
         s = stream if stream is not None else torch.cuda.current_stream()
         rc = tb_gravity(self.out.pos_sorted.data_ptr(), self.out.mass_sorted.data_ptr(), self.n,
                         self._struct, c_max, theta, n_crit, eps,
-                        TB_GRAV_QUADRUPOLE if quadrupole else 0, acc.data_ptr(),
+                        (TB_GRAV_QUADRUPOLE if quadrupole else 0) | (self.flags & TB_HILBERT),
+                        acc.data_ptr(),
                         stats.data_ptr(), self._grav_ws.data_ptr(), self._grav_ws_bytes,
                         s.cuda_stream)
         if rc:
@@ -471,7 +481,7 @@ class Builder(_Graphable):
 def build(pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 16, box=None,
           precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
           sorted_keys: bool = False, lookback: bool = False, subtrees: bool = False,
-          counted: bool = False) -> dict:
+          counted: bool = False, curve: str = "morton") -> dict:
     """One-shot build; returns device tensors trimmed to n_cells.
 
     box: None (derive from data) or (lo[3], side) with side a power of two.
@@ -479,9 +489,10 @@ def build(pos: torch.Tensor, mass: torch.Tensor, n_leaf: int = 16, box=None,
     subtrees: build the cells block by block from subtree roots (TB_SUBTREES); the
     tree is the same.
     counted: count the tiles' digits in every radix pass (TB_SORT_COUNTED).
+    curve: "morton" or "hilbert" (TB_HILBERT: Peano-Hilbert keys).
     cell_key is returned as int64 holding the uint64 bit pattern."""
     b = Builder(pos.shape[0], n_leaf, precision, sort_config, pos.device, sorted_particles,
-                sorted_keys, lookback, subtrees, counted)
+                sorted_keys, lookback, subtrees, counted, curve)
     b.launch(pos, mass, box)
     return b.result()
 
@@ -494,13 +505,13 @@ class BatchBuilder(_Graphable):
     def __init__(self, n_total: int, nsets: int, n_leaf: int = 16, precision: str = "fp64",
                  sort_config: int = 0, device="cuda", sorted_particles: bool = False,
                  sorted_keys: bool = False, lookback: bool = False, subtrees: bool = False,
-                 counted: bool = False):
+                 counted: bool = False, curve: str = "morton"):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         self.n, self.nsets, self.n_leaf, self.precision = int(n_total), int(nsets), int(n_leaf), precision
         self.flags = ((TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
                       | (TB_SORT_LOOKBACK if lookback else 0) | (TB_SUBTREES if subtrees else 0)
-                      | (TB_SORT_COUNTED if counted else 0))
+                      | (TB_SORT_COUNTED if counted else 0) | _curve_flag(curve))
         self.ws_bytes = tb_workspace_bytes_batched(self.n, self.nsets, self.n_leaf, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
@@ -557,9 +568,10 @@ def build_batched(pos: torch.Tensor, mass: torch.Tensor, set_offsets: torch.Tens
                   n_leaf: int = 16, boxes: Optional[torch.Tensor] = None,
                   precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
                   sorted_keys: bool = False, lookback: bool = False,
-                  subtrees: bool = False, counted: bool = False) -> dict:
+                  subtrees: bool = False, counted: bool = False, curve: str = "morton") -> dict:
     """One-shot batched build; returns device tensors trimmed to n_cells."""
     b = BatchBuilder(pos.shape[0], set_offsets.shape[0] - 1, n_leaf, precision, sort_config,
-                     pos.device, sorted_particles, sorted_keys, lookback, subtrees, counted)
+                     pos.device, sorted_particles, sorted_keys, lookback, subtrees, counted,
+                     curve)
     b.launch(pos, mass, set_offsets, boxes)
     return b.result()

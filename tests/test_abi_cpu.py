@@ -70,7 +70,8 @@ def test_workspace_bytes_grows_with_n():
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED) > 0
     with pytest.raises(tb.TreeBuildArgError):
         tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED | tb.TB_SORT_LOOKBACK)
-    for bit in (16, 20, 31):
+    assert tb.tb_workspace_bytes(10000, 16, tb.TB_HILBERT) > 0
+    for bit in (16, 21, 31):
         with pytest.raises(tb.TreeBuildArgError):
             tb.tb_workspace_bytes(10, 16, flags=1 << bit)
 
@@ -80,6 +81,10 @@ def test_lookback_flag_matches_header():
     assert m and (1 << int(m.group(1))) == tb.TB_SORT_LOOKBACK
     m = re.search(r"#define TB_SUBTREES \(1u << (\d+)\)", open(HEADER).read())
     assert m and (1 << int(m.group(1))) == tb.TB_SUBTREES
+    m = re.search(r"#define TB_HILBERT \(1u << (\d+)\)", open(HEADER).read())
+    assert m and (1 << int(m.group(1))) == tb.TB_HILBERT
+    m = re.search(r"#define TB_SORT_COUNTED \(1u << (\d+)\)", open(HEADER).read())
+    assert m and (1 << int(m.group(1))) == tb.TB_SORT_COUNTED
 
 
 def test_sort_config_table():

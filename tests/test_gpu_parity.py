@@ -63,25 +63,30 @@ def moment_errors(g_com, g_quad, o_com, o_quad, level, side=1.0, extent=None):
     return e_m.max(initial=0), e_c.max(initial=0), e_q.max(initial=0)
 
 
-def cell_extents(pos, o, lo=(0.0, 0.0, 0.0), side=1.0):
+def cell_extents(pos, o, lo=(0.0, 0.0, 0.0), side=1.0, curve="morton"):
     """Side of the smallest cube about each cell centre that holds its particles."""
     ext = np.zeros(o["n_cells"])
     u = pos.astype(np.float64) - np.asarray(lo, np.float64)
     for c in range(o["n_cells"]):
         f, k = int(o["cell_first"][c]), int(o["cell_count"][c])
-        off = np.array([float(v) for v in tc.cell_centre_offset(int(o["cell_key"][c]),
-                                                                int(o["cell_level"][c]), side)])
+        key, d = int(o["cell_key"][c]), int(o["cell_level"][c])
+        if curve == "hilbert":
+            ijk = oracle.hilbert_decode(np.array([key & ((1 << (3 * d)) - 1)], np.uint64), d)[0]
+            off = (ijk.astype(np.float64) + 0.5) * side * 2.0 ** -d
+        else:
+            off = np.array([float(v) for v in tc.cell_centre_offset(key, d, side)])
         ext[c] = 2.0 * np.abs(u[o["perm"][f:f + k]] - off).max()
     return ext
 
 
 def full_parity(pos, mass, n_leaf, lo=(0.0, 0.0, 0.0), side=1.0, box="given", extent=False, **kw):
-    o = oracle.build(pos, mass, n_leaf, lo=lo, side=side)
+    curve = kw.get("curve", "morton")
+    o = oracle.build(pos, mass, n_leaf, lo=lo, side=side, curve=curve)
     g = gpu_build(pos, mass, n_leaf, box=((lo, side) if box == "given" else None), **kw)
     compare_structure(g, o)
-    _, keys = oracle.keys(pos, lo, side)
+    _, keys = oracle.keys(pos, lo, side, curve=curve)
     assert np.array_equal(g["key_sorted"], keys[o["perm"]])
-    ext = cell_extents(pos, o, lo, side) if extent else None
+    ext = cell_extents(pos, o, lo, side, curve) if extent else None
     em, ec, eq = moment_errors(g["com"], g["quad"], o["com"], o["quad"], o["cell_level"], side, ext)
     assert em <= FP64_TOL and ec <= FP64_TOL and eq <= FP64_TOL, (em, ec, eq)
     return g, o
