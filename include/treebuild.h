@@ -310,6 +310,34 @@ int tb_gravity(const float *pos_sorted, const float *mass_sorted, int64_t n, con
                double *acc, int64_t *stats, void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------- */
+/* Particle updates of an N-body run around the build (Sec. 3: a leapfrog over
+ * constant timesteps with the tree rebuilt every step; Sec. 2.3 and Sec. 4:
+ * reordering the particles in memory is optional and may be done only every
+ * few steps).
+ *
+ * tb_kick_drift: for every sorted position s, with i = perm[s] (i = s when perm
+ * is NULL), in this order
+ *     vel[i] += acc[s] * dt_kick,   pos[i] += vel[i] * dt_drift,
+ * each component updated in FP64 (one rounding per operation) and stored in
+ * FP32.  perm [N] int32 DEVICE (a build's perm, or NULL); acc [N][4] double
+ * DEVICE (tb_gravity's output; the 4th column is ignored); pos, vel [N][3]
+ * float DEVICE, updated in place; status int32 DEVICE or NULL: an index out of
+ * [0, N) is skipped and sets TB_STATUS_INTERNAL.  A kick-drift-kick leapfrog
+ * is kick_drift(dt/2, dt) on the first step, kick_drift(dt, dt) after, and a
+ * closing kick_drift(dt/2, 0).
+ *
+ * tb_permute: dst[s][k] = src[perm[s]][k] for rows of `width` 4-byte words
+ * (1 <= width <= 64): reorders particle arrays into the key order of the build
+ * that produced perm.  src and dst must not overlap.  Same status behaviour.
+ *
+ * Both are asynchronous on `stream`.  Errors (synchronous): TB_ERR_ARG (N out
+ * of range, null pointers, non-finite steps, bad width), TB_ERR_HIP. */
+int tb_kick_drift(const int32_t *perm, const double *acc, int64_t n, double dt_kick,
+                  double dt_drift, float *pos, float *vel, int32_t *status, void *stream);
+int tb_permute(const int32_t *perm, int64_t n, const void *src, int32_t width, void *dst,
+               int32_t *status, void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Kernel timing.  When enabled, every kernel launch of a build is bracketed by
  * HIP events recorded on the build's stream; the per-kernel durations are
  * summed when tb_trace_read() is called (which synchronises on the events).

@@ -478,3 +478,27 @@ int tb_sort_configs(int32_t *desc, int cap, int *count) {
 const char *tb_version(void) { return "treebuild 0.2 gfx950"; }
 
 }  // extern "C"
+
+extern "C" int tb_kick_drift(const int32_t *perm, const double *acc, int64_t n, double dt_kick,
+                             double dt_drift, float *pos, float *vel, int32_t *status,
+                             void *stream) {
+  if (n < 0 || n > TB_MAX_N || !std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+    return TB_ERR_ARG;
+  if (n == 0) return TB_OK;
+  if (!acc || !pos || !vel) return TB_ERR_ARG;
+  return tb::launch_kick_drift(perm, acc, n, dt_kick, dt_drift, pos, vel, status,
+                               static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TB_OK
+             : TB_ERR_HIP;
+}
+
+extern "C" int tb_permute(const int32_t *perm, int64_t n, const void *src, int32_t width,
+                          void *dst, int32_t *status, void *stream) {
+  if (n < 0 || n > TB_MAX_N || width < 1 || width > 64) return TB_ERR_ARG;
+  if (n == 0) return TB_OK;
+  if (!perm || !src || !dst || src == dst) return TB_ERR_ARG;
+  return tb::launch_permute(perm, n, src, width, dst, status, static_cast<hipStream_t>(stream)) ==
+                 hipSuccess
+             ? TB_OK
+             : TB_ERR_HIP;
+}

@@ -211,6 +211,12 @@ struct GravIn {
   void *workspace;          // int32 [c_max] groups + u32 counter
 };
 hipError_t launch_gravity(const GravIn &in, hipStream_t s);
+// tb_sim.hip
+hipError_t launch_kick_drift(const int32_t *perm, const double *acc, int64_t n, double dt_kick,
+                             double dt_drift, float *pos, float *vel, int32_t *status,
+                             hipStream_t s);
+hipError_t launch_permute(const int32_t *perm, int64_t n, const void *src, int32_t width,
+                          void *dst, int32_t *status, hipStream_t s);
 size_t gravity_workspace_bytes(int64_t c_max);
 
 // The sorted keys, recomputed from the sorted particles by the reorder pass (the

@@ -16,6 +16,15 @@ distributions:
 * ``lognormal_masses`` -- m = exp(Z), Z ~ N(0, 1), normalised to sum 1.
 * ``batched_sizes`` / ``batched_plummer`` -- many independent Plummer sets with
                   log-uniform sizes.
+* ``exponential_disk`` -- thin disk, surface density ~ exp(-R/h) truncated at
+                  R = 10 h, vertical density ~ sech^2(z/z0) with z0 = 0.1 h,
+                  normalised into the unit cube.
+* ``plummer_sim`` / ``disk_sim`` -- the same two distributions with velocities
+                  in equilibrium (G = 1, total mass 1, the unit-cube frame), for
+                  multi-step runs: Plummer speeds by the rejection method of
+                  Aarseth, Henon & Wielen (1974); disk particles on circular
+                  orbits (Freeman's exponential-disk rotation curve) with a 10 %
+                  velocity dispersion.
 
 Every generator draws in FP64 with numpy's PCG64 and casts to FP32 last.
 """
@@ -51,11 +60,12 @@ def _isotropic(rng, n):
     return v / norm[:, None]
 
 
-def _to_unit_cube(x: np.ndarray) -> np.ndarray:
+def _unit_cube_map(x: np.ndarray):
     """Affine map of a point cloud into [0,1)^3: centre of the bounding box to 1/2,
-    largest extent (times 1 + 2^-20) to 1; cast to FP32 and clamp below 1."""
+    largest extent (times 1 + 2^-20) to 1; cast to FP32 and clamp below 1.
+    Returns (points, scale S): lengths shrink by 1/S."""
     if x.shape[0] == 0:
-        return x.astype(np.float32)
+        return x.astype(np.float32), 1.0
     mn = x.min(axis=0)
     mx = x.max(axis=0)
     centre = 0.5 * (mn + mx)
@@ -65,7 +75,11 @@ def _to_unit_cube(x: np.ndarray) -> np.ndarray:
     y = 0.5 + (x - centre) / s
     y = y.astype(np.float32)
     np.clip(y, np.float32(0.0), F32_BELOW_ONE, out=y)
-    return y
+    return y, s
+
+
+def _to_unit_cube(x: np.ndarray) -> np.ndarray:
+    return _unit_cube_map(x)[0]
 
 
 def plummer_radii(rng, n: int, rmax: float = 50.0) -> np.ndarray:
@@ -85,6 +99,88 @@ def plummer(n: int, seed: int = 2, masses: str = "equal"):
     pos = _to_unit_cube(x)
     mass = equal_masses(n) if masses == "equal" else lognormal_masses(n, seed + 1000)
     return pos, mass
+
+
+def _plummer_speeds(rng, r: np.ndarray) -> np.ndarray:
+    """Speeds of a Plummer sphere (G = M = a = 1) at radii r: v = q v_esc with
+    v_esc = sqrt(2) (1 + r^2)^-1/4 and q drawn from g(q) ~ q^2 (1 - q^2)^7/2 by
+    rejection (Aarseth, Henon & Wielen 1974)."""
+    n = r.shape[0]
+    q = np.empty(n)
+    todo = np.arange(n)
+    while todo.size:
+        x1 = rng.random(todo.size)
+        x2 = rng.random(todo.size)
+        ok = 0.1 * x2 < x1 * x1 * (1.0 - x1 * x1) ** 3.5
+        q[todo[ok]] = x1[ok]
+        todo = todo[~ok]
+    return q * np.sqrt(2.0) * (1.0 + r * r) ** -0.25
+
+
+def _scaled_velocities(v: np.ndarray, s: float) -> np.ndarray:
+    """Velocities in the unit-cube frame: with G and the total mass fixed,
+    shrinking lengths by 1/S speeds orbits up by sqrt(S)."""
+    return (v * math.sqrt(s)).astype(np.float32)
+
+
+def plummer_sim(n: int, seed: int = 12):
+    """Plummer sphere in equilibrium: (pos, vel, mass) in the unit-cube frame,
+    G = 1, total mass 1 (masses 1/N)."""
+    rng = _rng(seed)
+    r = plummer_radii(rng, n)
+    x = r[:, None] * _isotropic(rng, n)
+    v = _plummer_speeds(rng, r)[:, None] * _isotropic(rng, n)
+    pos, s = _unit_cube_map(x)
+    return pos, _scaled_velocities(v, s), equal_masses(n)
+
+
+def _disk_radii(rng, n: int, rmax: float = 10.0) -> np.ndarray:
+    """Radii of an exponential disk of scale length 1 truncated at rmax: the
+    enclosed mass fraction 1 - (1 + R) e^-R inverted by bisection."""
+    def frac(R):
+        return 1.0 - (1.0 + R) * np.exp(-R)
+    u = rng.random(n) * frac(rmax)
+    lo = np.zeros(n)
+    hi = np.full(n, rmax)
+    for _ in range(64):
+        mid = 0.5 * (lo + hi)
+        below = frac(mid) < u
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+def _disk_positions(rng, n: int, z0: float = 0.1, rmax: float = 10.0):
+    R = _disk_radii(rng, n, rmax)
+    phi = rng.random(n) * (2.0 * math.pi)
+    z = z0 * np.arctanh(np.clip(2.0 * rng.random(n) - 1.0, -1.0 + 1e-15, 1.0 - 1e-15))
+    x = np.stack([R * np.cos(phi), R * np.sin(phi), z], axis=1)
+    return x, R, phi
+
+
+def exponential_disk(n: int, seed: int = 6, z0: float = 0.1):
+    """Thin exponential disk (scale length 1, sech^2 scale height z0, truncated
+    at R = 10) normalised into the unit cube; equal masses."""
+    rng = _rng(seed)
+    x, _, _ = _disk_positions(rng, n, z0)
+    return _to_unit_cube(x), equal_masses(n)
+
+
+def disk_sim(n: int, seed: int = 13, z0: float = 0.1, sigma: float = 0.1):
+    """Exponential disk with velocities: (pos, vel, mass) in the unit-cube frame,
+    G = 1, disk mass 1.  Circular speed of the (untruncated) razor-thin disk,
+    v_c^2 = 2 y^2 [I0(y) K0(y) - I1(y) K1(y)] with y = R/2 (Freeman 1970), plus
+    isotropic Gaussian motions of sigma * v_c per axis."""
+    from scipy import special
+    rng = _rng(seed)
+    x, R, phi = _disk_positions(rng, n, z0)
+    y = np.maximum(0.5 * R, 1e-8)
+    vc = np.sqrt(np.maximum(2.0 * y * y * (special.i0(y) * special.k0(y)
+                                           - special.i1(y) * special.k1(y)), 0.0))
+    v = np.stack([-vc * np.sin(phi), vc * np.cos(phi), np.zeros(n)], axis=1)
+    v += sigma * vc[:, None] * rng.standard_normal((n, 3))
+    pos, s = _unit_cube_map(x)
+    return pos, _scaled_velocities(v, s), equal_masses(n)
 
 
 def _halo_counts(rng, n_halo_particles: int, n_halos: int, mmin=1e2, mmax=1e6, slope=1.9):
@@ -193,6 +289,7 @@ def workload(name: str, n: int | None = None):
     plummer16m   : N = 2^24 Plummer, n_leaf 16
     clustered64m : N = 2^26 clustered, n_leaf 8
     mixed16m     : N = 2^24 clustered with log-normal masses, n_leaf 8
+    disk16m      : N = 2^24 exponential disk, n_leaf 16
     """
     if name == "uniform64k":
         p, m = uniform(n or 65536, seed=1)
@@ -206,4 +303,7 @@ def workload(name: str, n: int | None = None):
     if name == "mixed16m":
         p, m = clustered(n or (1 << 24), seed=5, masses="lognormal")
         return p, m, 8
+    if name == "disk16m":
+        p, m = exponential_disk(n or (1 << 24), seed=6)
+        return p, m, 16
     raise KeyError(name)

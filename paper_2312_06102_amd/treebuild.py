@@ -62,7 +62,8 @@ TB_GRAV_QUADRUPOLE = 1
 
 EXPORTS = ("tb_max_cells", "tb_workspace_bytes", "tb_workspace_bytes_batched", "tb_build",
            "tb_build_sync", "tb_build_noalloc", "tb_gravity_workspace_bytes", "tb_gravity",
-           "tb_build_batched", "tb_build_batched_sync", "tb_trace_enable",
+           "tb_build_batched", "tb_build_batched_sync", "tb_kick_drift", "tb_permute",
+           "tb_trace_enable",
            "tb_trace_read", "tb_sort_configs", "tb_version")
 
 _ERRNAMES = {TB_ERR_ARG: "TB_ERR_ARG", TB_ERR_BOX: "TB_ERR_BOX", TB_ERR_WORKSPACE: "TB_ERR_WORKSPACE",
@@ -136,6 +137,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             ctypes.POINTER(TbTree), P, P]
     lib.tb_build_batched.argtypes = bsig
     lib.tb_build_batched_sync.argtypes = bsig
+    lib.tb_kick_drift.argtypes = [P, P, i64, ctypes.c_double, ctypes.c_double, P, P, P, P]
+    lib.tb_permute.argtypes = [P, i64, P, i32, P, P, P]
     lib.tb_trace_enable.argtypes = [ctypes.c_int]
     lib.tb_trace_read.argtypes = [ctypes.POINTER(TbTraceEntry), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.tb_sort_configs.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
@@ -210,6 +213,60 @@ def tb_gravity(pos_ptr: int, mass_ptr: int, n: int, tree: TbTree, c_max: int, th
                                      float(eps), int(flags), ctypes.c_void_p(acc_ptr),
                                      ctypes.c_void_p(stats_ptr), ctypes.c_void_p(ws_ptr),
                                      int(ws_bytes), ctypes.c_void_p(stream))
+
+
+def tb_kick_drift(perm_ptr: Optional[int], acc_ptr: int, n: int, dt_kick: float, dt_drift: float,
+                  pos_ptr: int, vel_ptr: int, status_ptr: Optional[int], stream: int) -> int:
+    """Raw call of the leapfrog update: device pointers as ints; returns the C code."""
+    return load_library().tb_kick_drift(ctypes.c_void_p(perm_ptr), ctypes.c_void_p(acc_ptr),
+                                        int(n), float(dt_kick), float(dt_drift),
+                                        ctypes.c_void_p(pos_ptr), ctypes.c_void_p(vel_ptr),
+                                        ctypes.c_void_p(status_ptr), ctypes.c_void_p(stream))
+
+
+def tb_permute(perm_ptr: int, n: int, src_ptr: int, width: int, dst_ptr: int,
+               status_ptr: Optional[int], stream: int) -> int:
+    """Raw call of the row gather dst[s] = src[perm[s]]; returns the C code."""
+    return load_library().tb_permute(ctypes.c_void_p(perm_ptr), int(n), ctypes.c_void_p(src_ptr),
+                                     int(width), ctypes.c_void_p(dst_ptr),
+                                     ctypes.c_void_p(status_ptr), ctypes.c_void_p(stream))
+
+
+def kick_drift(perm: Optional[torch.Tensor], acc: torch.Tensor, dt_kick: float, dt_drift: float,
+               pos: torch.Tensor, vel: torch.Tensor, status: Optional[torch.Tensor] = None,
+               stream=None) -> None:
+    """vel[perm[s]] += acc[s] dt_kick; pos[perm[s]] += vel[perm[s]] dt_drift (in place)."""
+    n = pos.shape[0]
+    _check_device_tensor(pos, "pos", torch.float32, (3,))
+    _check_device_tensor(vel, "vel", torch.float32, (3,))
+    _check_device_tensor(acc, "acc", torch.float64, (4,))
+    if vel.shape[0] != n or acc.shape[0] < n or (perm is not None and perm.shape[0] < n):
+        raise ValueError("pos, vel, acc and perm must describe the same particles")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = tb_kick_drift(perm.data_ptr() if perm is not None else None, acc.data_ptr(), n, dt_kick,
+                       dt_drift, pos.data_ptr(), vel.data_ptr(),
+                       status.data_ptr() if status is not None else None, s.cuda_stream)
+    if rc:
+        _raise(rc, "tb_kick_drift")
+
+
+def permute(perm: torch.Tensor, src: torch.Tensor, dst: torch.Tensor,
+            status: Optional[torch.Tensor] = None, stream=None) -> None:
+    """dst[s] = src[perm[s]] for rows of 4-byte elements (float32 or int32)."""
+    n = perm.shape[0]
+    if src.dtype not in (torch.float32, torch.int32) or dst.dtype != src.dtype:
+        raise ValueError("permute moves float32 or int32 rows")
+    if not (src.is_cuda and dst.is_cuda and perm.is_cuda and src.is_contiguous()
+            and dst.is_contiguous()):
+        raise ValueError("permute needs contiguous device tensors")
+    width = 1 if src.dim() == 1 else int(src[0].numel())
+    if src.shape != dst.shape or src.shape[0] != n:
+        raise ValueError("src and dst must be [N] or [N][width] with N = len(perm)")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = tb_permute(perm.data_ptr(), n, src.data_ptr(), width, dst.data_ptr(),
+                    status.data_ptr() if status is not None else None, s.cuda_stream)
+    if rc:
+        _raise(rc, "tb_permute")
 
 
 def tb_workspace_bytes_batched(n_total: int, nsets: int, n_leaf: int, flags: int = TB_FP64) -> int:

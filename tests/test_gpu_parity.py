@@ -126,6 +126,13 @@ def test_clustered_200k():
     full_parity(pos, mass, 8)
 
 
+def test_exponential_disk():
+    """The paper's second distribution: a thin disk (deep cells along z)."""
+    pos, mass = dg.exponential_disk(200000, seed=6)
+    full_parity(pos, mass, 16)
+    full_parity(pos, mass, 10, subtrees=True)
+
+
 def test_lognormal_masses():
     pos, mass = dg.clustered(100000, seed=5, n_halos=100, masses="lognormal")
     full_parity(pos, mass, 8)
