@@ -17,6 +17,13 @@ Workloads
   batched4096   4,096 Plummer sets, sizes log-uniform in [256, 262144], n_leaf 16:
                 one graph-captured batch per step, beside eager batches and 4,096
                 sequential single-set builds; the sort shape comes from the autotuner
+  disk16m       N = 2^24 thin exponential disk, n_leaf 16
+
+    python bench.py --sim plummer|disk [--sim-n N] [--steps K]
+
+runs leapfrog steps instead (build, reorder, walk, kick-drift per step; the
+paper's own methodology) and reports per-phase times with the particles
+reordered every step and every tenth step.
 """
 from __future__ import annotations
 
@@ -44,6 +51,8 @@ WORKLOADS = {
                     "n_leaf=8",
     "mixed16m": "N=2^24 clustered set (2000 NFW halos + 30% uniform) with log-normal masses, "
                 "n_leaf=8, mixed-precision moments vs FP64",
+    "disk16m": "N=2^24 exponential disk (scale length h, sech^2 height 0.1 h, R < 10 h) "
+               "normalised into the unit cube, equal masses, n_leaf=16",
     "batched4096": "4096 independent Plummer sets, sizes floor(exp(U(ln 256, ln 262144))), each in "
                    "its own unit cube, masses 1/n_b, n_leaf=16, one graph-captured batch",
 }
@@ -81,6 +90,9 @@ def parse():
                     help="particles of the workload the oracle builds for the CPU baseline "
                          "(default: all of a single set up to 2^24, the first 2^24 of a larger "
                          "one, whole sets up to 2^22 particles of a batch)")
+    ap.add_argument("--sim", choices=["plummer", "disk"], default=None,
+                    help="time leapfrog steps of an N-body run (build + walk per step) instead")
+    ap.add_argument("--sim-n", type=int, default=1 << 22, help="particles of the --sim run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 256 MiB (to scale HBM byte counters)")
     return ap.parse_args()
@@ -524,6 +536,44 @@ def cpu_baseline(args, data, np):
                         "moments combined from the children), same particles"}}
 
 
+def run_sim(args, dg, np):
+    """Leapfrog steps on a Plummer sphere or an exponential disk (Sec. 3: theta
+    0.75, n_leaf 10, n_crit 512), reordering every step and every tenth step."""
+    from paper_2312_06102_amd.simulate import Simulation
+    gen = dg.plummer_sim if args.sim == "plummer" else dg.disk_sim
+    pos, vel, mass = gen(args.sim_n)
+    dt = 1e-4 if args.sim == "plummer" else 3e-4
+    runs = {}
+    for k in (1, 10):
+        sim = Simulation(pos, vel, mass, dt, n_leaf=10, theta=0.75, n_crit=512, eps=5e-4,
+                         reorder_every=k)
+        sim.step(max(args.warmup, 1))
+        sim.synchronise()
+        sim._events.clear()
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        sim.synchronise()
+        wall = time.perf_counter() - t0
+        t = sim.timings()["mean_ms"]
+        inter = int(sim.interactions[-1].cpu()[1])
+        runs[f"reorder_every_{k}"] = {"ms_per_step": wall * 1e3 / args.steps, "phase_ms": t,
+                                      "interactions_last_step": inter}
+        print(f"[bench sim] k={k}: {wall * 1e3 / args.steps:.2f} ms/step {t}", file=sys.stderr,
+              flush=True)
+        del sim
+    r1, r10 = runs["reorder_every_1"], runs["reorder_every_10"]
+    build = lambda r: r["phase_ms"]["build"] + r["phase_ms"]["reorder"] * r["phase_ms"]["reorders"] / max(r["phase_ms"]["steps"], 1)
+    return {
+        "metric": "leapfrog N-body step with a tree rebuild every step: tree-build ms per step",
+        "value": build(r10), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+        "config": {"workload": f"{args.sim}_sim", "N": args.sim_n, "n_leaf": 10, "theta": 0.75,
+                   "n_crit": 512, "eps": 5e-4, "dt": dt, "quadrupole": True},
+        "build_ms_reorder_every_step": build(r1), "build_ms_reorder_every_10": build(r10),
+        "runs": runs,
+    }
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -540,6 +590,9 @@ def main():
     from paper_2312_06102_amd import datagen as dg
     from paper_2312_06102_amd import treebuild as tb
 
+    if args.sim:
+        print(json.dumps(run_sim(args, dg, np)))
+        return
     if args.workload == "batched4096":
         line, data = run_batched(args, tb, dg, torch, np)
     else:
