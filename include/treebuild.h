@@ -166,7 +166,11 @@ typedef struct {
  * or c_max == NULL. */
 int tb_max_cells(int64_t n, int32_t n_leaf, int64_t *c_max);
 
-/* Bytes of device workspace that tb_build() needs for these arguments.
+/* Bytes of device workspace that tb_build() needs for these arguments.  On the
+ * current device it also opts the cell kernels in to their full LDS size (a
+ * per-device kernel attribute, set once per process); a caller that captures
+ * builds into a HIP graph should size the workspace, or run one build, before
+ * the capture, so that no attribute call happens inside it.
  * Errors: as tb_max_cells(), plus TB_ERR_ARG for unknown flags. */
 int tb_workspace_bytes(int64_t n, int32_t n_leaf, uint32_t flags, size_t *bytes);
 

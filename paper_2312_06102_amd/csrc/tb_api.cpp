@@ -349,6 +349,10 @@ int tb_workspace_bytes_batched(int64_t n_total, int32_t nsets, int32_t n_leaf, u
     *bytes = 0;
     return TB_OK;
   }
+  // The cell kernels' LDS opt-in is a per-device attribute set once, here as
+  // well as on the first build, so that a caller who sizes the workspace before
+  // capturing a build into a graph makes no attribute call during the capture.
+  (void)tb::cell_lds_limit();
   // sized for data-derived boxes, so one workspace serves both kinds of call
   tb::Plan p;
   tb::make_plan(n_total, nsets, n_leaf, flags | tb::kAutoBoxFlag, sc, &p);
