@@ -95,6 +95,19 @@ def parse():
     ap.add_argument("--sim-n", type=int, default=1 << 22, help="particles of the --sim run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 256 MiB (to scale HBM byte counters)")
+    ap.add_argument("--gather-calibration", action="store_true",
+                    help="only run random-row gathers of 16-B and of 128-B rows (2^28 bytes each), "
+                         "to check the counter scale on gathers")
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="write profiles/build_<workload>_kernel_trace.md from a rocprofv3 "
+                         "--kernel-trace CSV (with --profile-command and --builds)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPYF", "COPYW"),
+                    help="write profiles/pmc_<workload>.json and its .md from rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE CSVs of the build and of --copy-calibration")
+    ap.add_argument("--gather-csv", default=None,
+                    help="with --summarize-pmc: FETCH_SIZE CSV of --gather-calibration")
+    ap.add_argument("--profile-command", default="", help="command line recorded in a summary")
+    ap.add_argument("--builds", type=int, default=0, help="builds in the profiled run")
     return ap.parse_args()
 
 
@@ -110,6 +123,203 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_per_launch": 1 << 28, "launches": 5}))
+
+
+def gather_calibration():
+    """Random-row gathers of 2^28 bytes, rows of 16 B (as the reorder's records)
+    and of 128 B (one cache line each), five of each: the first shows the line
+    amplification of 16-byte gathers, the second checks the counter scale on
+    random whole-line reads."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(7)
+    for width in (4, 32):
+        rows = (1 << 26) // width
+        src = torch.rand((rows, width), device="cuda:0")
+        idx = torch.randperm(rows, generator=g).to("cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            torch.index_select(src, 0, idx, out=dst)
+        torch.cuda.synchronize()
+        del src, dst, idx
+    print(json.dumps({"gather_calibration_bytes_per_launch": 1 << 28, "row_bytes": [16, 128],
+                      "launches": 5}))
+
+
+def _short_kernel(name: str) -> str:
+    """'void tb::k_onesweep<8, 11, 512, 2, 2, false>(...)' -> 'k_onesweep<8, 11, 512, 2, 2, false>'."""
+    n = name.split("(")[0]
+    if n.startswith("void "):
+        n = n[5:]
+    return n.replace("tb::", "").strip()
+
+
+STAGE_OF = [("k_onesweep", "sort_pass"), ("k_tile_count", "sort_pass"),
+            ("k_tile_scan", "sort_pass"), ("k_keygen", "keygen"), ("k_hist_reduce", "hist_reduce"),
+            ("k_reorder", "reorder"), ("k_cell_emit", "cell_emit"), ("k_cell_scan", "cell_scan"),
+            ("k_set_scan", "cell_scan"), ("k_parents", "parents"), ("k_init", "init"),
+            ("k_setup", "setup"), ("k_tile_map", "setup"), ("k_bbox", "bbox"),
+            ("k_blocks", "blocks"), ("k_block_build", "block_build"), ("k_upper", "upper")]
+
+
+def _stage(kernel: str):
+    if kernel.startswith("k_onesweep") and ", 0, 0, false>" in kernel:
+        return "set_pass"  # reads no key: a batch's set-id pass
+    for prefix, st in STAGE_OF:
+        if kernel.startswith(prefix):
+            return st
+    return None
+
+
+def _read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_trace(args):
+    """Markdown table of a rocprofv3 kernel trace: library kernels only."""
+    rows = _read_csv(args.summarize_trace)
+    agg = {}
+    for r in rows:
+        k = _short_kernel(r["Kernel_Name"])
+        if _stage(k) is None:
+            continue
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+        a = agg.setdefault(k, {"calls": 0, "tot": 0.0, "min": 1e30, "max": 0.0, "grid": 0,
+                               "wg": 0, "lds": 0, "vgpr": 0})
+        a["calls"] += 1
+        a["tot"] += d
+        a["min"] = min(a["min"], d)
+        a["max"] = max(a["max"], d)
+        wg = int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 0)
+        grid = int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+        a["wg"] = wg
+        a["grid"] = max(a["grid"], grid // max(wg, 1))
+        a["lds"] = int(r.get("Group_Segment_Size") or r.get("LDS_Block_Size") or 0)
+        a["vgpr"] = int(r.get("Arch_VGPR_Count") or r.get("VGPR_Count") or 0)
+    total = sum(a["tot"] for a in agg.values())
+    # one key-generation launch per build
+    b = args.builds or sum(a["calls"] for k, a in agg.items() if k.startswith("k_keygen")) or 1
+    args.builds = b
+    lines = [f"# Kernel trace: {args.workload} ({WORKLOADS.get(args.workload, '')})", "",
+             "Command (on the GPU host, repository root as `<repo>`):", "",
+             f"    {args.profile_command}", "",
+             f"{args.builds} builds traced. Durations in microseconds; library kernels only "
+             "(grid: the largest launch, in workgroups).", "",
+             "| kernel | stage | calls | per build | total us | avg us | min us | max us | share "
+             "| grid (WGs) | WG | static LDS B | VGPR |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["tot"]):
+        lines.append(f"| {k} | {_stage(k)} | {a['calls']} | {a['calls'] / b:g} | {a['tot']:.1f} | "
+                     f"{a['tot'] / a['calls']:.2f} | {a['min']:.2f} | {a['max']:.2f} | "
+                     f"{100 * a['tot'] / total:.1f}% | {a['grid']} | {a['wg']} | {a['lds']} | "
+                     f"{a['vgpr']} |")
+    st = {}
+    for k, a in agg.items():
+        st[_stage(k)] = st.get(_stage(k), 0.0) + a["tot"]
+    lines += ["", "Per build by stage (us): " + ", ".join(
+        f"{k} {v / b:.1f}" for k, v in sorted(st.items(), key=lambda kv: -kv[1])) + ".",
+              f"Sum of library kernel time per build: {total / b:.1f} us."]
+    if "sort_pass" in st:
+        n_pass = sum(a["calls"] for k, a in agg.items() if k.startswith("k_onesweep")
+                     and _stage(k) == "sort_pass") / b
+        lines.append(f"Sort passes (scatter + the count and scan of counted passes): "
+                     f"{st['sort_pass'] / b:.1f} us per build, {st['sort_pass'] / b / max(n_pass, 1):.1f} "
+                     f"us per pass over {n_pass:g} passes.")
+    out = os.path.join(PROFILES, f"build_{args.workload}_kernel_trace.md")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
+def summarize_pmc(args):
+    """Per-stage HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    scaled by the same counters on --copy-calibration (2^28 bytes read and written)."""
+    fetch, write, copyf, copyw = (_read_csv(p) for p in args.summarize_pmc)
+
+    def per_kernel(rows, counter):
+        out = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            k = _short_kernel(r["Kernel_Name"])
+            out.setdefault(k, []).append(float(r["Counter_Value"]) * 1024.0)
+        return out
+
+    def copy_bytes(rows, counter):
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in rows if r.get("Counter_Name") == counter
+                and "copy" in r["Kernel_Name"].lower()]
+        vals = sorted(vals)[len(vals) // 2:] if vals else []  # the large copies
+        return sum(vals) / max(len(vals), 1)
+
+    cal = 1 << 28
+    fs = cal / copy_bytes(copyf, "FETCH_SIZE")
+    ws = cal / copy_bytes(copyw, "WRITE_SIZE")
+    fk, wk = per_kernel(fetch, "FETCH_SIZE"), per_kernel(write, "WRITE_SIZE")
+    # one key-generation launch per build
+    b = args.builds or sum(len(v) for k, v in fk.items() if k.startswith("k_keygen")) or 1
+    stages = {}
+    for k in set(fk) | set(wk):
+        st = _stage(k)
+        if st is None:
+            continue
+        e = stages.setdefault(st, {"fetch": 0.0, "write": 0.0, "launches": 0, "names": set()})
+        e["fetch"] += sum(fk.get(k, [])) * fs
+        e["write"] += sum(wk.get(k, [])) * ws
+        if k.startswith("k_onesweep") or st not in ("sort_pass", "set_pass"):
+            e["launches"] += len(fk.get(k, []))
+        e["names"].add(k)
+    kernels = {}
+    for st, e in stages.items():
+        n = max(e["launches"], 1)
+        kernels[st] = {"fetch_bytes_per_launch": e["fetch"] / n, "write_bytes_per_launch":
+                       e["write"] / n, "bytes_per_launch": (e["fetch"] + e["write"]) / n,
+                       "launches_per_build": e["launches"] / b,
+                       "rocprof_names": sorted(e["names"])}
+    gather = None
+    if args.gather_csv:
+        # raw FETCH_SIZE per useful byte of the two gathers (16-B rows first, then 128-B rows)
+        g = [float(r["Counter_Value"]) * 1024.0 / (1 << 28) for r in _read_csv(args.gather_csv)
+             if r.get("Counter_Name") == "FETCH_SIZE" and "gather" in r["Kernel_Name"]]
+        if len(g) >= 2:
+            h = len(g) // 2
+            gather = {"what": "raw FETCH_SIZE per useful byte of random-row gathers of 2^28 "
+                              "bytes (bench.py --gather-calibration)",
+                      "rows_16B": sum(g[:h]) / h, "rows_128B": sum(g[h:]) / (len(g) - h)}
+    prof = {"workload": args.workload, "builds_profiled": b, "command": args.profile_command,
+            "gather_check": gather,
+            "calibration": {"what": "FETCH_SIZE / WRITE_SIZE (KiB) of a 2^28-byte device copy",
+                            "copy_bytes_per_launch": cal, "fetch_scale": fs, "write_scale": ws},
+            "source_sha256": source_hash(), "kernels": kernels,
+            "file": f"profiles/pmc_{args.workload}.json"}
+    out = os.path.join(PROFILES, f"pmc_{args.workload}.json")
+    with open(out, "w") as f:
+        json.dump(prof, f, indent=1, sort_keys=True)
+    lines = [f"# HBM traffic per stage: {args.workload}", "",
+             f"Counters: FETCH_SIZE x {fs:.4f} and WRITE_SIZE x {ws:.4f} (the same counters on a "
+             "plain copy of 2^28 bytes); means per launch over the profiled builds.", "",
+             "Command (repository root as `<repo>`):", "", f"    {args.profile_command}", "",
+             "| stage | launches / build | fetch MB / launch | write MB / launch | total MB / build |",
+             "|---|---|---|---|---|"]
+    for st, k in sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"] *
+                        kv[1]["launches_per_build"]):
+        lines.append(f"| {st} | {k['launches_per_build']:g} | {k['fetch_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{k['write_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{k['bytes_per_launch'] * k['launches_per_build'] / 1e6:.1f} |")
+    tot = sum(k["bytes_per_launch"] * k["launches_per_build"] for k in kernels.values())
+    lines += ["", f"Total per build: {tot / 1e9:.3f} GB."]
+    if gather:
+        lines += ["", "Scale check on gathers (`bench.py --gather-calibration`): a random gather of "
+                  f"128-byte rows reads {gather['rows_128B']:.2f} raw FETCH_SIZE bytes per byte, a "
+                  f"random gather of 16-byte rows {gather['rows_16B']:.2f}, against 0.50 for the "
+                  "streaming copy. Random whole-line reads count in full where streaming reads count "
+                  "half, so the copy's x2 overstates a gather: the reorder's fetch figure above is "
+                  "between its value and half of it (one 128-byte line per 16-byte record is "
+                  "about 2.1 GB per build at N = 2^24)."]
+    with open(os.path.join(PROFILES, f"build_{args.workload}_hbm_counters.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
 
 
 def source_hash() -> str:
@@ -578,6 +788,15 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.gather_calibration:
+        gather_calibration()
+        return
+    if args.summarize_trace:
+        summarize_trace(args)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
