@@ -163,8 +163,6 @@ STAGE_OF = [("k_onesweep", "sort_pass"), ("k_tile_count", "sort_pass"),
 
 
 def _stage(kernel: str):
-    if kernel.startswith("k_onesweep") and ", 0, 0, false>" in kernel:
-        return "set_pass"  # reads no key: a batch's set-id pass
     for prefix, st in STAGE_OF:
         if kernel.startswith(prefix):
             return st
@@ -267,7 +265,7 @@ def summarize_pmc(args):
         e = stages.setdefault(st, {"fetch": 0.0, "write": 0.0, "launches": 0, "names": set()})
         e["fetch"] += sum(fk.get(k, [])) * fs
         e["write"] += sum(wk.get(k, [])) * ws
-        if k.startswith("k_onesweep") or st not in ("sort_pass", "set_pass"):
+        if k.startswith("k_onesweep") or st != "sort_pass":
             e["launches"] += len(fk.get(k, []))
         e["names"].add(k)
     kernels = {}
@@ -344,8 +342,7 @@ def counter_traffic(workload: str) -> dict | None:
     return prof
 
 
-def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: int,
-                 precision: str) -> dict:
+def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: str) -> dict:
     """Bytes each traced stage must read + write for what it computes (its
     compulsory traffic), per build.
 
@@ -356,7 +353,6 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: i
                 and written by every pass
                 (passes over 32-bit keys also read their keys a second time to count
                 their tiles' digits: 4 bytes a key, not counted here)
-    set_pass    as a later key pass
     reorder     read perm 4 + gathered record 16; write the record in key order 16, its
                 key 8 and its (a_i, D_i) 2
     cell_emit   read sorted keys 8 + sorted records 16 + (a_i, D_i) 2 per particle; write
@@ -383,7 +379,6 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, set_passes: i
     return {
         "keygen": 40 * n,
         "sort_pass": sort,
-        "set_pass": 8 * n * set_passes,
         "reorder": 46 * n,
         "cell_emit": 26 * n + 25 * cells + (4 + mom) * leaves,
         "parents": (12 + mom) * max(cells - 1, 0) + (12 + mom) * inner,
@@ -527,7 +522,7 @@ def run_single(args, tb, dg, torch, np):
     leaves = int((res["child_ptr"][:, 0] < 0).sum().item())
     key_passes = (63 + tb.tb_sort_configs()[k][0] - 1) // tb.tb_sort_configs()[k][0]
     trace = traced_kernels(run, args.steps, tb)
-    alg = kernel_bytes(n, cells, leaves, key_passes, 0, precision)
+    alg = kernel_bytes(n, cells, leaves, key_passes, precision)
     total_method = method_bytes(n, cells, key_passes, precision)
     line = {
         "metric": METRIC, "value": n / sec, "unit": "particles/s", "n_gpus": 1,
@@ -617,12 +612,7 @@ def run_batched(args, tb, dg, torch, np):
     trace = traced_kernels(eager, args.steps, tb)
     bits = tb.tb_sort_configs()[k][0]
     key_passes = (63 + bits - 1) // bits
-    set_passes = 0
-    span = 1
-    while span < B:
-        span <<= bits
-        set_passes += 1
-    alg = kernel_bytes(n, cells, leaves, key_passes, set_passes, precision)
+    alg = kernel_bytes(n, cells, leaves, key_passes, precision)
     total_method = method_bytes(n, cells, key_passes, precision)
     line = {
         "metric": METRIC, "value": n / sec, "unit": "particles/s", "n_gpus": 1,

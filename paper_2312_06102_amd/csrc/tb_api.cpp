@@ -40,28 +40,32 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->nsets = nsets;
   p->sort = sc;
   p->key_passes = sc.passes();
-  p->set_passes = 0;  // digits of the set id: 0 for a single set
-  for (int64_t span = 1; span < nsets; span <<= sc.bits) ++p->set_passes;
-  p->coarse_shift = 0;
-  while (((n + (int64_t(1) << p->coarse_shift) - 1) >> p->coarse_shift) > kCoarse) ++p->coarse_shift;
-  p->sort_tiles = (n + sc.tile() - 1) / sc.tile();
+  // A batch sorts every set in place (tiles aligned to the sets, per-set digit
+  // bases), so no radix pass over the set id is needed.
+  p->seg = nsets > 1;
+  // each set starts a tile of its own
+  p->sort_tiles = (n + sc.tile() - 1) / sc.tile() + (p->seg ? nsets : 0);
   // On grids of up to kCountedMaxTiles tiles, passes over 32-bit keys count
   // their tiles' digits in a separate read (4 bytes a key) instead of chaining
   // the tiles through the look-back.  The extra read grows with N while the
   // look-back's cost does not: measured faster at N = 2^24 (2979 tiles), much
   // slower at 1.6e8 keys (28K tiles).
   // TB_SORT_COUNTED counts every key pass (a 64-bit pass re-reads 8 bytes a key).
+  // A batch keeps the look-back in every pass: its tiles' offsets restart at
+  // every set.
   p->counted = 0;
-  if (p->sort_tiles <= kCountedMaxTiles && !(flags & TB_SORT_LOOKBACK))
+  if (!p->seg && p->sort_tiles <= kCountedMaxTiles && !(flags & TB_SORT_LOOKBACK))
     for (int k = 0; k < p->key_passes; ++k)
       if (k * sc.bits >= 32 || (flags & TB_SORT_COUNTED)) p->counted |= 1u << k;
   // tiles never straddle two sets: at most one partial tile per set
   p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;
-  p->bbox_chunks = (flags & kAutoBoxFlag) ? (n + kBboxChunk - 1) / kBboxChunk + nsets : 1;
+  // chunks of at most kBboxChunk particles of one set: the auto box and, in a
+  // batch, the key kernel's per-set digit counts work chunk by chunk
+  p->bbox_chunks = ((flags & kAutoBoxFlag) || p->seg) ? (n + kBboxChunk - 1) / kBboxChunk + nsets : 1;
   // a set of n_b particles has at most n_b + 21 floor(n_b / (n_leaf + 1)) cells,
   // and the sum over the sets is bounded by the same expression of n
   p->c_max = max_cells(n, n_leaf);
-  const int P = p->key_passes + p->set_passes, R = sc.radix();
+  const int P = p->key_passes, R = sc.radix();
   const size_t B1 = (size_t)nsets + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -91,7 +95,9 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->set_cells = take(8 * B1);
   p->lvl_off = take(8 * (size_t)nsets * (kLevels + 1));
   p->par_start = take(8 * (size_t)kLevels * B1);
-  p->coarse = take(4 * (size_t)(kCoarse + 1));
+  p->seg_tile_start = take(p->seg ? 8 * B1 : 0);
+  p->seg_tile_set = take(p->seg ? 4 * (size_t)p->sort_tiles : 0);
+  p->seg_base = take(p->seg ? 4 * (size_t)nsets * p->key_passes * R : 0);
   p->packed = take(16 * (size_t)n);
   p->sorted = take(16 * (size_t)n);
   p->ad = take(2 * (size_t)n);
@@ -134,7 +140,9 @@ Work carve(const Plan &p, void *base) {
   w.set_cells = reinterpret_cast<int64_t *>(b + p.set_cells);
   w.lvl_off = reinterpret_cast<int64_t *>(b + p.lvl_off);
   w.par_start = reinterpret_cast<int64_t *>(b + p.par_start);
-  w.coarse = reinterpret_cast<uint32_t *>(b + p.coarse);
+  w.seg_tile_start = reinterpret_cast<int64_t *>(b + p.seg_tile_start);
+  w.seg_tile_set = reinterpret_cast<int32_t *>(b + p.seg_tile_set);
+  w.seg_base = reinterpret_cast<uint32_t *>(b + p.seg_base);
   w.packed = reinterpret_cast<float4 *>(b + p.packed);
   w.sorted = reinterpret_cast<float4 *>(b + p.sorted);
   w.ad = reinterpret_cast<uint16_t *>(b + p.ad);
@@ -262,9 +270,8 @@ static int build_impl(const float *pos, const float *mass, int64_t n, int32_t ns
   if (in.auto_box) run("bbox", [&] { return launch_bbox(p, w, pos, s); });
   run("keygen", [&] { return launch_keygen(p, w, pos, mass, *out, s); });
   run("hist_reduce", [&] { return launch_hist_reduce(p, w, s); });
-  for (int pass = 0; pass < p.key_passes + p.set_passes; ++pass)
-    run(pass < p.key_passes ? "sort_pass" : "set_pass",
-        [&] { return launch_sort_pass(p, w, pass, *out, s); });
+  for (int pass = 0; pass < p.key_passes; ++pass)
+    run("sort_pass", [&] { return launch_sort_pass(p, w, pass, *out, s); });
   run("reorder", [&] { return launch_reorder(p, w, *out, s); });
   run("cell_scan", [&] { return launch_cell_scan(p, w, *out, cell_offsets, s); });
   if (flags & TB_SUBTREES) {

@@ -38,14 +38,11 @@ constexpr uint32_t kXcds = 8;
 constexpr int kParentThreads = 256;
 constexpr int kParentChunk = kParentThreads;
 
-// Bounding-box chunks (auto box only).
+// Chunks of at most kBboxChunk particles of one set (the auto box; a batch's key kernel).
 constexpr int kBboxChunk = 65536;
 
-// Sets whose offsets fit the LDS table of the set-id radix passes.
+// Largest number of sets in one batch.
 constexpr int kMaxSetsLds = TB_MAX_SETS;
-// Coarse set table of the set-id passes: the set holding every 2^shift-th
-// position, at most kCoarse + 1 entries.
-constexpr int kCoarse = 4096;
 
 // counters[kUpperCounter + d]: number of cells above the blocks at depth d
 constexpr int kUpperCounter = 32;
@@ -74,9 +71,9 @@ struct Plan {
   int32_t nsets;    // B
   SortConfig sort;
   int key_passes;   // radix passes over the 63 key bits
-  int set_passes;   // radix passes over the set id (0 when B == 1)
-  int coarse_shift; // position >> coarse_shift indexes the coarse set table
   uint32_t counted; // bit k: key pass k takes its tile offsets from a count and a scan
+  bool seg;         // batch of several sets: every radix pass sorts each set in place
+                    // (tiles never straddle a set; each set has its own digit bases)
   int64_t sort_tiles;
   int64_t cell_tiles;   // upper bound of the cell tiles of all sets
   int64_t bbox_chunks;  // upper bound of the bounding-box chunks of all sets
@@ -85,7 +82,7 @@ struct Plan {
   // offsets
   size_t keys0, keys1;  // u64 [n] ping-pong key buffers
   size_t vals1;         // u32 [n] payload buffer (the other one is out->perm)
-  size_t hist;          // u32 [key_passes + set_passes][radix] global digit counts
+  size_t hist;          // u32 [key_passes][radix] global digit counts (single set)
   size_t hist_part;     // u32 [keygen blocks][key_passes][radix] per-workgroup counts
   size_t status0, status1;  // u64 [sort_tiles][radix] look-back words (alternating passes)
   size_t counters;      // u32 [64] dynamic tile counters
@@ -104,7 +101,10 @@ struct Plan {
   size_t set_cells;     // i64 [B + 1] first cell of each set; [B] = all cells
   size_t lvl_off;       // i64 [B][kLevels + 1] first cell of each depth of each set
   size_t par_start;     // i64 [kLevels][B + 1] parent-pass chunks per depth and set
-  size_t coarse;        // u32 [kCoarse + 1] set holding position k << coarse_shift
+  size_t seg_tile_start;  // i64 [B + 1] first radix tile of each set (seg)
+  size_t seg_tile_set;    // i32 [sort_tiles] set of each radix tile (seg)
+  size_t seg_base;        // u32 [B][key_passes][radix] digit counts of each set, then the
+                          // position where each digit's run of the set starts (seg)
   size_t packed;        // f32x4 [n] (x, y, z, m) records in original order
   size_t sorted;        // f32x4 [n] the same records in key order
   size_t ad;            // u16 [n] a_i | D_i << 8 of every particle in key order
@@ -140,7 +140,9 @@ struct Work {
   int64_t *set_cells;
   int64_t *lvl_off;
   int64_t *par_start;
-  uint32_t *coarse;
+  int64_t *seg_tile_start;
+  int32_t *seg_tile_set;
+  uint32_t *seg_base;
   float4 *packed;
   float4 *sorted;
   uint16_t *ad;
@@ -400,20 +402,6 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
     if (l >= o) v += t;
   }
   return v;
-}
-
-// Index b of the last entry of the sorted table tab[lo..hi] with tab[b] <= x,
-// given tab[lo] <= x.
-template <typename T>
-__device__ __forceinline__ int upper_index_in(const T *tab, int lo, int hi, int64_t x) {
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if ((int64_t)tab[mid] <= x)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
 }
 
 // Index b of the last entry of the sorted table tab[0..count) with tab[b] <= x

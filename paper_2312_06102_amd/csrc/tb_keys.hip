@@ -5,9 +5,8 @@
 //               copies the set offsets and caller-given root boxes into the
 //               workspace.
 // k_setup       checks the set offsets and caller-given boxes, then builds the
-//               per-set tables: first cell tile and bounding-box chunk of each
-//               set, the set of every tile and chunk, and the digit counts of
-//               the set-id radix passes.
+//               per-set tables: first cell tile, bounding-box chunk and radix
+//               tile of each set, and the set of every tile and chunk.
 // k_bbox_*      FP64 min/max over each set's positions -> root box with a
 //               power-of-two side (only when no box is given).
 // k_keygen      FP64 quantisation of each coordinate to 21 bits, bit interleave
@@ -15,6 +14,9 @@
 //               radix pass (so the sort never re-reads the keys to count them)
 //               and the packed (x, y, z, m) record of every particle.
 // k_hist_reduce column sums of those per-workgroup histograms.
+// k_keygen_sets the same for a batch, chunk by chunk of one set, with each set's
+//               digit counts added up per set;
+// k_set_base    each set's digit counts -> the start of every digit's run.
 #include "tb_internal.h"
 
 namespace tb {
@@ -115,13 +117,12 @@ __device__ __forceinline__ bool box_valid(const double *b) {
 
 __global__ __launch_bounds__(kSetupThreads) void k_setup(
     int64_t *__restrict__ set_off, int32_t nsets, int64_t n, int64_t *__restrict__ tile_start,
-    int64_t *__restrict__ chunk_start, uint32_t *__restrict__ set_hist, int set_passes, int bits,
-    int with_chunks, double *__restrict__ box, int check_boxes, uint32_t *__restrict__ coarse,
-    int coarse_shift, int32_t *__restrict__ status_word) {
-  __shared__ uint32_t s_w[2][kSetupThreads / 64];
-  __shared__ uint64_t s_carry[2];
+    int64_t *__restrict__ chunk_start, int64_t *__restrict__ sort_tile_start, int sort_tile_keys,
+    int with_chunks, double *__restrict__ box, int check_boxes,
+    int32_t *__restrict__ status_word) {
+  __shared__ uint32_t s_w[3][kSetupThreads / 64];
+  __shared__ uint64_t s_carry[3];
   __shared__ int s_bad;
-  const int R = 1 << bits;
   // The offsets must start at 0, end at n and never decrease.  Anything else is
   // reported and replaced by {0, ..., 0, n}, so no kernel indexes outside [0, n).
   if (threadIdx.x == 0) s_bad = (set_off[0] != 0 || set_off[nsets] != n) ? 1 : 0;
@@ -146,25 +147,8 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(
     }
     if (bad_box) atomicOr(status_word, TB_STATUS_BOX);
   }
-  __syncthreads();
-  // digit counts of the set-id passes: set b contributes its size to digit k of b
-  for (int i = threadIdx.x; i < set_passes * R; i += kSetupThreads) set_hist[i] = 0;
-  // coarse table of the set-id passes: the set holding position k << shift
-  if (set_passes > 0 && n > 0) {
-    const int64_t K = ((n - 1) >> coarse_shift) + 1;
-    for (int64_t k = threadIdx.x; k <= K; k += kSetupThreads) {
-      const int64_t pos = min(k << coarse_shift, n - 1);
-      coarse[k] = (uint32_t)upper_index(set_off, nsets + 1, pos);
-    }
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < nsets; b += kSetupThreads) {
-    const uint32_t nb = (uint32_t)(set_off[b + 1] - set_off[b]);
-    for (int k = 0; k < set_passes; ++k)
-      if (nb) atomicAdd(&set_hist[k * R + ((b >> (k * bits)) & (R - 1))], nb);
-  }
   // exclusive scans over sets of the tile and chunk counts, in rounds
-  if (threadIdx.x == 0) s_carry[0] = s_carry[1] = 0;
+  if (threadIdx.x == 0) s_carry[0] = s_carry[1] = s_carry[2] = 0;
   __syncthreads();
   const int wv = threadIdx.x / 64;
   for (int r0 = 0; r0 < nsets; r0 += kSetupThreads) {
@@ -173,71 +157,93 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(
     if (b < nsets) nb = set_off[b + 1] - set_off[b];
     const uint32_t nt = (uint32_t)((nb + kCellTile - 1) / kCellTile);
     const uint32_t nc = with_chunks ? (uint32_t)((nb + kBboxChunk - 1) / kBboxChunk) : 0u;
-    const uint32_t it = wave_inclusive_scan(nt), ic = wave_inclusive_scan(nc);
+    const uint32_t ns = sort_tile_start ? (uint32_t)((nb + sort_tile_keys - 1) / sort_tile_keys)
+                                        : 0u;
+    const uint32_t it = wave_inclusive_scan(nt), ic = wave_inclusive_scan(nc),
+                   is = wave_inclusive_scan(ns);
     if (lane_id() == 63) {
       s_w[0][wv] = it;
       s_w[1][wv] = ic;
+      s_w[2][wv] = is;
     }
     __syncthreads();
-    uint64_t ot = s_carry[0], oc = s_carry[1], tt = 0, tc = 0;
+    uint64_t ot = s_carry[0], oc = s_carry[1], os = s_carry[2], tt = 0, tc = 0, ts = 0;
     for (int q = 0; q < kSetupThreads / 64; ++q) {
       if (q < wv) {
         ot += s_w[0][q];
         oc += s_w[1][q];
+        os += s_w[2][q];
       }
       tt += s_w[0][q];
       tc += s_w[1][q];
+      ts += s_w[2][q];
     }
     ot += it - nt;
     oc += ic - nc;
+    os += is - ns;
     if (b < nsets) {
       tile_start[b] = (int64_t)ot;
       if (with_chunks) chunk_start[b] = (int64_t)oc;
+      if (sort_tile_start) sort_tile_start[b] = (int64_t)os;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       s_carry[0] += tt;
       s_carry[1] += tc;
+      s_carry[2] += ts;
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     tile_start[nsets] = (int64_t)s_carry[0];
     if (with_chunks) chunk_start[nsets] = (int64_t)s_carry[1];
+    if (sort_tile_start) sort_tile_start[nsets] = (int64_t)s_carry[2];
   }
 }
 
-// The set of every cell tile and bounding-box chunk: one thread per entry,
-// binary search over the first-tile / first-chunk tables.
-__global__ __launch_bounds__(256) void k_tile_map(const int64_t *__restrict__ tile_start,
-                                                  int32_t *__restrict__ tile_set,
-                                                  int64_t cell_tiles,
-                                                  const int64_t *__restrict__ chunk_start,
-                                                  int32_t *__restrict__ chunk_set,
-                                                  int64_t bbox_chunks, int with_chunks,
-                                                  int32_t nsets) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < cell_tiles) {
-    if (i < tile_start[nsets]) tile_set[i] = upper_index(tile_start, nsets + 1, i);
-  } else if (with_chunks) {
-    const int64_t c = i - cell_tiles;
-    if (c < bbox_chunks && c < chunk_start[nsets])
-      chunk_set[c] = upper_index(chunk_start, nsets + 1, c);
+// The set of every cell tile, bounding-box chunk and radix tile: one thread per
+// entry, binary search over the first-tile / first-chunk tables; the threads
+// past them clear a batch's per-set digit counts.
+__global__ __launch_bounds__(256) void k_tile_map(
+    const int64_t *__restrict__ tile_start, int32_t *__restrict__ tile_set, int64_t cell_tiles,
+    const int64_t *__restrict__ chunk_start, int32_t *__restrict__ chunk_set, int64_t bbox_chunks,
+    int with_chunks, const int64_t *__restrict__ sort_tile_start,
+    int32_t *__restrict__ sort_tile_set, int64_t sort_tiles, uint32_t *__restrict__ set_counts,
+    int64_t n_counts, int32_t nsets) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nc = with_chunks ? bbox_chunks : 0, ns = sort_tile_set ? sort_tiles : 0;
+  const int64_t total = cell_tiles + nc + ns + n_counts;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += stride) {
+    if (i < cell_tiles) {
+      if (i < tile_start[nsets]) tile_set[i] = upper_index(tile_start, nsets + 1, i);
+    } else if (i < cell_tiles + nc) {
+      const int64_t c = i - cell_tiles;
+      if (c < chunk_start[nsets]) chunk_set[c] = upper_index(chunk_start, nsets + 1, c);
+    } else if (i < cell_tiles + nc + ns) {
+      const int64_t t = i - cell_tiles - nc;
+      if (t < sort_tile_start[nsets]) sort_tile_set[t] = upper_index(sort_tile_start, nsets + 1, t);
+    } else {
+      set_counts[i - cell_tiles - nc - ns] = 0u;
+    }
   }
 }
 
 hipError_t launch_setup(const Plan &p, const Work &w, const BatchIn &in, int32_t *status,
                         hipStream_t s) {
   if (single_set(p, in)) return hipSuccess;  // written by k_init
-  const bool with_chunks = in.auto_box;
+  const bool with_chunks = in.auto_box || p.seg;
   k_setup<<<1, kSetupThreads, 0, s>>>(w.set_off, p.nsets, p.n, w.tile_start, w.chunk_start,
-                                      w.hist + (size_t)p.key_passes * p.sort.radix(),
-                                      p.set_passes, p.sort.bits, with_chunks ? 1 : 0, w.box,
-                                      in.dev_boxes ? 1 : 0, w.coarse, p.coarse_shift, status);
-  const int64_t entries = p.cell_tiles + (with_chunks ? p.bbox_chunks : 0);
-  k_tile_map<<<(unsigned)((entries + 255) / 256), 256, 0, s>>>(
+                                      p.seg ? w.seg_tile_start : nullptr, p.sort.tile(),
+                                      with_chunks ? 1 : 0, w.box, in.dev_boxes ? 1 : 0, status);
+  const int64_t n_counts = p.seg ? (int64_t)p.nsets * p.key_passes * p.sort.radix() : 0;
+  const int64_t entries = p.cell_tiles + (with_chunks ? p.bbox_chunks : 0) +
+                          (p.seg ? p.sort_tiles : 0) + n_counts;
+  int64_t grid = (entries + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  k_tile_map<<<(unsigned)grid, 256, 0, s>>>(
       w.tile_start, w.tile_set, p.cell_tiles, w.chunk_start, w.chunk_set, p.bbox_chunks,
-      with_chunks ? 1 : 0, p.nsets);
+      with_chunks ? 1 : 0, p.seg ? w.seg_tile_start : nullptr, p.seg ? w.seg_tile_set : nullptr,
+      p.sort_tiles, w.seg_base, n_counts, p.nsets);
   return hipGetLastError();
 }
 
@@ -344,32 +350,53 @@ hipError_t launch_bbox(const Plan &p, const Work &w, const float *pos, hipStream
 // Morton keys
 // ---------------------------------------------------------------------------
 
+// One particle's key and record, and its digit of every radix pass counted in
+// the LDS histograms h; a wave whose lanes all share a digit adds once (the upper
+// digits of clustered data are mostly uniform).
+template <int BITS>
+__device__ __forceinline__ void key_one(float x, float y, float z, float m, bool valid,
+                                        int64_t i, double lo0, double lo1, double lo2,
+                                        double scale, bool hilbert, uint64_t *__restrict__ keys,
+                                        float4 *__restrict__ packed, uint32_t *h, bool &bad) {
+  constexpr int R = 1 << BITS;
+  constexpr int MAXP = (63 + BITS - 1) / BITS;
+  bad |= valid && !(isfinite(x) && isfinite(y) && isfinite(z));
+  const uint64_t key = particle_key(x, y, z, lo0, lo1, lo2, scale, hilbert);
+  if (valid) {
+    keys[i] = key;
+    // (x, y, z, m) in one 16-byte record: the reorder step gathers one line each
+    packed[i] = make_float4(x, y, z, m);
+  }
+  const uint64_t active = __ballot(valid);
+  if (valid) {
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) {
+      const uint32_t d = (uint32_t)(key >> (p * BITS)) & (R - 1);
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+      if (__ballot(d == d0) == active) {
+        if (lane_id() == __ffsll((long long)active) - 1)
+          atomicAdd(&h[p * R + d0], (uint32_t)__popcll(active));
+      } else {
+        atomicAdd(&h[p * R + d], 1u);
+      }
+    }
+  }
+}
+
+// A single set: a grid-stride loop, one histogram per workgroup.
 template <int BITS>
 __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
     const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
-    const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
-    uint64_t *__restrict__ keys, float4 *__restrict__ packed, uint32_t *__restrict__ hist_part,
-    int passes, const uint32_t *__restrict__ coarse, int coarse_shift, int hilbert,
-    int32_t *__restrict__ status_word) {
+    const double *__restrict__ box, uint64_t *__restrict__ keys, float4 *__restrict__ packed,
+    uint32_t *__restrict__ hist_part, int passes, int hilbert, int32_t *__restrict__ status_word) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
   __shared__ uint32_t h[MAXP * R];
-  // [nsets + 1] set offsets (positions < 2^31), then (batches) the coarse set
-  // table: entry k is the set holding position k << coarse_shift
-  extern __shared__ uint32_t s_off[];
-  uint32_t *s_coarse = s_off + nsets + 1;
   for (int i = threadIdx.x; i < passes * R; i += blockDim.x) h[i] = 0;
-  for (int i = threadIdx.x; i <= nsets; i += blockDim.x) s_off[i] = (uint32_t)set_off[i];
-  if (nsets > 1) {
-    const int ncoarse = (int)((n - 1) >> coarse_shift) + 1;
-    for (int i = threadIdx.x; i <= ncoarse; i += blockDim.x) s_coarse[i] = coarse[i];
-  }
   __syncthreads();
-
   bool bad = false;
-  // the box of set 0 (the only one of a single build) stays in registers
-  const double b_lo0 = box[0], b_lo1 = box[1], b_lo2 = box[2];
-  const double b_scale = 2097152.0 / box[3];
+  const double lo0 = box[0], lo1 = box[1], lo2 = box[2];
+  const double scale = 2097152.0 / box[3];
   // each step a thread handles kKeygenIpt particles whose loads are all issued
   // before any is used (indices past the end are clamped and masked)
   const int64_t step = (int64_t)gridDim.x * blockDim.x * kKeygenIpt;
@@ -387,50 +414,86 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
 #pragma unroll
     for (int r = 0; r < kKeygenIpt; ++r) {
       const int64_t i = i0 + (int64_t)r * blockDim.x;
-      const bool valid = i < n;
-      double lo0 = b_lo0, lo1 = b_lo1, lo2 = b_lo2, scale = b_scale;
-      if (nsets > 1) {
-        // the set holding position i lies between the sets holding the coarse
-        // positions around it.  Positions past the end (masked below) look up
-        // the last particle's set: their coarse index would run past the table.
-        const int64_t ic = valid ? i : n - 1;
-        const int k = (int)(ic >> coarse_shift);
-        const int b = min(upper_index_in(s_off, (int)s_coarse[k], (int)s_coarse[k + 1], ic),
-                          nsets - 1);
-        lo0 = box[4 * b + 0];
-        lo1 = box[4 * b + 1];
-        lo2 = box[4 * b + 2];
-        scale = 2097152.0 / box[4 * b + 3];
-      }
-      bad |= valid && !(isfinite(x[r]) && isfinite(y[r]) && isfinite(z[r]));
-      const uint64_t key = particle_key(x[r], y[r], z[r], lo0, lo1, lo2, scale, hilbert != 0);
-      if (valid) {
-        keys[i] = key;
-        // (x, y, z, m) in one 16-byte record: the reorder step gathers one line each
-        packed[i] = make_float4(x[r], y[r], z[r], m[r]);
-      }
-      // digit histograms of every radix pass; a wave whose lanes all share the
-      // digit adds once (the upper digits of clustered data are mostly uniform)
-      const uint64_t active = __ballot(valid);
-      if (valid) {
-#pragma unroll
-        for (int p = 0; p < MAXP; ++p) {
-          const uint32_t d = (uint32_t)(key >> (p * BITS)) & (R - 1);
-          const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-          if (__ballot(d == d0) == active) {
-            if (lane_id() == __ffsll((long long)active) - 1)
-              atomicAdd(&h[p * R + d0], (uint32_t)__popcll(active));
-          } else {
-            atomicAdd(&h[p * R + d], 1u);
-          }
-        }
-      }
+      key_one<BITS>(x[r], y[r], z[r], m[r], i < n, i, lo0, lo1, lo2, scale, hilbert != 0, keys,
+                    packed, h, bad);
     }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_NONFINITE);
   __syncthreads();
   uint32_t *dst = hist_part + (int64_t)blockIdx.x * passes * R;
   for (int i = threadIdx.x; i < passes * R; i += blockDim.x) dst[i] = h[i];
+}
+
+// A batch: workgroups take chunk after chunk (at most kBboxChunk particles of one
+// set) and add each chunk's digit counts to its set's counts, set_counts[b][p][d].
+template <int BITS>
+__global__ __launch_bounds__(kKeygenThreads) void k_keygen_sets(
+    const float *__restrict__ pos, const float *__restrict__ mass, const int64_t *__restrict__ set_off,
+    const int64_t *__restrict__ chunk_start, const int32_t *__restrict__ chunk_set,
+    int32_t nsets, const double *__restrict__ box, uint64_t *__restrict__ keys,
+    float4 *__restrict__ packed, uint32_t *__restrict__ set_counts, int passes, int hilbert,
+    int32_t *__restrict__ status_word) {
+  constexpr int R = 1 << BITS;
+  constexpr int MAXP = (63 + BITS - 1) / BITS;
+  __shared__ uint32_t h[MAXP * R];
+  bool bad = false;
+  const int64_t n_chunks = chunk_start[nsets];
+  for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int b = chunk_set[c];
+    const int64_t c0 = set_off[b] + (c - chunk_start[b]) * (int64_t)kBboxChunk;
+    const int64_t c1 = min(c0 + (int64_t)kBboxChunk, set_off[b + 1]);
+    const double lo0 = box[4 * b + 0], lo1 = box[4 * b + 1], lo2 = box[4 * b + 2];
+    const double scale = 2097152.0 / box[4 * b + 3];
+    for (int64_t i0 = c0 + threadIdx.x; i0 < c1; i0 += (int64_t)blockDim.x * kKeygenIpt) {
+      float x[kKeygenIpt], y[kKeygenIpt], z[kKeygenIpt], m[kKeygenIpt];
+#pragma unroll
+      for (int r = 0; r < kKeygenIpt; ++r) {
+        const int64_t i = min(i0 + (int64_t)r * blockDim.x, c1 - 1);
+        x[r] = pos[3 * i + 0];
+        y[r] = pos[3 * i + 1];
+        z[r] = pos[3 * i + 2];
+        m[r] = mass[i];
+      }
+#pragma unroll
+      for (int r = 0; r < kKeygenIpt; ++r) {
+        const int64_t i = i0 + (int64_t)r * blockDim.x;
+        key_one<BITS>(x[r], y[r], z[r], m[r], i < c1, i, lo0, lo1, lo2, scale, hilbert != 0,
+                      keys, packed, h, bad);
+      }
+    }
+    __syncthreads();
+    uint32_t *dst = set_counts + (int64_t)b * passes * R;
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x)
+      if (h[i]) atomicAdd(&dst[i], h[i]);
+    __syncthreads();  // h is cleared for the next chunk
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_NONFINITE);
+}
+
+// Each set's digit counts of every pass -> the position where each digit's run
+// of the set starts (the set's first position plus the counts of the smaller
+// digits).  One workgroup per set, one thread per digit.
+template <int BITS>
+__global__ __launch_bounds__(1 << BITS) void k_set_base(const int64_t *__restrict__ set_off,
+                                                        uint32_t *__restrict__ set_counts,
+                                                        int passes, int32_t nsets) {
+  constexpr int R = 1 << BITS;
+  __shared__ uint32_t s_w[R / 64];
+  for (int b = blockIdx.x; b < nsets; b += gridDim.x) {
+    for (int p = 0; p < passes; ++p) {
+      uint32_t *row = set_counts + ((int64_t)b * passes + p) * R;
+      const uint32_t v = row[threadIdx.x];
+      const uint32_t inc = wave_inclusive_scan(v);
+      if (lane_id() == 63) s_w[threadIdx.x / 64] = inc;
+      __syncthreads();
+      uint32_t off = 0;
+      for (int q = 0; q < (int)threadIdx.x / 64; ++q) off += s_w[q];
+      row[threadIdx.x] = (uint32_t)set_off[b] + off + inc - v;
+      __syncthreads();
+    }
+  }
 }
 
 // hist[c] = sum over rows b of part[b][c], for c < cols.  16 columns per
@@ -466,25 +529,47 @@ int keygen_blocks(int64_t n) {
 
 hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const float *mass,
                          const tb_tree &out, hipStream_t s) {
-  const int blocks = keygen_blocks(p.n);
   const int passes = p.key_passes;
-  const int64_t ncoarse = p.nsets > 1 ? ((p.n - 1) >> p.coarse_shift) + 1 : -1;
-  const size_t lds = 4 * (size_t)(p.nsets + 1 + ncoarse + 1);
-#define TB_KEYGEN(B)                                                                          \
-  k_keygen<B><<<blocks, kKeygenThreads, lds, s>>>(pos, mass, p.n, w.set_off, p.nsets, w.box, \
-                                                  w.keys0, w.packed, w.hist_part, passes,    \
-                                                  w.coarse, p.coarse_shift,                 \
-                                                  (p.flags & TB_HILBERT) ? 1 : 0, out.status)
-  switch (p.sort.bits) {
-    case 8: TB_KEYGEN(8); break;
-    case 9: TB_KEYGEN(9); break;
-    default: return hipErrorInvalidValue;
-  }
+  const int hil = (p.flags & TB_HILBERT) ? 1 : 0;
+  if (!p.seg) {
+    const int blocks = keygen_blocks(p.n);
+#define TB_KEYGEN(B)                                                                           \
+  k_keygen<B><<<blocks, kKeygenThreads, 0, s>>>(pos, mass, p.n, w.box, w.keys0, w.packed,      \
+                                                w.hist_part, passes, hil, out.status)
+    switch (p.sort.bits) {
+      case 8: TB_KEYGEN(8); break;
+      case 9: TB_KEYGEN(9); break;
+      default: return hipErrorInvalidValue;
+    }
 #undef TB_KEYGEN
+  } else {
+    int64_t blocks = p.bbox_chunks;
+    if (blocks > 2 * kKeygenMaxBlocks) blocks = 2 * kKeygenMaxBlocks;
+#define TB_KEYGEN_SETS(B)                                                                      \
+  k_keygen_sets<B><<<(unsigned)blocks, kKeygenThreads, 0, s>>>(                                \
+      pos, mass, w.set_off, w.chunk_start, w.chunk_set, p.nsets, w.box, w.keys0, w.packed,     \
+      w.seg_base, passes, hil, out.status)
+    switch (p.sort.bits) {
+      case 8: TB_KEYGEN_SETS(8); break;
+      case 9: TB_KEYGEN_SETS(9); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef TB_KEYGEN_SETS
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s) {
+  if (p.seg) {  // each set's digit counts become its digit bases
+    const int64_t grid = p.nsets < 65535 ? p.nsets : 65535;
+    if (p.sort.bits == 8)
+      k_set_base<8><<<(unsigned)grid, 256, 0, s>>>(w.set_off, w.seg_base, p.key_passes, p.nsets);
+    else if (p.sort.bits == 9)
+      k_set_base<9><<<(unsigned)grid, 512, 0, s>>>(w.set_off, w.seg_base, p.key_passes, p.nsets);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   const int cols = p.key_passes * p.sort.radix();
   k_hist_reduce<<<(cols + 15) / 16, 256, 0, s>>>(w.hist_part, keygen_blocks(p.n), cols, w.hist);
   return hipGetLastError();

@@ -23,15 +23,17 @@
 // on its predecessors.  There, reading 4 bytes a key again costs less than the
 // look-back chain across the chip; TB_SORT_LOOKBACK keeps the look-back.
 //
-// The set-id passes of a batch run a fixed grid whose workgroups take tile
-// after tile, so that each loads the set tables into LDS once.
+// A batch sorts every set in place: a set's tiles never straddle it, its tiles'
+// look-back chain starts at its own first tile, and its digit runs start at
+// bases taken from its own digit counts (counted per set by the key kernel).
+// The passes thus give the (set, key) order with no pass over the set id.
 //
 // Key width shrinks as the passes go: a pass carries only the key bits later
 // passes still need.  Passes whose digit lies (partly) in the low 32 bits read
 // the 64-bit key; once those bits are consumed the key travels as its upper 32
-// bits; the last key pass writes no key at all, and the set-id passes of a batch
-// move only the payload.  The sorted keys themselves are recomputed from the
-// sorted particles in the reorder pass, which reads those particles anyway.
+// bits, and the last pass writes no key at all.  The sorted keys themselves are
+// recomputed from the sorted particles in the reorder pass, which reads those
+// particles anyway.
 #include "tb_internal.h"
 
 namespace tb {
@@ -82,10 +84,7 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
   return (k >> shift) & ((1u << BITS) - 1u);
 }
 
-// KIN / KOUT: key width read / written (kKeyNone in: a set-id pass).
-// SETID passes take the digit from the set that holds the payload's original
-// index, so that after the key passes they group the particles by set without
-// disturbing the key order inside a set.
+// KIN / KOUT: key width read / written.
 // Digit counts of one tile of a counted pass: tile t (the keys [t TILE,
 // (t + 1) TILE), as the scatter kernel tiles them) writes cnt[d][t].
 template <int BITS, int IPT, int THREADS, int KIN>
@@ -154,17 +153,30 @@ __global__ __launch_bounds__(THREADS) void k_tile_scan(uint32_t *__restrict__ cn
   }
 }
 
-template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED>
+// Tiles of a pass.  A single set: tile t holds keys [t TILE, (t+1) TILE) of the
+// array, and the digit runs start where the global digit counts put them.  A
+// batch: every set is sorted in place; a set's tiles never straddle it, tile t
+// of set b holds the set's keys [t TILE, (t+1) TILE) counted from the set's
+// first tile, and each digit's run of the set starts at the set's own base.
+struct SegTiles {
+  const int64_t *tile_start;  // [B + 1] first tile of each set, or NULL (single set)
+  const int32_t *tile_set;    // [tiles] set of each tile
+  const int64_t *set_off;     // [B + 1] first position of each set
+  size_t base_stride;         // words between two sets' rows of `hist`
+  int32_t nsets;
+};
+
+// hist: single set, the pass's global digit counts [radix]; batch, the pass's
+// row of each set's digit bases (set b at b * base_stride).
+template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED, bool SEG>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const void *__restrict__ kin_v, void *__restrict__ kout_v,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
     const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
     const uint32_t *__restrict__ tile_off, int32_t *__restrict__ status_word, uint32_t n_tiles,
-    const int64_t *__restrict__ set_off, int32_t nsets, const uint32_t *__restrict__ coarse,
-    int coarse_shift) {
-  constexpr bool SETID = KIN == kKeyNone;
-  using KI = typename KeyType<KIN == kKeyNone ? kKey32 : KIN>::T;
+    SegTiles seg) {
+  using KI = typename KeyType<KIN>::T;
   using KO = typename KeyType<KOUT == kKeyNone ? kKey32 : KOUT>::T;
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
@@ -178,237 +190,221 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   __shared__ uint32_t s_vals[TILE];
   __shared__ uint32_t s_wc[WAVES * R];     // per-wave digit counters, then wave offsets
   __shared__ uint32_t s_tstart[R];         // tile-local start of each digit
-  __shared__ int32_t s_goff[R];            // global position minus tile-local position
+  __shared__ int32_t s_goff[R];            // output position minus tile-local position
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
-  // SETID: [nsets + 1] set offsets, then the coarse table [K + 1]
-  extern __shared__ uint32_t s_soff[];
   const KI *__restrict__ kin = static_cast<const KI *>(kin_v);
   KO *__restrict__ kout = static_cast<KO *>(kout_v);
-  const int ncoarse = (int)(((int64_t)n - 1) >> coarse_shift) + 1;  // K
-  uint32_t *s_coarse = s_soff + nsets + 1;
-  if constexpr (SETID) {
-    for (int i = threadIdx.x; i <= nsets; i += THREADS) s_soff[i] = (uint32_t)set_off[i];
-    for (int i = threadIdx.x; i <= ncoarse; i += THREADS) s_coarse[i] = coarse[i];
-  }
-  auto digit = [&](KI kk, uint32_t vv) -> uint32_t {
-    if constexpr (SETID) {
-      // the set holding original position vv lies between the sets holding the
-      // coarse positions around it
-      const int k = (int)(vv >> coarse_shift);
-      const int b = upper_index_in(s_soff, (int)s_coarse[k], (int)s_coarse[k + 1], (int64_t)vv);
-      return ((uint32_t)b >> shift) & ((1u << BITS) - 1u);
-    } else {
-      return digit_of<BITS>(kk, shift);
-    }
-  };
+  constexpr bool batch = SEG;
 
-  // The global digit counts do not depend on the tile.
+  // Look-back passes take tiles in the order they start, so that every earlier
+  // tile is already running; counted passes (single sets only) need no order.
+  if (!COUNTED && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+  for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
+  __syncthreads();
+  const uint32_t tile = COUNTED ? xcd_tile(blockIdx.x, gridDim.x) : s_tile;
+  // a batch launches one workgroup for each tile it may have
+  const uint32_t tiles_here = batch ? (uint32_t)seg.tile_start[seg.nsets] : n_tiles;
+  if (tile >= tiles_here) {
+    // a single set launches one workgroup per tile: the counter was not reset
+    if (!batch && threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
+    return;
+  }
+  // the tile's keys [lo, lo + tile_n); its set's first tile starts the look-back
+  uint32_t lo = tile * (uint32_t)TILE, hi = n, set_lo = 0u;
+  bool first = tile == 0;
+  const uint32_t *digit_base = hist;
+  if constexpr (batch) {
+    const int b = seg.tile_set[tile];
+    const int64_t t0 = seg.tile_start[b];
+    set_lo = (uint32_t)seg.set_off[b];
+    lo = set_lo + (uint32_t)((int64_t)(tile - t0) * TILE);
+    hi = (uint32_t)seg.set_off[b + 1];
+    first = (int64_t)tile == t0;
+    digit_base = hist + (size_t)b * seg.base_stride;
+  }
+  const uint32_t tile_n = (hi - lo) < (uint32_t)TILE ? (hi - lo) : (uint32_t)TILE;
+  const uint32_t last = lo + tile_n - 1u;
+  // where each digit's run starts does not depend on the keys: issue its load first
   uint32_t g[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
     const int d = threadIdx.x * DPT + t;
-    g[t] = (d < R) ? hist[d] : 0u;
+    g[t] = (d < R) ? digit_base[d] : 0u;
   }
-  bool bad = false;
-  // Look-back passes take tiles in the order they start, so that every earlier
-  // tile is already running; counted passes need no order.  A set-id pass keeps
-  // its workgroups and takes tile after tile, so that each workgroup loads the
-  // set tables once.
-  for (;;) {
-    if (!COUNTED && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
-    __syncthreads();
-    const uint32_t tile = COUNTED ? xcd_tile(blockIdx.x, gridDim.x) : s_tile;
-    if (tile >= n_tiles) {
-      // one tile per workgroup: the counter was not reset (never after k_init)
-      if (!SETID && threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
-      break;
-    }
-    const uint32_t base = tile * TILE;
-    const int wv = threadIdx.x / 64;
-    const int ln = lane_id();
-    const uint64_t lt = lanemask_lt();
+  const int wv = threadIdx.x / 64;
+  const int ln = lane_id();
+  const uint64_t lt = lanemask_lt();
 
-    // wave-striped load: item j of lane l is key base + wv*64*IPT + j*64 + l.
-    // Loads are branch-free (indices past the end are clamped and the items
-    // masked later) so that all of them are in flight together.
-    KI k[IPT];
-    uint32_t v[IPT];
-    uint32_t dg[IPT];
-    uint32_t rk[IPT];
-    const uint32_t wbase = base + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
-    if constexpr (!SETID) {
-  #pragma unroll
-      for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, n - 1u)];
-    } else {
-  #pragma unroll
-      for (int j = 0; j < IPT; ++j) k[j] = 0;
-    }
-    if (vin) {
-  #pragma unroll
-      for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, n - 1u)];
-    } else {
-  #pragma unroll
-      for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
-    }
-  #pragma unroll
-    for (int j = 0; j < IPT; ++j) dg[j] = digit(k[j], v[j]);
+  // wave-striped load: item j of lane l is key lo + wv*64*IPT + j*64 + l.
+  // Loads are branch-free (indices past the tile are clamped and the items
+  // masked later) so that all of them are in flight together.
+  KI k[IPT];
+  uint32_t v[IPT];
+  uint32_t dg[IPT];
+  uint32_t rk[IPT];
+  const uint32_t wbase = lo + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, last)];
+  if (vin) {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, last)];
+  } else {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
+  }
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) dg[j] = digit_of<BITS>(k[j], shift);
 
-    // Stable wave-level ranking: for every digit bit a ballot; XOR-ing the
-    // ballot with "all ones unless my bit is set" keeps exactly the lanes that
-    // agree with me on that bit, so the AND over all bits is the set of lanes
-    // holding my digit.  Its population below my lane is my rank among them.
-    uint32_t *wc = s_wc + wv * R;
-  #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      const bool valid = wbase + j * 64 < n;
+  // Stable wave-level ranking: for every digit bit a ballot; XOR-ing the
+  // ballot with "all ones unless my bit is set" keeps exactly the lanes that
+  // agree with me on that bit, so the AND over all bits is the set of lanes
+  // holding my digit.  Its population below my lane is my rank among them.
+  uint32_t *wc = s_wc + wv * R;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const bool valid = wbase + j * 64 <= last;
+    const uint32_t d = dg[j];
+    const uint64_t vmask = __ballot(valid);
+    uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+      const uint32_t bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      const uint32_t flip = bit - 1u;  // 0 if my bit is set, all ones if clear
+      plo &= (uint32_t)bb ^ flip;
+      phi &= (uint32_t)(bb >> 32) ^ flip;
+    }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
+    const uint32_t pre = (uint32_t)__popcll(peers & lt);
+    uint32_t cnt = 0;
+    if (valid) cnt = wc[d];
+    rk[j] = cnt + pre;
+    if (valid && pre == 0) wc[d] = cnt + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+
+  // per digit: exclusive offsets across waves and the tile count
+  uint32_t tcnt[DPT];
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    uint32_t run = 0;
+    if (d < R) {
+#pragma unroll
+      for (int q = 0; q < WAVES; ++q) {
+        const uint32_t c = s_wc[q * R + d];
+        s_wc[q * R + d] = run;
+        run += c;
+      }
+      if constexpr (!COUNTED)
+        atomic_store_agent(&status[(size_t)tile * R + d],
+                           (first ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
+    }
+    tcnt[t] = run;
+  }
+
+  // tile-local digit starts (a block scan over the digits), and where each
+  // digit's run starts in the output: a block scan of the global digit counts,
+  // or the set's own bases
+  uint32_t tsum = 0, gsum = 0;
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    tsum += tcnt[t];
+    gsum += g[t];
+  }
+  uint32_t dummy;
+  uint32_t trun = block_exclusive_sum<THREADS>(tsum, s_tmp, &dummy);
+  uint32_t grun = 0;
+  if constexpr (!batch) grun = block_exclusive_sum<THREADS>(gsum, s_tmp, &dummy);
+
+  uint32_t trun_d[DPT], grun_d[DPT];
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    if (d < R) s_tstart[d] = trun;
+    trun_d[t] = trun;
+    grun_d[t] = batch ? g[t] : grun;
+    trun += tcnt[t];
+    grun += g[t];
+  }
+  __syncthreads();
+
+  // sort the tile by digit in LDS (the input key when a key is written, else
+  // the digit), before the look-back so that predecessors have this time to
+  // publish
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if (wbase + j * 64 <= last) {
       const uint32_t d = dg[j];
-      const uint64_t vmask = __ballot(valid);
-      uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
-  #pragma unroll
-      for (int b = 0; b < BITS; ++b) {
-        const uint32_t bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        const uint32_t flip = bit - 1u;  // 0 if my bit is set, all ones if clear
-        plo &= (uint32_t)bb ^ flip;
-        phi &= (uint32_t)(bb >> 32) ^ flip;
-      }
-      const uint64_t peers = ((uint64_t)phi << 32) | plo;
-      const uint32_t pre = (uint32_t)__popcll(peers & lt);
-      uint32_t cnt = 0;
-      if (valid) cnt = wc[d];
-      rk[j] = cnt + pre;
-      if (valid && pre == 0) wc[d] = cnt + (uint32_t)__popcll(peers);
+      const uint32_t p = s_tstart[d] + wc[d] + rk[j];
+      if constexpr (KOUT == kKeyNone)
+        reinterpret_cast<uint16_t *>(s_slot)[p] = (uint16_t)d;
+      else
+        reinterpret_cast<KI *>(s_slot)[p] = k[j];
+      s_vals[p] = v[j];
     }
-    __syncthreads();
+  }
+  // the next pass's look-back words for this tile start cleared
+  for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
 
-    // per digit: exclusive offsets across waves and the tile count
-    uint32_t tcnt[DPT];
-  #pragma unroll
-    for (int t = 0; t < DPT; ++t) {
-      const int d = threadIdx.x * DPT + t;
-      uint32_t run = 0;
-      if (d < R) {
-  #pragma unroll
-        for (int q = 0; q < WAVES; ++q) {
-          const uint32_t c = s_wc[q * R + d];
-          s_wc[q * R + d] = run;
-          run += c;
-        }
-        if constexpr (!COUNTED)
-          atomic_store_agent(&status[(size_t)tile * R + d],
-                             (tile == 0 ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
+  // decoupled look-back within the set (or the counted offsets), one thread per digit
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    if (d < R) {
+      uint32_t excl = 0;
+      if (COUNTED) {
+        excl = tile_off[(size_t)d * n_tiles + tile];
+      } else if (!first) {
+        bool timed_out = false;
+        excl = lookback<2>(status, R, tile, d, timed_out);
+        if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
+        atomic_store_agent(&status[(size_t)tile * R + d],
+                           kFlagInclusive | (uint64_t)(excl + tcnt[t]));
       }
-      tcnt[t] = run;
+      s_goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
     }
+  }
+  __syncthreads();
 
-    // tile-local digit starts and global digit starts (block scans over digits)
-    uint32_t tsum = 0, gsum = 0;
-  #pragma unroll
-    for (int t = 0; t < DPT; ++t) {
-      tsum += tcnt[t];
-      gsum += g[t];
+  // coalesced scatter: consecutive lanes write consecutive slots of a digit run,
+  // inside the tile's set [set_lo, hi)
+  bool bad = false;
+  for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
+    uint32_t d;
+    KO key = 0;
+    if constexpr (KOUT == kKeyNone) {
+      d = reinterpret_cast<const uint16_t *>(s_slot)[i];
+    } else {
+      const KI kk = reinterpret_cast<const KI *>(s_slot)[i];
+      d = digit_of<BITS>(kk, shift);
+      // a 64-bit key keeps only its upper half once its low bits are consumed
+      key = (KIN == kKey64 && KOUT == kKey32) ? (KO)((uint64_t)kk >> 32) : (KO)kk;
     }
-    uint32_t dummy;
-    uint32_t trun = block_exclusive_sum<THREADS>(tsum, s_tmp, &dummy);
-    uint32_t grun = block_exclusive_sum<THREADS>(gsum, s_tmp, &dummy);
-
-    // tile-local digit starts; the local sort below needs nothing global
-    uint32_t trun_d[DPT], grun_d[DPT];
-  #pragma unroll
-    for (int t = 0; t < DPT; ++t) {
-      const int d = threadIdx.x * DPT + t;
-      if (d < R) s_tstart[d] = trun;
-      trun_d[t] = trun;
-      grun_d[t] = grun;
-      trun += tcnt[t];
-      grun += g[t];
+    const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
+    if (gp < set_lo || gp >= hi) {  // cannot happen with consistent digit counts
+      bad = true;
+      continue;
     }
-    __syncthreads();
-
-    // sort the tile by digit in LDS (the input key when a key is written, else
-    // the digit), before the look-back so that predecessors have this time to
-    // publish
-  #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      if (wbase + j * 64 < n) {
-        const uint32_t d = dg[j];
-        const uint32_t p = s_tstart[d] + wc[d] + rk[j];
-        if constexpr (KOUT == kKeyNone)
-          reinterpret_cast<uint16_t *>(s_slot)[p] = (uint16_t)d;
-        else
-          reinterpret_cast<KI *>(s_slot)[p] = k[j];
-        s_vals[p] = v[j];
-      }
-    }
-    // the next pass's look-back words for this tile start cleared
-    for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
-
-    // decoupled look-back (or the counted offsets), one thread per digit
-  #pragma unroll
-    for (int t = 0; t < DPT; ++t) {
-      const int d = threadIdx.x * DPT + t;
-      if (d < R) {
-        uint32_t excl = 0;
-        if (COUNTED) {
-          excl = tile_off[(size_t)d * n_tiles + tile];
-        } else if (tile > 0) {
-          bool timed_out = false;
-          excl = lookback<2>(status, R, tile, d, timed_out);
-          if (timed_out) atomicOr(status_word, TB_STATUS_INTERNAL);
-          atomic_store_agent(&status[(size_t)tile * R + d],
-                             kFlagInclusive | (uint64_t)(excl + tcnt[t]));
-        }
-        s_goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
-      }
-    }
-    __syncthreads();
-
-    // coalesced scatter: consecutive lanes write consecutive slots of a digit run
-    const uint32_t tile_n = (n - base) < (uint32_t)TILE ? (n - base) : (uint32_t)TILE;
-    for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
-      uint32_t d;
-      KO key = 0;
-      if constexpr (KOUT == kKeyNone) {
-        d = reinterpret_cast<const uint16_t *>(s_slot)[i];
-      } else {
-        const KI kk = reinterpret_cast<const KI *>(s_slot)[i];
-        d = digit_of<BITS>(kk, shift);
-        // a 64-bit key keeps only its upper half once its low bits are consumed
-        key = (KIN == kKey64 && KOUT == kKey32) ? (KO)((uint64_t)kk >> 32) : (KO)kk;
-      }
-      const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
-      if (gp >= n) {  // cannot happen with consistent histograms
-        bad = true;
-        continue;
-      }
-      if constexpr (KOUT != kKeyNone) kout[gp] = key;
-      vout[gp] = s_vals[i];
-    }
-    if constexpr (!SETID) break;
-    __syncthreads();  // the next tile reuses the shared arrays
+    if constexpr (KOUT != kKeyNone) kout[gp] = key;
+    vout[gp] = s_vals[i];
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
 // Key widths of pass `pass`: a key pass whose digit starts below bit 32 reads
-// the 64-bit key; later key passes read the upper 32 bits; set-id passes read
-// no key.  A pass writes what the next pass reads.
-static int key_in(const Plan &p, int pass) {
-  if (pass >= p.key_passes) return kKeyNone;
-  return pass * p.sort.bits < 32 ? kKey64 : kKey32;
-}
+// the 64-bit key; later key passes read the upper 32 bits.  A pass writes what
+// the next pass reads; the last writes no key.
+static int key_in(const Plan &p, int pass) { return pass * p.sort.bits < 32 ? kKey64 : kKey32; }
 static int key_out(const Plan &p, int pass) {
   return pass + 1 < p.key_passes ? key_in(p, pass + 1) : kKeyNone;
 }
 
-constexpr int64_t kSetPassWorkgroups = 512;
-
 template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED>
 static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
-  const int P = p.key_passes + p.set_passes;
+  const int P = p.key_passes;
   void *K[2] = {w.keys0, w.keys1};
   // the last pass must write its payload into out.perm
   uint32_t *V[2];
@@ -417,26 +413,25 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
   uint64_t *S[2] = {w.status0, w.status1};
   const uint32_t *vin = pass == 0 ? nullptr : V[pass % 2];
   const int R = 1 << BITS;
-  int shift;
-  if (KIN == kKeyNone)
-    shift = (pass - p.key_passes) * BITS;  // set-id digit
-  else
-    shift = pass * BITS - (KIN == kKey32 ? 32 : 0);
-  const int64_t ncoarse = ((p.n - 1) >> p.coarse_shift) + 1;
-  const size_t lds = KIN == kKeyNone ? 4 * (size_t)(p.nsets + 1 + ncoarse + 1) : 0;
+  const int shift = pass * BITS - (KIN == kKey32 ? 32 : 0);
   if constexpr (COUNTED) {
-    static_assert(KIN != kKeyNone, "set-id passes use the look-back");
     k_tile_count<BITS, IPT, THREADS, KIN><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
         K[pass % 2], (uint32_t)p.n, shift, w.tile_off, (uint32_t)p.sort_tiles);
     k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
   }
-  // set-id passes: two workgroups per CU take the tiles in turn
-  const int64_t grid =
-      KIN == kKeyNone && p.sort_tiles > kSetPassWorkgroups ? kSetPassWorkgroups : p.sort_tiles;
-  k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED><<<(unsigned)grid, THREADS, lds, s>>>(
-      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift,
-      w.hist + (size_t)pass * R, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, w.tile_off,
-      out.status, (uint32_t)p.sort_tiles, w.set_off, p.nsets, w.coarse, p.coarse_shift);
+  SegTiles seg{nullptr, nullptr, nullptr, 0, p.nsets};
+  const uint32_t *hist = w.hist + (size_t)pass * R;
+  if (p.seg) {
+    seg = SegTiles{w.seg_tile_start, w.seg_tile_set, w.set_off, (size_t)p.key_passes * R,
+                   p.nsets};
+    hist = w.seg_base + (size_t)pass * R;
+  }
+  auto k = p.seg ? k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED, true>
+                 : k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED, false>;
+  k<<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
+      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift, hist,
+      S[pass % 2], S[(pass + 1) % 2], w.counters + pass, w.tile_off, out.status,
+      (uint32_t)p.sort_tiles, seg);
   return hipGetLastError();
 }
 
@@ -444,7 +439,7 @@ template <int BITS, int IPT, int THREADS>
 static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
   const int ki = key_in(p, pass), ko = key_out(p, pass);
-  const bool counted = pass < p.key_passes && ((p.counted >> pass) & 1u);
+  const bool counted = (p.counted >> pass) & 1u;
   if (ki == kKey64 && ko == kKey64)
     return counted ? launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64, true>(p, w, pass, out, s)
                    : launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64, false>(p, w, pass, out, s);
@@ -458,8 +453,6 @@ static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb
     return counted
                ? launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone, true>(p, w, pass, out, s)
                : launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone, false>(p, w, pass, out, s);
-  if (ki == kKeyNone && ko == kKeyNone)
-    return launch_pass_k<BITS, IPT, THREADS, kKeyNone, kKeyNone, false>(p, w, pass, out, s);
   return hipErrorInvalidValue;  // no other combination arises for 8- or 9-bit digits
 }
 

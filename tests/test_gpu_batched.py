@@ -154,9 +154,10 @@ def test_one_set_batch_equals_single_build():
 
 @pytest.mark.parametrize("lookback", [False, True])
 @pytest.mark.parametrize("sort_config", [0, 2])
-def test_many_small_sets_two_set_digits(sort_config, lookback):
-    """600 sets: two 8-bit set-id digits (config 0) or one 9-bit digit (config 2),
-    after counted key passes or after the look-back in every key pass."""
+def test_many_small_sets(sort_config, lookback):
+    """600 sets of up to 300 particles, many sharing one radix tile's worth of
+    positions with their neighbours but each sorted in place in tiles of its own;
+    8- and 9-bit digits (configs 0 and 2), with and without TB_SORT_LOOKBACK."""
     rng = _rng(33)
     sizes = rng.integers(0, 300, 600)
     sizes[::50] = 0

@@ -40,12 +40,12 @@ def test_autotune_cache_tolerates_damage(tmp_path):
 
 def test_sort_bytes_follow_key_widths():
     n = 1 << 20
-    b8 = bench.kernel_bytes(n, 0, 0, 8, 0, "fp64")["sort_pass"] / n
+    b8 = bench.kernel_bytes(n, 0, 0, 8, "fp64")["sort_pass"] / n
     # passes 0..3 read 64-bit keys (pass 3 writes their upper halves), passes
     # 4..6 move 32-bit keys, the last writes no key; payload 4 B in and out
     assert b8 == (8 + 0 + 8 + 4) + 2 * (8 + 4 + 8 + 4) + (8 + 4 + 4 + 4) + 2 * (4 + 4 + 4 + 4) \
         + (4 + 4 + 4 + 4) + (4 + 4 + 0 + 4)
-    b9 = bench.kernel_bytes(n, 0, 0, 7, 0, "fp64")["sort_pass"] / n
+    b9 = bench.kernel_bytes(n, 0, 0, 7, "fp64")["sort_pass"] / n
     assert b9 == (8 + 0 + 8 + 4) + 2 * (8 + 4 + 8 + 4) + (8 + 4 + 4 + 4) + 2 * (4 + 4 + 4 + 4) \
         + (4 + 4 + 0 + 4)
 
@@ -92,45 +92,27 @@ def test_bench_refuses_more_than_one_gpu():
 
 
 # --------------------------------------------------------------------------
-# the batched set lookup through the coarse set table, emulated on the CPU
+# the per-set radix tiles and key chunks of a batch, emulated on the CPU
 # --------------------------------------------------------------------------
-# The key kernel and the set-id sort passes find the set that holds position x
-# as follows (tb_keys.hip, k_setup / k_keygen; tb_sort.hip, k_onesweep):
-#   shift  : smallest s with ceil(n / 2^s) <= K_COARSE                (make_plan)
-#   coarse : coarse[k] = last b with off[b] <= min(k << shift, n - 1),
-#            for k = 0 .. ((n - 1) >> shift)                            (k_setup)
-#   lookup : k = x >> shift; b = last index in [coarse[k], coarse[k + 1]]
-#            with off[b] <= x, found by the kernels' binary search; the key
-#            kernel clamps x to n - 1 for lanes past the end and b to B - 1.
-# The emulation checks that every index stays inside the table and that the
-# set found is the one a plain search over all offsets finds.
+# A batch sorts every set in place (tb_keys.hip k_setup / k_tile_map /
+# k_keygen_sets; tb_sort.hip k_onesweep):
+#   tiles  : set b has ceil(n_b / TILE) radix tiles starting at tile_start[b]
+#            (an exclusive scan over the sets), tile_set[t] = last b with
+#            tile_start[b] <= t; tile t of set b holds positions
+#            [off[b] + (t - tile_start[b]) TILE, min(+TILE, off[b + 1]));
+#   chunks : the same with kBboxChunk = 65536 for the key kernel's chunks;
+#   grid   : one workgroup per possible tile, N / TILE + B + ... of them; those
+#            past tile_start[B] leave at once.
+# The emulation checks that the tiles and chunks of every layout cover each
+# set exactly once, never straddle a set, and that every index stays inside
+# the tables and the workspace the plan sizes.
 
-K_COARSE = 4096
-
-
-def _coarse_shift(n):
-    s = 0
-    while (n + (1 << s) - 1) >> s > K_COARSE:
-        s += 1
-    return s
-
-
-def _upper_index_in(tab, lo, hi, x):
-    """Vectorised copy of the kernels' search: last b in [lo, hi] with tab[b] <= x,
-    given tab[lo] <= x."""
-    lo, hi = lo.copy(), hi.copy()
-    while True:
-        act = lo < hi
-        if not act.any():
-            return lo
-        mid = (lo + hi + 1) >> 1
-        ok = tab[np.minimum(mid, len(tab) - 1)] <= x
-        lo = np.where(act & ok, mid, lo)
-        hi = np.where(act & ~ok, mid - 1, hi)
+TILE = 512 * 11
+CHUNK = 65536
 
 
 def _random_layout(rng):
-    nsets = int(rng.choice([1, 2, 7, 64, 1000, 4096, 16383]))
+    nsets = int(rng.choice([2, 7, 64, 1000, 4096, 16383]))
     sizes = rng.integers(0, rng.choice([3, 40, 3000, 70000]), nsets)
     sizes[rng.random(nsets) < 0.2] = 0  # empty sets anywhere, also at both ends
     if sizes.sum() == 0:
@@ -139,35 +121,39 @@ def _random_layout(rng):
     return nsets, off
 
 
-def test_coarse_set_lookup_emulation():
+def _tables(off, unit):
+    sizes = np.diff(off)
+    per = (sizes + unit - 1) // unit
+    start = np.concatenate([[0], np.cumsum(per)]).astype(np.int64)
+    t = np.arange(start[-1], dtype=np.int64)
+    owner = np.searchsorted(start, t, side="right") - 1  # last b with start[b] <= t
+    lo = off[owner] + (t - start[owner]) * unit
+    hi = np.minimum(lo + unit, off[owner + 1])
+    return start, owner, lo, hi
+
+
+def test_batch_tiles_and_chunks_emulation():
     rng = np.random.default_rng(2024)
-    lookups = 0
+    checked = 0
     for _ in range(300):
         nsets, off = _random_layout(rng)
         n = int(off[-1])
-        shift = _coarse_shift(n)
-        K = ((n - 1) >> shift) + 1
-        assert K <= K_COARSE
-        kpos = np.minimum(np.arange(K + 1, dtype=np.int64) << shift, n - 1)
-        # k_setup: the set holding each coarse position (search over all B + 1 offsets)
-        coarse = _upper_index_in(off, np.zeros(K + 1, np.int64), np.full(K + 1, nsets, np.int64),
-                                 kpos)
-        assert coarse.max() <= nsets - 1  # off[B] = n is never <= a position below n
-        # every position of small batches, a sample plus every set boundary of large
-        # ones, and lanes past the end (clamped to n - 1 by the key kernel)
-        if n <= 20000:
-            x = np.arange(n, dtype=np.int64)
-        else:
-            edges = np.concatenate([off[:-1], off[1:] - 1, kpos]).clip(0, n - 1)
-            x = np.concatenate([rng.integers(0, n, 20000), edges])
-        x = np.concatenate([x, np.full(64, n - 1, np.int64)])
-        k = x >> shift
-        assert k.max() + 1 <= K  # both table entries read stay inside the K + 1 entries
-        lo, hi = coarse[k], coarse[k + 1]
-        assert np.all(off[lo] <= x) and np.all(lo <= hi)
-        b = np.minimum(_upper_index_in(off, lo, hi, x), nsets - 1)
-        want = np.searchsorted(off, x, side="right") - 1
-        assert np.array_equal(b, want)
-        assert np.all((off[b] <= x) & (x < off[b + 1]))  # a non-empty set holding x
-        lookups += x.size
-    assert lookups > 5_000_000
+        for unit, bound in ((TILE, (n + TILE - 1) // TILE + nsets),
+                            (CHUNK, (n + CHUNK - 1) // CHUNK + nsets)):
+            start, owner, lo, hi = _tables(off, unit)
+            assert start[-1] <= bound  # the plan's grid and table sizes
+            assert np.all((owner >= 0) & (owner < nsets))
+            assert np.all(lo < hi) and np.all(hi - lo <= unit)
+            assert np.all((off[owner] <= lo) & (hi <= off[owner + 1]))  # never straddles a set
+            # every position exactly once: within a set the tiles abut, a set's
+            # first tile starts at its first position and its last ends at its end
+            same = owner[1:] == owner[:-1]
+            assert np.all(lo[1:][same] == hi[:-1][same])
+            assert np.all(hi[:-1][~same] == off[owner[:-1][~same] + 1])
+            sizes = np.diff(off)
+            assert np.array_equal(np.bincount(owner, weights=hi - lo, minlength=nsets), sizes)
+            # a set's first tile starts its look-back chain: tile == start[owner]
+            first = np.arange(start[-1]) == start[owner]
+            assert np.array_equal(lo[first], off[owner[first]])
+            checked += len(lo)
+    assert checked > 100_000
