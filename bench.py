@@ -156,6 +156,7 @@ def _short_kernel(name: str) -> str:
 
 STAGE_OF = [("k_onesweep", "sort_pass"), ("k_tile_count", "sort_pass"),
             ("k_tile_scan", "sort_pass"), ("k_keygen", "keygen"), ("k_hist_reduce", "hist_reduce"),
+            ("k_set_base", "hist_reduce"), ("k_set_sums", "cell_scan"),
             ("k_reorder", "reorder"), ("k_cell_emit", "cell_emit"), ("k_cell_scan", "cell_scan"),
             ("k_set_scan", "cell_scan"), ("k_parents", "parents"), ("k_init", "init"),
             ("k_setup", "setup"), ("k_tile_map", "setup"), ("k_bbox", "bbox"),

@@ -59,9 +59,9 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
       if (k * sc.bits >= 32 || (flags & TB_SORT_COUNTED)) p->counted |= 1u << k;
   // tiles never straddle two sets: at most one partial tile per set
   p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;
-  // chunks of at most kBboxChunk particles of one set: the auto box and, in a
-  // batch, the key kernel's per-set digit counts work chunk by chunk
-  p->bbox_chunks = ((flags & kAutoBoxFlag) || p->seg) ? (n + kBboxChunk - 1) / kBboxChunk + nsets : 1;
+  // chunks of at most kBboxChunk particles of one set: the auto box works chunk
+  // by chunk
+  p->bbox_chunks = (flags & kAutoBoxFlag) ? (n + kBboxChunk - 1) / kBboxChunk + nsets : 1;
   // a set of n_b particles has at most n_b + 21 floor(n_b / (n_leaf + 1)) cells,
   // and the sum over the sets is bounded by the same expression of n
   p->c_max = max_cells(n, n_leaf);
@@ -94,6 +94,7 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->set_tot = take(4 * (size_t)nsets * kLevels);
   p->set_cells = take(8 * B1);
   p->lvl_off = take(8 * (size_t)nsets * (kLevels + 1));
+  p->set_wg = take(8 * (size_t)((nsets + 255) / 256) * kLevels);
   p->par_start = take(8 * (size_t)kLevels * B1);
   p->seg_tile_start = take(p->seg ? 8 * B1 : 0);
   p->seg_tile_set = take(p->seg ? 4 * (size_t)p->sort_tiles : 0);
@@ -139,6 +140,7 @@ Work carve(const Plan &p, void *base) {
   w.set_tot = reinterpret_cast<uint32_t *>(b + p.set_tot);
   w.set_cells = reinterpret_cast<int64_t *>(b + p.set_cells);
   w.lvl_off = reinterpret_cast<int64_t *>(b + p.lvl_off);
+  w.set_wg = reinterpret_cast<int64_t *>(b + p.set_wg);
   w.par_start = reinterpret_cast<int64_t *>(b + p.par_start);
   w.seg_tile_start = reinterpret_cast<int64_t *>(b + p.seg_tile_start);
   w.seg_tile_set = reinterpret_cast<int32_t *>(b + p.seg_tile_set);

@@ -23,7 +23,7 @@
 //                the keys of its tile plus an n_leaf halo, a_i and D_i of every
 //                particle and the tile's per-depth cell counts;
 // k_cell_scan  : per-depth prefix over the tiles of each set;
-// k_set_scan   : first cell of every set and depth;
+// k_set_scan_* : first cell of every set and depth;
 // k_cell_emit  : writes key, depth, first particle and first-child slot of
 //                every cell, and count plus moments of every leaf.
 // (With TB_SUBTREES the cells are written block by block instead:
@@ -324,84 +324,151 @@ __global__ __launch_bounds__(THREADS) void k_cell_scan(
   }
 }
 
-// One workgroup over all sets, THREADS sets per round and every row of a round
-// at once: the first cell of every set and of every depth of every set, the
-// outputs level_offset [B][23], cell_offsets [B+1] and n_cells, the
-// parent-pass chunk tables, and the boxes used.  Up to 64 sets take one wave.
+// Rows of the set scan: 0 = cells per set; r = 1..21 = parent-pass chunks at
+// depth r - 1 (children at depth r).
+__device__ inline void set_rows(const uint32_t *__restrict__ set_tot, int32_t nsets, int b,
+                                uint32_t t[kLevels], uint32_t v[kLevels]) {
+#pragma unroll
+  for (int d = 0; d < kLevels; ++d) t[d] = (b < nsets) ? set_tot[b * kLevels + d] : 0u;
+  v[0] = 0;
+#pragma unroll
+  for (int d = 0; d < kLevels; ++d) v[0] += t[d];
+#pragma unroll
+  for (int r = 1; r < kLevels; ++r) v[r] = (t[r] + kParentChunk - 1) / kParentChunk;
+}
+
+// Sets [b0, b0 + THREADS), one per thread, every row at once, given in s_carry
+// the sums of every row over the sets before b0: writes the first cell of every
+// set and of every depth of every set (level_offset [B][23], cell_offsets), the
+// parent-pass chunk tables and the boxes used, and leaves in s_w the block's
+// per-wave row sums.
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_set_scan(
+__device__ inline void set_scan_block(
+    int b0, const uint32_t *__restrict__ set_tot, int32_t nsets, int64_t *__restrict__ set_cells,
+    int64_t *__restrict__ lvl_off, int64_t *__restrict__ level_offset,
+    int64_t *__restrict__ cell_offsets, int64_t *__restrict__ par_start,
+    const double *__restrict__ box, double *__restrict__ box_out,
+    uint32_t (*s_w)[THREADS / 64], const int64_t *s_carry) {
+  const int wv = threadIdx.x / 64;
+  const int b = b0 + threadIdx.x;
+  uint32_t t[kLevels], v[kLevels], inc[kLevels];
+  set_rows(set_tot, nsets, b, t, v);
+#pragma unroll
+  for (int r = 0; r < kLevels; ++r) inc[r] = wave_inclusive_scan(v[r]);
+  if (lane_id() == 63) {
+#pragma unroll
+    for (int r = 0; r < kLevels; ++r) s_w[r][wv] = inc[r];
+  }
+  __syncthreads();
+  int64_t off[kLevels];
+#pragma unroll
+  for (int r = 0; r < kLevels; ++r) {
+    int64_t o = s_carry[r];
+    for (int q = 0; q < wv; ++q) o += s_w[r][q];
+    off[r] = o + (int64_t)(inc[r] - v[r]);
+  }
+  if (b < nsets) {
+    set_cells[b] = off[0];
+    if (cell_offsets) cell_offsets[b] = off[0];
+    int64_t run = off[0];
+#pragma unroll
+    for (int d = 0; d < kLevels; ++d) {
+      lvl_off[b * (kLevels + 1) + d] = run;
+      level_offset[b * (kLevels + 1) + d] = run;
+      run += t[d];
+    }
+    lvl_off[b * (kLevels + 1) + kLevels] = run;
+    level_offset[b * (kLevels + 1) + kLevels] = run;
+    if (box_out)
+      for (int k = 0; k < 4; ++k) box_out[4 * b + k] = box[4 * b + k];
+#pragma unroll
+    for (int r = 1; r < kLevels; ++r) par_start[(r - 1) * (nsets + 1) + b] = off[r];
+  }
+}
+
+// The totals over all sets: set_cells[B], cell_offsets[B], n_cells and the last
+// entry of every parent-pass chunk table (thread r < kLevels writes row r).
+__device__ inline void set_scan_totals(int r, int64_t total, int32_t nsets,
+                                       int64_t *__restrict__ set_cells,
+                                       int64_t *__restrict__ cell_offsets,
+                                       int64_t *__restrict__ n_cells,
+                                       int64_t *__restrict__ par_start) {
+  if (r == 0) {
+    set_cells[nsets] = total;
+    if (cell_offsets) cell_offsets[nsets] = total;
+    *n_cells = total;
+  } else {
+    par_start[(r - 1) * (nsets + 1) + nsets] = total;
+  }
+}
+
+// Up to 64 sets: one wave does the whole scan.
+__global__ __launch_bounds__(64) void k_set_scan_wave(
     const uint32_t *__restrict__ set_tot, int32_t nsets, int64_t *__restrict__ set_cells,
     int64_t *__restrict__ lvl_off, int64_t *__restrict__ level_offset,
     int64_t *__restrict__ cell_offsets, int64_t *__restrict__ n_cells,
     int64_t *__restrict__ par_start, const double *__restrict__ box,
     double *__restrict__ box_out) {
-  constexpr int kSetScanWaves = THREADS / 64;
-  // rows: 0 = cells per set, r = 1..21 = parent chunks at depth r - 1 (children at depth r)
-  __shared__ uint32_t s_w[kLevels][kSetScanWaves];
+  __shared__ uint32_t s_w[kLevels][1];
   __shared__ int64_t s_carry[kLevels];
-  const int wv = threadIdx.x / 64;
   if (threadIdx.x < kLevels) s_carry[threadIdx.x] = 0;
   __syncthreads();
-  for (int r0 = 0; r0 < nsets; r0 += THREADS) {
-    const int b = r0 + threadIdx.x;
-    uint32_t t[kLevels];
+  set_scan_block<64>(0, set_tot, nsets, set_cells, lvl_off, level_offset, cell_offsets,
+                     par_start, box, box_out, s_w, s_carry);
+  __syncthreads();
+  if (threadIdx.x < kLevels)
+    set_scan_totals(threadIdx.x, (int64_t)s_w[threadIdx.x][0], nsets, set_cells, cell_offsets,
+                    n_cells, par_start);
+}
+
+// More sets: kSetScanThreads sets per workgroup over G workgroups, in two
+// launches.  k_set_sums writes the row sums of each workgroup's sets,
+// wg_sum[g][r]; k_set_scan_wg adds the sums of the earlier workgroups to its own
+// block scan.
+constexpr int kSetScanThreads = 256;
+
+__global__ __launch_bounds__(kSetScanThreads) void k_set_sums(
+    const uint32_t *__restrict__ set_tot, int32_t nsets, int64_t *__restrict__ wg_sum) {
+  constexpr int W = kSetScanThreads / 64;
+  __shared__ uint32_t s_w[kLevels][W];
+  uint32_t t[kLevels], v[kLevels];
+  set_rows(set_tot, nsets, blockIdx.x * kSetScanThreads + threadIdx.x, t, v);
 #pragma unroll
-    for (int d = 0; d < kLevels; ++d) t[d] = (b < nsets) ? set_tot[b * kLevels + d] : 0u;
-    uint32_t v[kLevels], inc[kLevels];
-    v[0] = 0;
-#pragma unroll
-    for (int d = 0; d < kLevels; ++d) v[0] += t[d];
-#pragma unroll
-    for (int r = 1; r < kLevels; ++r) v[r] = (t[r] + kParentChunk - 1) / kParentChunk;
-#pragma unroll
-    for (int r = 0; r < kLevels; ++r) inc[r] = wave_inclusive_scan(v[r]);
-    if (lane_id() == 63) {
-#pragma unroll
-      for (int r = 0; r < kLevels; ++r) s_w[r][wv] = inc[r];
-    }
-    __syncthreads();
-    int64_t off[kLevels];
-#pragma unroll
-    for (int r = 0; r < kLevels; ++r) {
-      int64_t o = s_carry[r];
-      for (int q = 0; q < wv; ++q) o += s_w[r][q];
-      off[r] = o + (int64_t)(inc[r] - v[r]);
-    }
-    if (b < nsets) {
-      set_cells[b] = off[0];
-      if (cell_offsets) cell_offsets[b] = off[0];
-      int64_t run = off[0];
-#pragma unroll
-      for (int d = 0; d < kLevels; ++d) {
-        lvl_off[b * (kLevels + 1) + d] = run;
-        level_offset[b * (kLevels + 1) + d] = run;
-        run += t[d];
-      }
-      lvl_off[b * (kLevels + 1) + kLevels] = run;
-      level_offset[b * (kLevels + 1) + kLevels] = run;
-      if (box_out)
-        for (int k = 0; k < 4; ++k) box_out[4 * b + k] = box[4 * b + k];
-#pragma unroll
-      for (int r = 1; r < kLevels; ++r) par_start[(r - 1) * (nsets + 1) + b] = off[r];
-    }
-    __syncthreads();
-    if (threadIdx.x < kLevels) {
-      int64_t tot = 0;
-      for (int q = 0; q < kSetScanWaves; ++q) tot += s_w[threadIdx.x][q];
-      s_carry[threadIdx.x] += tot;
-    }
-    __syncthreads();
+  for (int r = 0; r < kLevels; ++r) {
+    const uint32_t inc = wave_inclusive_scan(v[r]);
+    if (lane_id() == 63) s_w[r][threadIdx.x / 64] = inc;
   }
+  __syncthreads();
   if (threadIdx.x < kLevels) {
-    const int r = threadIdx.x;
-    const int64_t total = s_carry[r];
-    if (r == 0) {
-      set_cells[nsets] = total;
-      if (cell_offsets) cell_offsets[nsets] = total;
-      *n_cells = total;
-    } else {
-      par_start[(r - 1) * (nsets + 1) + nsets] = total;
-    }
+    int64_t tot = 0;
+    for (int q = 0; q < W; ++q) tot += s_w[threadIdx.x][q];
+    wg_sum[blockIdx.x * kLevels + threadIdx.x] = tot;
+  }
+}
+
+__global__ __launch_bounds__(kSetScanThreads) void k_set_scan_wg(
+    const uint32_t *__restrict__ set_tot, int32_t nsets, const int64_t *__restrict__ wg_sum,
+    int64_t *__restrict__ set_cells, int64_t *__restrict__ lvl_off,
+    int64_t *__restrict__ level_offset, int64_t *__restrict__ cell_offsets,
+    int64_t *__restrict__ n_cells, int64_t *__restrict__ par_start,
+    const double *__restrict__ box, double *__restrict__ box_out) {
+  constexpr int W = kSetScanThreads / 64;
+  __shared__ uint32_t s_w[kLevels][W];
+  __shared__ int64_t s_carry[kLevels];
+  if (threadIdx.x < kLevels) {
+    int64_t c = 0;
+    for (int g = 0; g < (int)blockIdx.x; ++g) c += wg_sum[g * kLevels + threadIdx.x];
+    s_carry[threadIdx.x] = c;
+  }
+  __syncthreads();
+  set_scan_block<kSetScanThreads>(blockIdx.x * kSetScanThreads, set_tot, nsets, set_cells,
+                                  lvl_off, level_offset, cell_offsets, par_start, box, box_out,
+                                  s_w, s_carry);
+  __syncthreads();
+  if (blockIdx.x + 1 == gridDim.x && threadIdx.x < kLevels) {
+    int64_t tot = s_carry[threadIdx.x];
+    for (int q = 0; q < W; ++q) tot += s_w[threadIdx.x][q];
+    set_scan_totals(threadIdx.x, tot, nsets, set_cells, cell_offsets, n_cells, par_start);
   }
 }
 
@@ -679,13 +746,16 @@ hipError_t launch_cell_scan(const Plan &p, const Work &w, const tb_tree &out,
   else
     k_cell_scan<256><<<dim3(kLevels, gy), 256, 0, s>>>(w.cell_cnt, p.cell_tiles, w.tile_start,
                                                       p.nsets, w.cell_excl, w.set_tot);
-  if (p.nsets <= 64)
-    k_set_scan<64><<<1, 64, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off, out.level_offset,
-                                    cell_offsets, out.n_cells, w.par_start, w.box, out.box_out);
-  else  // 512 threads: its 22 counts per set fit in registers (1024 would spill)
-    k_set_scan<512><<<1, 512, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off,
-                                      out.level_offset, cell_offsets, out.n_cells, w.par_start,
-                                      w.box, out.box_out);
+  if (p.nsets <= 64) {
+    k_set_scan_wave<<<1, 64, 0, s>>>(w.set_tot, p.nsets, w.set_cells, w.lvl_off, out.level_offset,
+                                     cell_offsets, out.n_cells, w.par_start, w.box, out.box_out);
+  } else {
+    const int g = (p.nsets + kSetScanThreads - 1) / kSetScanThreads;
+    k_set_sums<<<g, kSetScanThreads, 0, s>>>(w.set_tot, p.nsets, w.set_wg);
+    k_set_scan_wg<<<g, kSetScanThreads, 0, s>>>(w.set_tot, p.nsets, w.set_wg, w.set_cells,
+                                                w.lvl_off, out.level_offset, cell_offsets,
+                                                out.n_cells, w.par_start, w.box, out.box_out);
+  }
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ constexpr uint32_t kXcds = 8;
 constexpr int kParentThreads = 256;
 constexpr int kParentChunk = kParentThreads;
 
-// Chunks of at most kBboxChunk particles of one set (the auto box; a batch's key kernel).
+// Chunks of at most kBboxChunk particles of one set (the auto box).
 constexpr int kBboxChunk = 65536;
 
 // Largest number of sets in one batch.
@@ -100,6 +100,7 @@ struct Plan {
   size_t set_tot;       // u32 [B][kLevels] cells of each set and depth
   size_t set_cells;     // i64 [B + 1] first cell of each set; [B] = all cells
   size_t lvl_off;       // i64 [B][kLevels + 1] first cell of each depth of each set
+  size_t set_wg;        // i64 [ceil(B / 256)][kLevels] row sums of each set-scan workgroup
   size_t par_start;     // i64 [kLevels][B + 1] parent-pass chunks per depth and set
   size_t seg_tile_start;  // i64 [B + 1] first radix tile of each set (seg)
   size_t seg_tile_set;    // i32 [sort_tiles] set of each radix tile (seg)
@@ -139,6 +140,7 @@ struct Work {
   uint32_t *set_tot;
   int64_t *set_cells;
   int64_t *lvl_off;
+  int64_t *set_wg;
   int64_t *par_start;
   int64_t *seg_tile_start;
   int32_t *seg_tile_set;

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_tile_map(
 hipError_t launch_setup(const Plan &p, const Work &w, const BatchIn &in, int32_t *status,
                         hipStream_t s) {
   if (single_set(p, in)) return hipSuccess;  // written by k_init
-  const bool with_chunks = in.auto_box || p.seg;
+  const bool with_chunks = in.auto_box;
   k_setup<<<1, kSetupThreads, 0, s>>>(w.set_off, p.nsets, p.n, w.tile_start, w.chunk_start,
                                       p.seg ? w.seg_tile_start : nullptr, p.sort.tile(),
                                       with_chunks ? 1 : 0, w.box, in.dev_boxes ? 1 : 0, status);
@@ -424,33 +424,49 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
   for (int i = threadIdx.x; i < passes * R; i += blockDim.x) dst[i] = h[i];
 }
 
-// A batch: workgroups take chunk after chunk (at most kBboxChunk particles of one
-// set) and add each chunk's digit counts to its set's counts, set_counts[b][p][d].
+// A batch: workgroup g takes the particles [g N / G, (g + 1) N / G) of the whole
+// batch, which may span several sets (or part of one).  Its histogram is added
+// to the set's counts, set_counts[b][p][d], each time its range leaves a set, so
+// every workgroup has the same number of particles whatever the set sizes.
 template <int BITS>
 __global__ __launch_bounds__(kKeygenThreads) void k_keygen_sets(
-    const float *__restrict__ pos, const float *__restrict__ mass, const int64_t *__restrict__ set_off,
-    const int64_t *__restrict__ chunk_start, const int32_t *__restrict__ chunk_set,
-    int32_t nsets, const double *__restrict__ box, uint64_t *__restrict__ keys,
-    float4 *__restrict__ packed, uint32_t *__restrict__ set_counts, int passes, int hilbert,
-    int32_t *__restrict__ status_word) {
+    const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
+    const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
+    uint64_t *__restrict__ keys, float4 *__restrict__ packed, uint32_t *__restrict__ set_counts,
+    int passes, int hilbert, int32_t *__restrict__ status_word) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
+  constexpr int64_t kStep = (int64_t)kKeygenThreads * kKeygenIpt;
   __shared__ uint32_t h[MAXP * R];
+  __shared__ int s_b;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t g_lo = (int64_t)blockIdx.x * per;
+  const int64_t g_hi = min(n, g_lo + per);
+  if (g_lo >= g_hi) return;  // the same for the whole workgroup
+  // the set holding g_lo: the last b with set_off[b] <= g_lo (the offsets start
+  // at 0, end at n and never decrease)
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = nsets;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (set_off[mid] <= g_lo) lo = mid; else hi = mid;
+    }
+    s_b = lo;
+  }
+  for (int i = threadIdx.x; i < passes * R; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  int b = s_b;
   bool bad = false;
-  const int64_t n_chunks = chunk_start[nsets];
-  for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    const int b = chunk_set[c];
-    const int64_t c0 = set_off[b] + (c - chunk_start[b]) * (int64_t)kBboxChunk;
-    const int64_t c1 = min(c0 + (int64_t)kBboxChunk, set_off[b + 1]);
+  for (int64_t s0 = g_lo; s0 < g_hi;) {
+    while (b + 1 < nsets && set_off[b + 1] <= s0) ++b;  // past empty sets
+    const int64_t s1 = min(g_hi, max(s0 + 1, set_off[b + 1]));
     const double lo0 = box[4 * b + 0], lo1 = box[4 * b + 1], lo2 = box[4 * b + 2];
     const double scale = 2097152.0 / box[4 * b + 3];
-    for (int64_t i0 = c0 + threadIdx.x; i0 < c1; i0 += (int64_t)blockDim.x * kKeygenIpt) {
+    for (int64_t base = s0; base < s1; base += kStep) {
       float x[kKeygenIpt], y[kKeygenIpt], z[kKeygenIpt], m[kKeygenIpt];
 #pragma unroll
       for (int r = 0; r < kKeygenIpt; ++r) {
-        const int64_t i = min(i0 + (int64_t)r * blockDim.x, c1 - 1);
+        const int64_t i = min(base + r * kKeygenThreads + threadIdx.x, s1 - 1);
         x[r] = pos[3 * i + 0];
         y[r] = pos[3 * i + 1];
         z[r] = pos[3 * i + 2];
@@ -458,16 +474,22 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen_sets(
       }
 #pragma unroll
       for (int r = 0; r < kKeygenIpt; ++r) {
-        const int64_t i = i0 + (int64_t)r * blockDim.x;
-        key_one<BITS>(x[r], y[r], z[r], m[r], i < c1, i, lo0, lo1, lo2, scale, hilbert != 0,
+        const int64_t i = base + r * kKeygenThreads + threadIdx.x;
+        key_one<BITS>(x[r], y[r], z[r], m[r], i < s1, i, lo0, lo1, lo2, scale, hilbert != 0,
                       keys, packed, h, bad);
       }
     }
     __syncthreads();
     uint32_t *dst = set_counts + (int64_t)b * passes * R;
-    for (int i = threadIdx.x; i < passes * R; i += blockDim.x)
-      if (h[i]) atomicAdd(&dst[i], h[i]);
-    __syncthreads();  // h is cleared for the next chunk
+    for (int i = threadIdx.x; i < passes * R; i += blockDim.x) {
+      const uint32_t c = h[i];
+      if (c) {
+        atomicAdd(&dst[i], c);
+        h[i] = 0;  // cleared for the next set
+      }
+    }
+    __syncthreads();
+    s0 = s1;
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_NONFINITE);
 }
@@ -543,12 +565,12 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const f
     }
 #undef TB_KEYGEN
   } else {
-    int64_t blocks = p.bbox_chunks;
-    if (blocks > 2 * kKeygenMaxBlocks) blocks = 2 * kKeygenMaxBlocks;
+    // as many particles per workgroup as the single-set kernel at its largest grid
+    const int blocks = 2 * keygen_blocks(p.n);
 #define TB_KEYGEN_SETS(B)                                                                      \
   k_keygen_sets<B><<<(unsigned)blocks, kKeygenThreads, 0, s>>>(                                \
-      pos, mass, w.set_off, w.chunk_start, w.chunk_set, p.nsets, w.box, w.keys0, w.packed,     \
-      w.seg_base, passes, hil, out.status)
+      pos, mass, p.n, w.set_off, p.nsets, w.box, w.keys0, w.packed, w.seg_base, passes, hil,   \
+      out.status)
     switch (p.sort.bits) {
       case 8: TB_KEYGEN_SETS(8); break;
       case 9: TB_KEYGEN_SETS(9); break;
