@@ -82,6 +82,8 @@ def parse():
                          "timing the subtree-rooted cell build on the same data")
     ap.add_argument("--sort-counted", action="store_true",
                     help="count the tiles' digits in every radix pass (TB_SORT_COUNTED)")
+    ap.add_argument("--sort-lookback", action="store_true",
+                    help="keep the decoupled look-back in every radix pass (TB_SORT_LOOKBACK)")
     ap.add_argument("--curve", default="morton", choices=["morton", "hilbert"],
                     help="particle keys: Morton (default) or Peano-Hilbert (TB_HILBERT)")
     ap.add_argument("--subtrees", action="store_true",
@@ -348,12 +350,12 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: st
     compulsory traffic), per build.
 
     keygen      read pos 12 + mass 4; write key 8 + packed (x, y, z, m) record 16
-    sort_pass   pass 0 reads keys 8 (the payload is generated); a pass moves the key
-                as 8 bytes while its digit touches the low 32 bits, then as the upper
-                4 bytes; the last key pass writes no key; payload 4 read (after pass 0)
-                and written by every pass
-                (passes over 32-bit keys also read their keys a second time to count
-                their tiles' digits: 4 bytes a key, not counted here)
+    sort_pass   per pass, what its element format moves in and out (sort_forms):
+                key 8 + index 4 while the key is 64-bit (pass 0 reads the key alone:
+                its index is the position), then one packed word of 8 or 4 bytes;
+                the last pass writes the index alone, 4
+                (counted passes also read their elements a second time to count
+                their tiles' digits, not counted here)
     reorder     read perm 4 + gathered record 16; write the record in key order 16, its
                 key 8 and its (a_i, D_i) 2
     cell_emit   read sorted keys 8 + sorted records 16 + (a_i, D_i) 2 per particle; write
@@ -371,12 +373,11 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: st
     mom = 80 if precision == "fp64" else 44
     inner = cells - leaves
     bits = -(-63 // key_passes)  # digit width of these passes
+    forms = sort_forms(n, bits)
+    size = {"key64": 12, "pack64": 8, "pack32": 4, "idx": 4}
     sort = 0
     for p in range(key_passes):
-        kin = 8 if p * bits < 32 else 4
-        nxt = p + 1
-        kout = 0 if nxt >= key_passes else (8 if nxt * bits < 32 else 4)
-        sort += (kin + (4 if p else 0) + kout + 4) * n
+        sort += ((8 if p == 0 else size[forms[p]]) + size[forms[p + 1]]) * n
     return {
         "keygen": 40 * n,
         "sort_pass": sort,
@@ -386,6 +387,27 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: st
         "blocks": 9 * n,
         "block_build": 25 * n + (25 + mom) * cells,
     }
+
+
+def sort_forms(n: int, bits: int) -> list:
+    """Element format read by each radix pass, then the last pass's output, as
+    the library plans them: the index needs ib = bits(n - 1) bits; once the key
+    bits not yet consumed (with its leading 1) fit beside it in 64 or 32 bits,
+    key and index travel as one packed word."""
+    ib = max(1, (n - 1).bit_length())
+    passes = -(-63 // bits)
+    forms = ["key64"]
+    for k in range(passes):
+        rem = 64 - (k + 1) * bits  # key >> consumed bits, the leading 1 at bit 63 included
+        if k + 1 == passes:
+            forms.append("idx")
+        elif rem + ib <= 32:
+            forms.append("pack32")
+        elif rem + ib <= 64:
+            forms.append("pack64")
+        else:
+            forms.append("key64")
+    return forms
 
 
 def method_bytes(n: int, cells: int, key_passes: int, precision: str) -> float:
@@ -422,17 +444,26 @@ def kernels_table(trace, steps, alg):
     return out
 
 
-def roofline(trace, alg, key_passes, workload):
-    """Roofline entry of the dominant kernel (the sort's key passes)."""
+SORT_PASS_BYTES = 24  # the method's bytes per key and radix pass: (key 8 + index 4) in and out
+
+
+def roofline(trace, alg, key_passes, workload, n):
+    """Roofline entry of the dominant kernel (the sort's key passes).  achieved =
+    the method's algorithmic bytes of one pass (24 per key) / the mean pass
+    time; design_* = what this design's element formats move (less, as the
+    key narrows and is packed with its index)."""
     launches, total_ms = trace["sort_pass"]
     avg_ms = total_ms / launches
-    per_launch = alg["sort_pass"] / key_passes
+    per_launch = SORT_PASS_BYTES * n
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    r = {"kernel": "k_onesweep (radix pass over the key bits, one per digit; a counted pass over "
-                   "32-bit keys includes its k_tile_count and k_tile_scan)",
+    design = alg["sort_pass"] / key_passes
+    r = {"kernel": "k_onesweep (radix pass over the key bits, one per digit; a counted pass "
+                   "includes its k_tile_count and k_tile_scan)",
          "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
          "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-         "alg_bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 5)}
+         "alg_bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 5),
+         "design_bytes_per_launch": design,
+         "design_GBps": round(design / (avg_ms * 1e-3) / 1e9, 1)}
     prof = counter_traffic(workload)
     if prof is not None:
         k = prof["kernels"].get("sort_pass")
@@ -514,7 +545,7 @@ def run_single(args, tb, dg, torch, np):
     mass = torch.from_numpy(mass_np).to(dev)
     box = ((0.0, 0.0, 0.0), 1.0)
     b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=args.subtrees,
-                   counted=args.sort_counted, curve=args.curve)
+                   counted=args.sort_counted, lookback=args.sort_lookback, curve=args.curve)
     run = lambda: b.launch(pos, mass, box)
     sec = time_steps(run, args.steps, args.warmup)
     print(f"[bench] {args.steps} builds, {sec * 1e3:.3f} ms/build", file=sys.stderr, flush=True)
@@ -536,8 +567,9 @@ def run_single(args, tb, dg, torch, np):
                    "sort_config": list(tb.tb_sort_configs()[k]), "cells": cells,
                    "leaves": leaves,
                    "cell_build": "subtree-rooted blocks" if args.subtrees else "tiles + parents",
-                   "sort_counted_all_passes": bool(args.sort_counted), "keys": args.curve},
-        "roofline": roofline(trace, alg, key_passes, args.workload),
+                   "sort_counted_all_passes": bool(args.sort_counted),
+                   "sort_lookback_all_passes": bool(args.sort_lookback), "keys": args.curve},
+        "roofline": roofline(trace, alg, key_passes, args.workload, n),
         "build_method_bytes": total_method,
         "build_alg_GBps": round(total_method / sec / 1e9, 1),
         "build_alg_frac": round(total_method / sec / 1e9 / HBM_PEAK_GBPS, 4),
@@ -548,7 +580,8 @@ def run_single(args, tb, dg, torch, np):
     if not args.no_compare:
         # the other cell build on the same data (the tree is the same either way)
         alt_b = tb.Builder(n, n_leaf, precision, k, dev, subtrees=not args.subtrees,
-                           counted=args.sort_counted, curve=args.curve)
+                           counted=args.sort_counted, lookback=args.sort_lookback,
+                           curve=args.curve)
         alt_run = lambda: alt_b.launch(pos, mass, box)
         sec_alt = time_steps(alt_run, args.steps, args.warmup)
         alt = alt_b.result()
@@ -626,7 +659,7 @@ def run_batched(args, tb, dg, torch, np):
                    "n_leaf": n_leaf, "precision": precision, "box": "unit cube per set",
                    "sort_config": list(tb.tb_sort_configs()[k]), "autotune_s": round(tune_s, 2),
                    "cells": cells, "leaves": leaves, "launch": "one HIP graph per batch"},
-        "roofline": roofline(trace, alg, key_passes, "batched4096"),
+        "roofline": roofline(trace, alg, key_passes, "batched4096", n),
         "build_method_bytes": total_method,
         "build_alg_GBps": round(total_method / sec / 1e9, 1),
         "build_alg_frac": round(total_method / sec / 1e9 / HBM_PEAK_GBPS, 4),

@@ -96,16 +96,17 @@ extern "C" {
  * results; only speed and workspace size differ. */
 #define TB_SORT_CONFIG(k) (((uint32_t)(k)&0xffu) << 8)
 
-/* Radix passes over the upper 32 key bits normally take their tile offsets
- * from a separate count of every tile's digits (one more read of 4 bytes a
- * key) when the sort has at most 4096 tiles, and from the decoupled look-back
- * across tiles otherwise.  This flag keeps the look-back in every pass.
- * Results are bit-identical either way; the flag exists for tuning and tests. */
+/* The radix passes of a single set normally take their tile offsets from a
+ * separate count of every tile's digits (one more read of the pass's elements,
+ * 8 or 4 bytes each) when the sort has at most 4096 tiles, and from the
+ * decoupled look-back across tiles otherwise (and always in a batch).  This
+ * flag keeps the look-back in every pass.  Results are bit-identical either
+ * way; the flag exists for tuning and tests. */
 #define TB_SORT_LOOKBACK (1u << 17)
 
-/* Count the tiles' digits in every key pass, the passes over the low 32 key
- * bits too (they re-read 8 bytes a key), when the sort has at most 4096 tiles.
- * Not with TB_SORT_LOOKBACK (TB_ERR_ARG).  Results are bit-identical. */
+/* Count the tiles' digits in every radix pass of a single set whatever the
+ * number of tiles (batches keep the look-back).  Not with TB_SORT_LOOKBACK
+ * (TB_ERR_ARG).  Results are bit-identical. */
 #define TB_SORT_COUNTED (1u << 19)
 
 /* Build the cells subtree by subtree (Sec. 2.3.3, eq. 2): the sorted keys are

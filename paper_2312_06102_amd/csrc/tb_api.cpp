@@ -45,18 +45,38 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->seg = nsets > 1;
   // each set starts a tile of its own
   p->sort_tiles = (n + sc.tile() - 1) / sc.tile() + (p->seg ? nsets : 0);
-  // On grids of up to kCountedMaxTiles tiles, passes over 32-bit keys count
-  // their tiles' digits in a separate read (4 bytes a key) instead of chaining
-  // the tiles through the look-back.  The extra read grows with N while the
-  // look-back's cost does not: measured faster at N = 2^24 (2979 tiles), much
-  // slower at 1.6e8 keys (28K tiles).
-  // TB_SORT_COUNTED counts every key pass (a 64-bit pass re-reads 8 bytes a key).
-  // A batch keeps the look-back in every pass: its tiles' offsets restart at
-  // every set.
+  // Element formats.  The index needs idx_bits bits; once the key bits still to
+  // be sorted fit beside it in 64 (or 32) bits, key and index travel as one
+  // packed word, so every later pass moves 8 (or 4) bytes an element in and out
+  // instead of 12.  With 8-bit digits and N = 2^24 the third pass writes 40 key
+  // bits + 24 index bits in 8 bytes, and the seventh 8 + 24 bits in 4.
+  p->idx_bits = 1;
+  while (p->idx_bits < 32 && (int64_t{1} << p->idx_bits) < n) ++p->idx_bits;
+  // The leading 1 at bit 63 stays in the word (the key kernel's counts of the
+  // last 8-bit digit include it), so key >> consumed bits keeps 64 - consumed bits.
+  p->form[0] = kFormKey64;
+  for (int k = 0; k < p->key_passes; ++k) {
+    const int rem = 64 - (k + 1) * sc.bits;  // bits of key >> consumed bits after pass k
+    if (k + 1 == p->key_passes)
+      p->form[k + 1] = kFormIdx;
+    else if (rem + p->idx_bits <= 32)
+      p->form[k + 1] = kFormPack32;
+    else if (rem + p->idx_bits <= 64)
+      p->form[k + 1] = kFormPack64;
+    else
+      p->form[k + 1] = kFormKey64;
+  }
+  // On grids of up to kCountedMaxTiles tiles every pass counts its tiles' digits
+  // in a separate read of its elements (8 or 4 bytes each) instead of chaining
+  // the tiles through the look-back: measured faster at N = 2^24 (2979 tiles:
+  // 831 against 856 us for the eight passes).  The extra read grows with N while
+  // the look-back's cost does not, so larger grids look back unless
+  // TB_SORT_COUNTED asks for counting.  A batch keeps the look-back in every
+  // pass: its tiles' offsets restart at every set.
   p->counted = 0;
-  if (!p->seg && p->sort_tiles <= kCountedMaxTiles && !(flags & TB_SORT_LOOKBACK))
-    for (int k = 0; k < p->key_passes; ++k)
-      if (k * sc.bits >= 32 || (flags & TB_SORT_COUNTED)) p->counted |= 1u << k;
+  if (!p->seg && !(flags & TB_SORT_LOOKBACK) &&
+      ((flags & TB_SORT_COUNTED) || p->sort_tiles <= kCountedMaxTiles))
+    p->counted = (1u << p->key_passes) - 1u;
   // tiles never straddle two sets: at most one partial tile per set
   p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;
   // chunks of at most kBboxChunk particles of one set: the auto box works chunk

@@ -62,6 +62,17 @@ struct SortConfig {
   int passes() const { return (63 + bits - 1) / bits; }  // bit 63 is always 1
 };
 
+// What one radix pass reads or writes per element.  The index is the element's
+// position before the sort (perm after the last pass); a packed element holds the
+// key bits later passes still need above the index bits.
+enum SortForm : uint8_t {
+  kFormIdx = 0,     // the index alone (the last pass's output)
+  kFormKey64 = 2,   // the 64-bit key, with the index in a separate u32 array
+  kFormPack64 = 3,  // (key >> consumed bits) << idx_bits | index, in 64 bits
+  kFormPack32 = 4,  // the same in 32 bits
+};
+constexpr int kMaxKeyPasses = 8;
+
 // Workspace plan: byte offsets of every scratch array inside the caller's
 // workspace, all 256-byte aligned.
 struct Plan {
@@ -72,6 +83,8 @@ struct Plan {
   SortConfig sort;
   int key_passes;   // radix passes over the 63 key bits
   uint32_t counted; // bit k: key pass k takes its tile offsets from a count and a scan
+  int idx_bits;     // bits of the largest index, n - 1 (at least 1)
+  uint8_t form[kMaxKeyPasses + 1];  // form[k]: what pass k reads; form[k + 1]: what it writes
   bool seg;         // batch of several sets: every radix pass sorts each set in place
                     // (tiles never straddle a set; each set has its own digit bases)
   int64_t sort_tiles;
@@ -80,7 +93,7 @@ struct Plan {
   int64_t c_max;
   int64_t upper_cap;    // cells above the blocks, per depth: at most n / (n_serial + 1) + B
   // offsets
-  size_t keys0, keys1;  // u64 [n] ping-pong key buffers
+  size_t keys0, keys1;  // u64 [n] ping-pong buffers of keys or packed words
   size_t vals1;         // u32 [n] payload buffer (the other one is out->perm)
   size_t hist;          // u32 [key_passes][radix] global digit counts (single set)
   size_t hist_part;     // u32 [keygen blocks][key_passes][radix] per-workgroup counts

@@ -16,11 +16,11 @@
 // The global digit counts come from the key-generation pass, so the keys are
 // read only once per pass.  The index payload of the last pass is `perm`.
 //
-// On small grids (see kCountedMaxTiles) passes over 32-bit keys are "counted"
-// instead (reduce, then scan): a first kernel reads only the keys and writes
-// every tile's digit counts, a second turns them into exclusive prefixes over
-// the tiles, and the scatter kernel reads its tile's offsets instead of waiting
-// on its predecessors.  There, reading 4 bytes a key again costs less than the
+// On small grids (see kCountedMaxTiles) the passes are "counted" instead
+// (reduce, then scan): a first kernel reads only the elements and writes every
+// tile's digit counts, a second turns them into exclusive prefixes over the
+// tiles, and the scatter kernel reads its tile's offsets instead of waiting on
+// its predecessors.  There, reading the elements again costs less than the
 // look-back chain across the chip; TB_SORT_LOOKBACK keeps the look-back.
 //
 // A batch sorts every set in place: a set's tiles never straddle it, its tiles'
@@ -28,12 +28,13 @@
 // bases taken from its own digit counts (counted per set by the key kernel).
 // The passes thus give the (set, key) order with no pass over the set id.
 //
-// Key width shrinks as the passes go: a pass carries only the key bits later
-// passes still need.  Passes whose digit lies (partly) in the low 32 bits read
-// the 64-bit key; once those bits are consumed the key travels as its upper 32
-// bits, and the last pass writes no key at all.  The sorted keys themselves are
-// recomputed from the sorted particles in the reorder pass, which reads those
-// particles anyway.
+// Elements shrink as the passes go: a pass carries only the key bits later
+// passes still need.  The first passes move the 64-bit key and the index in two
+// arrays (12 bytes); once the key bits left fit beside the index in 64 or 32
+// bits, both travel as one packed word, (key >> consumed bits) << idx_bits |
+// index, whose digit is read at bit idx_bits.  The last pass writes the index
+// alone.  The sorted keys themselves are recomputed from the sorted particles in
+// the reorder pass, which reads those particles anyway.
 #include "tb_internal.h"
 
 namespace tb {
@@ -58,20 +59,22 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t *s_
   return off + inc - v;
 }
 
-// Key storage of a pass: the full 64-bit key, its upper 32 bits, or nothing.
-enum KeyWidth { kKeyNone = 0, kKey32 = 1, kKey64 = 2 };
-
-template <int W>
-struct KeyType {
+// Word type of an element format (kFormIdx and kFormPack32: 32-bit words).
+template <int F>
+struct FormType {
   using T = uint32_t;
 };
 template <>
-struct KeyType<kKey64> {
+struct FormType<kFormKey64> {
+  using T = uint64_t;
+};
+template <>
+struct FormType<kFormPack64> {
   using T = uint64_t;
 };
 
-// Digit at bit offset `shift` (uniform) of a key stored with width W (for
-// kKey32 the shift is already relative to bit 32).
+// Digit at bit offset `shift` (uniform): the pass's digit position for a 64-bit
+// key, idx_bits for a packed element.
 template <int BITS>
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
   const uint32_t lo = (uint32_t)k, hi = (uint32_t)(k >> 32);
@@ -84,15 +87,14 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
   return (k >> shift) & ((1u << BITS) - 1u);
 }
 
-// KIN / KOUT: key width read / written.
-// Digit counts of one tile of a counted pass: tile t (the keys [t TILE,
+// Digit counts of one tile of a counted pass: tile t (the elements [t TILE,
 // (t + 1) TILE), as the scatter kernel tiles them) writes cnt[d][t].
-template <int BITS, int IPT, int THREADS, int KIN>
+template <int BITS, int IPT, int THREADS, int FIN>
 __global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__ kin_v,
                                                         uint32_t n, int shift,
                                                         uint32_t *__restrict__ cnt,
                                                         uint32_t n_tiles) {
-  using KI = typename KeyType<KIN>::T;
+  using KI = typename FormType<FIN>::T;
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
   constexpr uint32_t TILE = (uint32_t)THREADS * IPT;
@@ -166,28 +168,34 @@ struct SegTiles {
   int32_t nsets;
 };
 
+// FIN / FOUT: element format read / written (FIN is never kFormIdx).  kin/kout
+// hold the key or packed words; vin/vout the separate index of kFormKey64 (vin
+// NULL: the index is the position) and the output of kFormIdx.  shift: the
+// digit's bit offset in the input word; ib: idx_bits.
 // hist: single set, the pass's global digit counts [radix]; batch, the pass's
 // row of each set's digit bases (set b at b * base_stride).
-template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED, bool SEG>
+template <int BITS, int IPT, int THREADS, int FIN, int FOUT, bool COUNTED, bool SEG>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const void *__restrict__ kin_v, void *__restrict__ kout_v,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
-    const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
+    int ib, const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
     const uint32_t *__restrict__ tile_off, int32_t *__restrict__ status_word, uint32_t n_tiles,
     SegTiles seg) {
-  using KI = typename KeyType<KIN>::T;
-  using KO = typename KeyType<KOUT == kKeyNone ? kKey32 : KOUT>::T;
+  using KI = typename FormType<FIN>::T;
+  using KO = typename FormType<FOUT>::T;
+  constexpr bool PIN = FIN != kFormKey64;  // packed input: the index is in the word
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
   constexpr int TILE = THREADS * IPT;
   constexpr int DPT = (R + THREADS - 1) / THREADS;  // digits per thread
-  // the local sort keeps the input key (when a key is written), or else the
-  // digit of each slot
-  constexpr int SLOT_BYTES = KOUT == kKeyNone ? 2 : (int)sizeof(KI);
+  // the local sort keeps the input word, except where only a separate index is
+  // written: there the digit of each slot suffices
+  constexpr bool SLOT_DIGIT = FOUT == kFormIdx && !PIN;
+  constexpr int SLOT_BYTES = SLOT_DIGIT ? 2 : (int)sizeof(KI);
 
   __shared__ __align__(16) unsigned char s_slot[TILE * SLOT_BYTES];
-  __shared__ uint32_t s_vals[TILE];
+  __shared__ uint32_t s_vals[PIN ? 1 : TILE];
   __shared__ uint32_t s_wc[WAVES * R];     // per-wave digit counters, then wave offsets
   __shared__ uint32_t s_tstart[R];         // tile-local start of each digit
   __shared__ int32_t s_goff[R];            // output position minus tile-local position
@@ -246,12 +254,14 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   const uint32_t wbase = lo + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, last)];
-  if (vin) {
+  if constexpr (!PIN) {
+    if (vin) {
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, last)];
-  } else {
+      for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, last)];
+    } else {
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
+      for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
+    }
   }
 #pragma unroll
   for (int j = 0; j < IPT; ++j) dg[j] = digit_of<BITS>(k[j], shift);
@@ -338,11 +348,11 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     if (wbase + j * 64 <= last) {
       const uint32_t d = dg[j];
       const uint32_t p = s_tstart[d] + wc[d] + rk[j];
-      if constexpr (KOUT == kKeyNone)
+      if constexpr (SLOT_DIGIT)
         reinterpret_cast<uint16_t *>(s_slot)[p] = (uint16_t)d;
       else
         reinterpret_cast<KI *>(s_slot)[p] = k[j];
-      s_vals[p] = v[j];
+      if constexpr (!PIN) s_vals[p] = v[j];
     }
   }
   // the next pass's look-back words for this tile start cleared
@@ -371,51 +381,51 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   // coalesced scatter: consecutive lanes write consecutive slots of a digit run,
   // inside the tile's set [set_lo, hi)
   bool bad = false;
+  const uint32_t idx_mask = ib >= 32 ? 0xffffffffu : (1u << ib) - 1u;
   for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
     uint32_t d;
-    KO key = 0;
-    if constexpr (KOUT == kKeyNone) {
+    KI kk = 0;
+    if constexpr (SLOT_DIGIT) {
       d = reinterpret_cast<const uint16_t *>(s_slot)[i];
     } else {
-      const KI kk = reinterpret_cast<const KI *>(s_slot)[i];
+      kk = reinterpret_cast<const KI *>(s_slot)[i];
       d = digit_of<BITS>(kk, shift);
-      // a 64-bit key keeps only its upper half once its low bits are consumed
-      key = (KIN == kKey64 && KOUT == kKey32) ? (KO)((uint64_t)kk >> 32) : (KO)kk;
     }
+    const uint32_t idx = PIN ? ((uint32_t)kk & idx_mask) : s_vals[i];
     const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
     if (gp < set_lo || gp >= hi) {  // cannot happen with consistent digit counts
       bad = true;
       continue;
     }
-    if constexpr (KOUT != kKeyNone) kout[gp] = key;
-    vout[gp] = s_vals[i];
+    if constexpr (FOUT == kFormIdx) {
+      vout[gp] = idx;
+    } else if constexpr (FOUT == kFormKey64) {
+      kout[gp] = (KO)kk;
+      vout[gp] = idx;
+    } else {
+      // the key bits above this digit, moved down to sit above the index
+      const uint64_t rest = (uint64_t)kk >> (shift + BITS);
+      kout[gp] = (KO)((rest << ib) | idx);
+    }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
-// Key widths of pass `pass`: a key pass whose digit starts below bit 32 reads
-// the 64-bit key; later key passes read the upper 32 bits.  A pass writes what
-// the next pass reads; the last writes no key.
-static int key_in(const Plan &p, int pass) { return pass * p.sort.bits < 32 ? kKey64 : kKey32; }
-static int key_out(const Plan &p, int pass) {
-  return pass + 1 < p.key_passes ? key_in(p, pass + 1) : kKeyNone;
-}
-
-template <int BITS, int IPT, int THREADS, int KIN, int KOUT, bool COUNTED>
+template <int BITS, int IPT, int THREADS, int FIN, int FOUT, bool COUNTED>
 static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
   const int P = p.key_passes;
   void *K[2] = {w.keys0, w.keys1};
-  // the last pass must write its payload into out.perm
+  // the last pass must write its index into out.perm
   uint32_t *V[2];
   V[P % 2] = reinterpret_cast<uint32_t *>(out.perm);
   V[(P + 1) % 2] = w.vals1;
   uint64_t *S[2] = {w.status0, w.status1};
-  const uint32_t *vin = pass == 0 ? nullptr : V[pass % 2];
+  const uint32_t *vin = (pass == 0 || FIN != kFormKey64) ? nullptr : V[pass % 2];
   const int R = 1 << BITS;
-  const int shift = pass * BITS - (KIN == kKey32 ? 32 : 0);
+  const int shift = FIN == kFormKey64 ? pass * BITS : p.idx_bits;
   if constexpr (COUNTED) {
-    k_tile_count<BITS, IPT, THREADS, KIN><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
+    k_tile_count<BITS, IPT, THREADS, FIN><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
         K[pass % 2], (uint32_t)p.n, shift, w.tile_off, (uint32_t)p.sort_tiles);
     k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
   }
@@ -426,34 +436,41 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
                    p.nsets};
     hist = w.seg_base + (size_t)pass * R;
   }
-  auto k = p.seg ? k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED, true>
-                 : k_onesweep<BITS, IPT, THREADS, KIN, KOUT, COUNTED, false>;
+  auto k = p.seg ? k_onesweep<BITS, IPT, THREADS, FIN, FOUT, COUNTED, true>
+                 : k_onesweep<BITS, IPT, THREADS, FIN, FOUT, COUNTED, false>;
   k<<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
-      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift, hist,
-      S[pass % 2], S[(pass + 1) % 2], w.counters + pass, w.tile_off, out.status,
+      K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift, p.idx_bits,
+      hist, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, w.tile_off, out.status,
       (uint32_t)p.sort_tiles, seg);
   return hipGetLastError();
 }
 
+template <int BITS, int IPT, int THREADS, int FIN, int FOUT>
+static hipError_t launch_pass_c(const Plan &p, const Work &w, int pass, const tb_tree &out,
+                                hipStream_t s) {
+  return ((p.counted >> pass) & 1u)
+             ? launch_pass_k<BITS, IPT, THREADS, FIN, FOUT, true>(p, w, pass, out, s)
+             : launch_pass_k<BITS, IPT, THREADS, FIN, FOUT, false>(p, w, pass, out, s);
+}
+
+// The format pairs make_plan produces for 8- and 9-bit digits and any N below
+// 2^32 (a 64-bit key is packed by the time 32 of its bits are consumed, since the
+// 32 bits left and at most 32 index bits fit in 64).
 template <int BITS, int IPT, int THREADS>
 static hipError_t launch_pass_t(const Plan &p, const Work &w, int pass, const tb_tree &out,
                                 hipStream_t s) {
-  const int ki = key_in(p, pass), ko = key_out(p, pass);
-  const bool counted = (p.counted >> pass) & 1u;
-  if (ki == kKey64 && ko == kKey64)
-    return counted ? launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64, true>(p, w, pass, out, s)
-                   : launch_pass_k<BITS, IPT, THREADS, kKey64, kKey64, false>(p, w, pass, out, s);
-  if (ki == kKey64 && ko == kKey32)
-    return counted ? launch_pass_k<BITS, IPT, THREADS, kKey64, kKey32, true>(p, w, pass, out, s)
-                   : launch_pass_k<BITS, IPT, THREADS, kKey64, kKey32, false>(p, w, pass, out, s);
-  if (ki == kKey32 && ko == kKey32)
-    return counted ? launch_pass_k<BITS, IPT, THREADS, kKey32, kKey32, true>(p, w, pass, out, s)
-                   : launch_pass_k<BITS, IPT, THREADS, kKey32, kKey32, false>(p, w, pass, out, s);
-  if (ki == kKey32 && ko == kKeyNone)
-    return counted
-               ? launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone, true>(p, w, pass, out, s)
-               : launch_pass_k<BITS, IPT, THREADS, kKey32, kKeyNone, false>(p, w, pass, out, s);
-  return hipErrorInvalidValue;  // no other combination arises for 8- or 9-bit digits
+  const int fi = p.form[pass], fo = p.form[pass + 1];
+#define TB_PAIR(FI, FO) \
+  if (fi == FI && fo == FO) return launch_pass_c<BITS, IPT, THREADS, FI, FO>(p, w, pass, out, s);
+  TB_PAIR(kFormKey64, kFormKey64)
+  TB_PAIR(kFormKey64, kFormPack64)
+  TB_PAIR(kFormPack64, kFormPack64)
+  TB_PAIR(kFormPack64, kFormPack32)
+  TB_PAIR(kFormPack64, kFormIdx)
+  TB_PAIR(kFormPack32, kFormPack32)
+  TB_PAIR(kFormPack32, kFormIdx)
+#undef TB_PAIR
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_sort_pass(const Plan &p, const Work &w, int pass, const tb_tree &out,

@@ -269,9 +269,9 @@ def test_mixed_nonunit_box_and_duplicates():
 # --------------------------------------------------------------------------
 
 def test_every_sort_config_identical():
-    """Every sort shape, with the passes over 32-bit keys counted (the default on
-    small grids), with the look-back kept in every pass and with every pass
-    counted, gives the same tree."""
+    """Every sort shape, with its default passes (counted on small grids), with
+    the look-back kept in every pass and with counting forced, gives the same
+    tree."""
     pos, mass = dg.plummer(150000, seed=9)
     o = oracle.build(pos, mass, 16)
     ref = None

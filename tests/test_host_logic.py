@@ -38,16 +38,81 @@ def test_autotune_cache_tolerates_damage(tmp_path):
     assert autotune.lookup(1000, 1, 16, path=str(path)) is None
 
 
-def test_sort_bytes_follow_key_widths():
-    n = 1 << 20
+def test_sort_bytes_follow_element_formats():
+    n = 1 << 24
+    assert bench.sort_forms(n, 8) == ["key64", "key64", "key64", "pack64", "pack64", "pack64",
+                                      "pack64", "pack32", "idx"]
     b8 = bench.kernel_bytes(n, 0, 0, 8, "fp64")["sort_pass"] / n
-    # passes 0..3 read 64-bit keys (pass 3 writes their upper halves), passes
-    # 4..6 move 32-bit keys, the last writes no key; payload 4 B in and out
-    assert b8 == (8 + 0 + 8 + 4) + 2 * (8 + 4 + 8 + 4) + (8 + 4 + 4 + 4) + 2 * (4 + 4 + 4 + 4) \
-        + (4 + 4 + 4 + 4) + (4 + 4 + 0 + 4)
-    b9 = bench.kernel_bytes(n, 0, 0, 7, "fp64")["sort_pass"] / n
-    assert b9 == (8 + 0 + 8 + 4) + 2 * (8 + 4 + 8 + 4) + (8 + 4 + 4 + 4) + 2 * (4 + 4 + 4 + 4) \
-        + (4 + 4 + 0 + 4)
+    # pass 0 reads the key alone; key + index (12) until 40 key bits (the
+    # leading 1 included) + 24 index bits fit in 8 bytes; 8 + 24 bits fit in 4;
+    # the last pass writes the index
+    assert b8 == (8 + 12) + (12 + 12) + (12 + 8) + 3 * (8 + 8) + (8 + 4) + (4 + 4)
+    # 2^26 elements: 40 + 26 bits do not fit in 64, 8 + 26 not in 32
+    assert bench.sort_forms(1 << 26, 8) == ["key64"] * 4 + ["pack64"] * 4 + ["idx"]
+    # 9-bit digits: 37 + 24 bits fit after the third pass; 10 + 24 never fit in 32
+    assert bench.sort_forms(1 << 24, 9) == ["key64"] * 3 + ["pack64"] * 4 + ["idx"]
+
+
+SUPPORTED_PAIRS = {("key64", "key64"), ("key64", "pack64"), ("pack64", "pack64"),
+                   ("pack64", "pack32"), ("pack64", "idx"), ("pack32", "pack32"),
+                   ("pack32", "idx")}
+
+
+def test_sort_form_pairs_are_the_instantiated_ones():
+    """Every (read, write) pair the plan can produce for 8- and 9-bit digits is
+    one the radix pass is built for."""
+    sizes = {1, 2, 3}
+    for b in range(1, 32):
+        sizes |= {(1 << b) - 1, 1 << b, (1 << b) + 1}
+    for bits in (8, 9):
+        for n in sorted(sizes):
+            f = bench.sort_forms(n, bits)
+            for pair in zip(f[:-1], f[1:]):
+                assert pair in SUPPORTED_PAIRS, (n, bits, f)
+
+
+def _emulate_packed_sort(keys, bits, ib):
+    """The radix passes as the kernels compute them: digit at bit k*bits of a
+    64-bit key or at bit ib of a packed word; a packed word is written as
+    (word >> (shift + bits)) << ib | index, truncated to its width.  Every
+    pass's digit must be the key's digit k (what the key kernel counted for the
+    global digit offsets)."""
+    n = keys.shape[0]
+    forms = bench.sort_forms(1 << ib, bits)
+    mask = np.uint64((1 << ib) - 1)
+    dmask = np.uint64((1 << bits) - 1)
+    words, idx = keys.copy(), np.arange(n, dtype=np.uint64)
+    for k in range(len(forms) - 1):
+        fi, fo = forms[k], forms[k + 1]
+        shift = k * bits if fi == "key64" else ib
+        if fi != "key64":
+            idx = words & mask
+        d = (words >> np.uint64(shift)) & dmask
+        assert np.array_equal(d, (keys[idx.astype(np.int64)] >> np.uint64(k * bits)) & dmask), \
+            (k, fi)
+        order = np.argsort(d, kind="stable")
+        words, idx = words[order], idx[order]
+        if fo in ("pack64", "pack32"):
+            words = ((words >> np.uint64(shift + bits)) << np.uint64(ib)) | idx
+            if fo == "pack32":
+                words &= np.uint64(0xFFFFFFFF)
+    return idx
+
+
+@pytest.mark.parametrize("bits", [8, 9])
+@pytest.mark.parametrize("ib", [1, 2, 7, 12, 23, 24, 25, 26, 28, 31])
+def test_packed_passes_sort_stably(bits, ib):
+    rng = np.random.default_rng(ib * 10 + bits)
+    n = min(4000, 1 << ib)  # the indices fit in ib bits
+    body = rng.integers(0, 1 << 63, n, dtype=np.uint64)
+    # duplicates and keys that differ only in the lowest or highest bits
+    body[::7] = body[1::7][: body[::7].shape[0]]
+    body[3::11] ^= np.uint64(1)
+    body[5::13] ^= np.uint64(1 << 62)
+    keys = body | np.uint64(1 << 63)
+    got = _emulate_packed_sort(keys, bits, ib)
+    want = np.argsort(keys, kind="stable")
+    assert np.array_equal(got, want.astype(np.uint64))
 
 
 def test_method_bytes_model():
