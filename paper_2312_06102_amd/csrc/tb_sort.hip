@@ -168,12 +168,205 @@ struct SegTiles {
   int32_t nsets;
 };
 
-// FIN / FOUT: element format read / written (FIN is never kFormIdx).  kin/kout
-// hold the key or packed words; vin/vout the separate index of kFormKey64 (vin
-// NULL: the index is the position) and the output of kFormIdx.  shift: the
-// digit's bit offset in the input word; ib: idx_bits.
-// hist: single set, the pass's global digit counts [radix]; batch, the pass's
-// row of each set's digit bases (set b at b * base_stride).
+// All ones if bit b of d is set, else zero: one signed one-bit field extract
+// (the compiler would otherwise shift left and then arithmetically right).
+__device__ __forceinline__ uint32_t lane_bit_mask(uint32_t d, int b) {
+  uint32_t m;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(d), "i"(b));
+  return m;
+}
+
+// Shape and LDS of one radix tile.  FIN / FOUT: element format read / written
+// (FIN is never kFormIdx).
+template <int BITS, int IPT, int THREADS, int FIN, int FOUT>
+struct Sweep {
+  using KI = typename FormType<FIN>::T;
+  using KO = typename FormType<FOUT>::T;
+  static constexpr bool PIN = FIN != kFormKey64;  // packed input: the index is in the word
+  static constexpr int R = 1 << BITS;
+  static constexpr int WAVES = THREADS / 64;
+  static constexpr int TILE = THREADS * IPT;
+  static constexpr int DPT = (R + THREADS - 1) / THREADS;  // digits per thread
+  // the local sort keeps the input word, except where only a separate index is
+  // written: there the digit of each slot suffices
+  static constexpr bool SLOT_DIGIT = FOUT == kFormIdx && !PIN;
+  static constexpr int SLOT_BYTES = SLOT_DIGIT ? 2 : (int)sizeof(KI);
+  struct Lds {
+    alignas(16) unsigned char slot[TILE * SLOT_BYTES];
+    uint32_t vals[PIN ? 1 : TILE];
+    uint32_t wc[WAVES * R];   // per-wave digit counters, then wave offsets
+    uint32_t tstart[R];       // tile-local start of each digit
+    int32_t goff[R];          // output position minus tile-local position
+    uint32_t tmp[WAVES];
+    uint32_t tile;
+  };
+};
+
+// Wave-striped load of a tile: item j of lane l is element wbase + j*64, with
+// wbase = lo + wave*64*IPT + l.  Loads are branch-free (indices past the tile
+// are clamped and the items masked later) so that all of them are in flight
+// together.  v: the separate index of kFormKey64 (the position when vin is NULL).
+template <class S, int IPT>
+__device__ __forceinline__ void sweep_load(const typename S::KI *__restrict__ kin,
+                                           const uint32_t *__restrict__ vin, uint32_t wbase,
+                                           uint32_t last, typename S::KI (&k)[IPT],
+                                           uint32_t (&v)[IPT]) {
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, last)];
+  if constexpr (!S::PIN) {
+    if (vin) {
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, last)];
+    } else {
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
+    }
+  }
+}
+
+// Ranks a loaded tile and sorts it by digit in LDS.  On entry L.wc is zero
+// (behind a barrier).  On return, for each digit d = threadIdx.x * DPT + t:
+// tcnt[t] its count in the tile and trun[t] its tile-local start; with PUBLISH
+// the tile's per-digit counts are also published for the look-back (inclusive
+// when it is the first tile of its set).
+template <class S, int BITS, int IPT, int THREADS, bool PUBLISH>
+__device__ __forceinline__ void sweep_rank(typename S::Lds &L, const typename S::KI (&k)[IPT],
+                                           const uint32_t (&v)[IPT], uint32_t wbase,
+                                           uint32_t last, int shift, uint64_t *status,
+                                           uint32_t tile, bool first, uint32_t (&tcnt)[S::DPT],
+                                           uint32_t (&trun_d)[S::DPT]) {
+  constexpr int R = S::R, WAVES = S::WAVES, DPT = S::DPT;
+  const int wv = threadIdx.x / 64;
+  const uint64_t lt = lanemask_lt();
+  uint32_t dg[IPT], rk[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) dg[j] = digit_of<BITS>(k[j], shift);
+
+  // Stable wave-level ranking: for every digit bit a ballot; XNOR-ing the
+  // ballot with "all ones if my bit is set" keeps exactly the lanes that agree
+  // with me on that bit, so the AND over all bits is the set of lanes holding
+  // my digit.  Its population below my lane is my rank among them.  (The mask
+  // is a signed one-bit field extract, which also feeds the ballot, and each
+  // half of the AND is one three-input bit operation: four instructions a bit.
+  // The operation's table is indexed by (a, b, c) bits as a*4 + b*2 + c, so
+  // a & ~(b ^ c) is 0xF0 & ~(0xCC ^ 0xAA) = 0x90.)
+  uint32_t *wc = L.wc + wv * R;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const bool valid = wbase + j * 64 <= last;
+    const uint32_t d = dg[j];
+    const uint64_t vmask = __ballot(valid);
+    uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+      const uint32_t m = lane_bit_mask(d, b);  // bit b set: all ones
+      const uint64_t bb = __ballot(m != 0u);
+      plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)bb, m, 0x90);
+      phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(bb >> 32), m, 0x90);
+    }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
+    const uint32_t pre = (uint32_t)__popcll(peers & lt);
+    uint32_t cnt = 0;
+    if (valid) cnt = wc[d];
+    rk[j] = cnt + pre;
+    if (valid && pre == 0) wc[d] = cnt + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+
+  // per digit: exclusive offsets across waves and the tile count
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    uint32_t run = 0;
+    if (d < R) {
+#pragma unroll
+      for (int q = 0; q < WAVES; ++q) {
+        const uint32_t c = L.wc[q * R + d];
+        L.wc[q * R + d] = run;
+        run += c;
+      }
+      if constexpr (PUBLISH)
+        atomic_store_agent(&status[(size_t)tile * R + d],
+                           (first ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
+    }
+    tcnt[t] = run;
+  }
+
+  // tile-local digit starts: a block scan over the digits
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) tsum += tcnt[t];
+  uint32_t dummy;
+  uint32_t trun = block_exclusive_sum<THREADS>(tsum, L.tmp, &dummy);
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) {
+    const int d = threadIdx.x * DPT + t;
+    if (d < R) L.tstart[d] = trun;
+    trun_d[t] = trun;
+    trun += tcnt[t];
+  }
+  __syncthreads();
+
+  // sort the tile by digit in LDS (the input word, or the digit where only a
+  // separate index is written)
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if (wbase + j * 64 <= last) {
+      const uint32_t d = dg[j];
+      const uint32_t p = L.tstart[d] + wc[d] + rk[j];
+      if constexpr (S::SLOT_DIGIT)
+        reinterpret_cast<uint16_t *>(L.slot)[p] = (uint16_t)d;
+      else
+        reinterpret_cast<typename S::KI *>(L.slot)[p] = k[j];
+      if constexpr (!S::PIN) L.vals[p] = v[j];
+    }
+  }
+}
+
+// Coalesced scatter of a tile sorted in LDS (L.goff set, behind a barrier):
+// consecutive lanes write consecutive slots of a digit run, inside [set_lo, hi).
+// A packed output word holds the key bits above this digit over the index.
+template <class S, int BITS, int THREADS, int FOUT>
+__device__ __forceinline__ void sweep_scatter(const typename S::Lds &L, uint32_t tile_n, int shift,
+                                              int ib, uint32_t set_lo, uint32_t hi,
+                                              typename S::KO *__restrict__ kout,
+                                              uint32_t *__restrict__ vout, bool &bad) {
+  using KI = typename S::KI;
+  using KO = typename S::KO;
+  const uint32_t idx_mask = ib >= 32 ? 0xffffffffu : (1u << ib) - 1u;
+  for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
+    uint32_t d;
+    KI kk = 0;
+    if constexpr (S::SLOT_DIGIT) {
+      d = reinterpret_cast<const uint16_t *>(L.slot)[i];
+    } else {
+      kk = reinterpret_cast<const KI *>(L.slot)[i];
+      d = digit_of<BITS>(kk, shift);
+    }
+    const uint32_t idx = S::PIN ? ((uint32_t)kk & idx_mask) : L.vals[i];
+    const uint32_t gp = (uint32_t)(L.goff[d] + (int32_t)i);
+    if (gp < set_lo || gp >= hi) {  // cannot happen with consistent digit counts
+      bad = true;
+      continue;
+    }
+    if constexpr (FOUT == kFormIdx) {
+      vout[gp] = idx;
+    } else if constexpr (FOUT == kFormKey64) {
+      kout[gp] = (KO)kk;
+      vout[gp] = idx;
+    } else {
+      const uint64_t rest = (uint64_t)kk >> (shift + BITS);
+      kout[gp] = (KO)((rest << ib) | idx);
+    }
+  }
+}
+
+// One radix pass, one workgroup per tile.  kin/kout hold the key or packed
+// words; vin/vout the separate index of kFormKey64 (vin NULL: the index is the
+// position) and the output of kFormIdx.  shift: the digit's bit offset in the
+// input word; ib: idx_bits.  hist: single set, the pass's global digit counts
+// [radix]; batch, the pass's row of each set's digit bases (set b at b *
+// base_stride).
 template <int BITS, int IPT, int THREADS, int FIN, int FOUT, bool COUNTED, bool SEG>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const void *__restrict__ kin_v, void *__restrict__ kout_v,
@@ -182,35 +375,20 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
     const uint32_t *__restrict__ tile_off, int32_t *__restrict__ status_word, uint32_t n_tiles,
     SegTiles seg) {
-  using KI = typename FormType<FIN>::T;
-  using KO = typename FormType<FOUT>::T;
-  constexpr bool PIN = FIN != kFormKey64;  // packed input: the index is in the word
-  constexpr int R = 1 << BITS;
-  constexpr int WAVES = THREADS / 64;
-  constexpr int TILE = THREADS * IPT;
-  constexpr int DPT = (R + THREADS - 1) / THREADS;  // digits per thread
-  // the local sort keeps the input word, except where only a separate index is
-  // written: there the digit of each slot suffices
-  constexpr bool SLOT_DIGIT = FOUT == kFormIdx && !PIN;
-  constexpr int SLOT_BYTES = SLOT_DIGIT ? 2 : (int)sizeof(KI);
-
-  __shared__ __align__(16) unsigned char s_slot[TILE * SLOT_BYTES];
-  __shared__ uint32_t s_vals[PIN ? 1 : TILE];
-  __shared__ uint32_t s_wc[WAVES * R];     // per-wave digit counters, then wave offsets
-  __shared__ uint32_t s_tstart[R];         // tile-local start of each digit
-  __shared__ int32_t s_goff[R];            // output position minus tile-local position
-  __shared__ uint32_t s_tmp[WAVES];
-  __shared__ uint32_t s_tile;
+  using S = Sweep<BITS, IPT, THREADS, FIN, FOUT>;
+  using KI = typename S::KI;
+  constexpr int R = S::R, WAVES = S::WAVES, TILE = S::TILE, DPT = S::DPT;
+  __shared__ typename S::Lds L;
   const KI *__restrict__ kin = static_cast<const KI *>(kin_v);
-  KO *__restrict__ kout = static_cast<KO *>(kout_v);
+  typename S::KO *__restrict__ kout = static_cast<typename S::KO *>(kout_v);
   constexpr bool batch = SEG;
 
   // Look-back passes take tiles in the order they start, so that every earlier
   // tile is already running; counted passes (single sets only) need no order.
-  if (!COUNTED && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-  for (int i = threadIdx.x; i < WAVES * R; i += THREADS) s_wc[i] = 0;
+  if (!COUNTED && threadIdx.x == 0) L.tile = atomicAdd(tile_counter, 1u);
+  for (int i = threadIdx.x; i < WAVES * R; i += THREADS) L.wc[i] = 0;
   __syncthreads();
-  const uint32_t tile = COUNTED ? xcd_tile(blockIdx.x, gridDim.x) : s_tile;
+  const uint32_t tile = COUNTED ? xcd_tile(blockIdx.x, gridDim.x) : L.tile;
   // a batch launches one workgroup for each tile it may have
   const uint32_t tiles_here = batch ? (uint32_t)seg.tile_start[seg.nsets] : n_tiles;
   if (tile >= tiles_here) {
@@ -218,7 +396,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     if (!batch && threadIdx.x == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
     return;
   }
-  // the tile's keys [lo, lo + tile_n); its set's first tile starts the look-back
+  // the tile's elements [lo, lo + tile_n); its set's first tile starts the look-back
   uint32_t lo = tile * (uint32_t)TILE, hi = n, set_lo = 0u;
   bool first = tile == 0;
   const uint32_t *digit_base = hist;
@@ -233,126 +411,36 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   }
   const uint32_t tile_n = (hi - lo) < (uint32_t)TILE ? (hi - lo) : (uint32_t)TILE;
   const uint32_t last = lo + tile_n - 1u;
-  // where each digit's run starts does not depend on the keys: issue its load first
+  // where each digit's run starts does not depend on the elements: issue its load first
   uint32_t g[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
     const int d = threadIdx.x * DPT + t;
     g[t] = (d < R) ? digit_base[d] : 0u;
   }
-  const int wv = threadIdx.x / 64;
-  const int ln = lane_id();
-  const uint64_t lt = lanemask_lt();
-
-  // wave-striped load: item j of lane l is key lo + wv*64*IPT + j*64 + l.
-  // Loads are branch-free (indices past the tile are clamped and the items
-  // masked later) so that all of them are in flight together.
+  const uint32_t wbase = lo + (uint32_t)(threadIdx.x / 64) * 64u * IPT + (uint32_t)lane_id();
   KI k[IPT];
   uint32_t v[IPT];
-  uint32_t dg[IPT];
-  uint32_t rk[IPT];
-  const uint32_t wbase = lo + (uint32_t)wv * 64u * IPT + (uint32_t)ln;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, last)];
-  if constexpr (!PIN) {
-    if (vin) {
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, last)];
-    } else {
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) dg[j] = digit_of<BITS>(k[j], shift);
+  sweep_load<S, IPT>(kin, vin, wbase, last, k, v);
 
-  // Stable wave-level ranking: for every digit bit a ballot; XOR-ing the
-  // ballot with "all ones unless my bit is set" keeps exactly the lanes that
-  // agree with me on that bit, so the AND over all bits is the set of lanes
-  // holding my digit.  Its population below my lane is my rank among them.
-  uint32_t *wc = s_wc + wv * R;
+  uint32_t tcnt[DPT], trun_d[DPT];
+  sweep_rank<S, BITS, IPT, THREADS, !COUNTED>(L, k, v, wbase, last, shift, status, tile, first,
+                                               tcnt, trun_d);
+  // where each digit's run starts in the output: a block scan of the global
+  // digit counts, or the set's own bases
+  uint32_t grun_d[DPT];
+  if constexpr (batch) {
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const bool valid = wbase + j * 64 <= last;
-    const uint32_t d = dg[j];
-    const uint64_t vmask = __ballot(valid);
-    uint32_t plo = (uint32_t)vmask, phi = (uint32_t)(vmask >> 32);
+    for (int t = 0; t < DPT; ++t) grun_d[t] = g[t];
+  } else {
+    uint32_t gsum = 0, dummy;
 #pragma unroll
-    for (int b = 0; b < BITS; ++b) {
-      const uint32_t bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      const uint32_t flip = bit - 1u;  // 0 if my bit is set, all ones if clear
-      plo &= (uint32_t)bb ^ flip;
-      phi &= (uint32_t)(bb >> 32) ^ flip;
-    }
-    const uint64_t peers = ((uint64_t)phi << 32) | plo;
-    const uint32_t pre = (uint32_t)__popcll(peers & lt);
-    uint32_t cnt = 0;
-    if (valid) cnt = wc[d];
-    rk[j] = cnt + pre;
-    if (valid && pre == 0) wc[d] = cnt + (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-
-  // per digit: exclusive offsets across waves and the tile count
-  uint32_t tcnt[DPT];
+    for (int t = 0; t < DPT; ++t) gsum += g[t];
+    uint32_t grun = block_exclusive_sum<THREADS>(gsum, L.tmp, &dummy);
 #pragma unroll
-  for (int t = 0; t < DPT; ++t) {
-    const int d = threadIdx.x * DPT + t;
-    uint32_t run = 0;
-    if (d < R) {
-#pragma unroll
-      for (int q = 0; q < WAVES; ++q) {
-        const uint32_t c = s_wc[q * R + d];
-        s_wc[q * R + d] = run;
-        run += c;
-      }
-      if constexpr (!COUNTED)
-        atomic_store_agent(&status[(size_t)tile * R + d],
-                           (first ? kFlagInclusive : kFlagAggregate) | (uint64_t)run);
-    }
-    tcnt[t] = run;
-  }
-
-  // tile-local digit starts (a block scan over the digits), and where each
-  // digit's run starts in the output: a block scan of the global digit counts,
-  // or the set's own bases
-  uint32_t tsum = 0, gsum = 0;
-#pragma unroll
-  for (int t = 0; t < DPT; ++t) {
-    tsum += tcnt[t];
-    gsum += g[t];
-  }
-  uint32_t dummy;
-  uint32_t trun = block_exclusive_sum<THREADS>(tsum, s_tmp, &dummy);
-  uint32_t grun = 0;
-  if constexpr (!batch) grun = block_exclusive_sum<THREADS>(gsum, s_tmp, &dummy);
-
-  uint32_t trun_d[DPT], grun_d[DPT];
-#pragma unroll
-  for (int t = 0; t < DPT; ++t) {
-    const int d = threadIdx.x * DPT + t;
-    if (d < R) s_tstart[d] = trun;
-    trun_d[t] = trun;
-    grun_d[t] = batch ? g[t] : grun;
-    trun += tcnt[t];
-    grun += g[t];
-  }
-  __syncthreads();
-
-  // sort the tile by digit in LDS (the input key when a key is written, else
-  // the digit), before the look-back so that predecessors have this time to
-  // publish
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    if (wbase + j * 64 <= last) {
-      const uint32_t d = dg[j];
-      const uint32_t p = s_tstart[d] + wc[d] + rk[j];
-      if constexpr (SLOT_DIGIT)
-        reinterpret_cast<uint16_t *>(s_slot)[p] = (uint16_t)d;
-      else
-        reinterpret_cast<KI *>(s_slot)[p] = k[j];
-      if constexpr (!PIN) s_vals[p] = v[j];
+    for (int t = 0; t < DPT; ++t) {
+      grun_d[t] = grun;
+      grun += g[t];
     }
   }
   // the next pass's look-back words for this tile start cleared
@@ -373,41 +461,13 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
         atomic_store_agent(&status[(size_t)tile * R + d],
                            kFlagInclusive | (uint64_t)(excl + tcnt[t]));
       }
-      s_goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
+      L.goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
     }
   }
   __syncthreads();
 
-  // coalesced scatter: consecutive lanes write consecutive slots of a digit run,
-  // inside the tile's set [set_lo, hi)
   bool bad = false;
-  const uint32_t idx_mask = ib >= 32 ? 0xffffffffu : (1u << ib) - 1u;
-  for (uint32_t i = threadIdx.x; i < tile_n; i += THREADS) {
-    uint32_t d;
-    KI kk = 0;
-    if constexpr (SLOT_DIGIT) {
-      d = reinterpret_cast<const uint16_t *>(s_slot)[i];
-    } else {
-      kk = reinterpret_cast<const KI *>(s_slot)[i];
-      d = digit_of<BITS>(kk, shift);
-    }
-    const uint32_t idx = PIN ? ((uint32_t)kk & idx_mask) : s_vals[i];
-    const uint32_t gp = (uint32_t)(s_goff[d] + (int32_t)i);
-    if (gp < set_lo || gp >= hi) {  // cannot happen with consistent digit counts
-      bad = true;
-      continue;
-    }
-    if constexpr (FOUT == kFormIdx) {
-      vout[gp] = idx;
-    } else if constexpr (FOUT == kFormKey64) {
-      kout[gp] = (KO)kk;
-      vout[gp] = idx;
-    } else {
-      // the key bits above this digit, moved down to sit above the index
-      const uint64_t rest = (uint64_t)kk >> (shift + BITS);
-      kout[gp] = (KO)((rest << ib) | idx);
-    }
-  }
+  sweep_scatter<S, BITS, THREADS, FOUT>(L, tile_n, shift, ib, set_lo, hi, kout, vout, bad);
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
