@@ -95,7 +95,7 @@ struct Plan {
   // offsets
   size_t keys0, keys1;  // u64 [n] ping-pong buffers of keys or packed words
   size_t vals1;         // u32 [n] payload buffer (the other one is out->perm)
-  size_t hist;          // u32 [key_passes][radix] global digit counts (single set)
+  size_t hist;          // u32 [key_passes][radix] global digit counts, then bases (single set)
   size_t hist_part;     // u32 [keygen blocks][key_passes][radix] per-workgroup counts
   size_t status0, status1;  // u64 [sort_tiles][radix] look-back words (alternating passes)
   size_t counters;      // u32 [64] dynamic tile counters

@@ -16,7 +16,8 @@
 // k_hist_reduce column sums of those per-workgroup histograms.
 // k_keygen_sets the same for a batch, chunk by chunk of one set, with each set's
 //               digit counts added up per set;
-// k_set_base    each set's digit counts -> the start of every digit's run.
+// k_set_base    each set's digit counts -> the start of every digit's run (a
+//               single set's global counts too).
 #include "tb_internal.h"
 
 namespace tb {
@@ -496,25 +497,25 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen_sets(
 
 // Each set's digit counts of every pass -> the position where each digit's run
 // of the set starts (the set's first position plus the counts of the smaller
-// digits).  One workgroup per set, one thread per digit.
+// digits).  One workgroup per (set, pass) (blockIdx.y: the pass), one thread
+// per digit.
 template <int BITS>
 __global__ __launch_bounds__(1 << BITS) void k_set_base(const int64_t *__restrict__ set_off,
                                                         uint32_t *__restrict__ set_counts,
                                                         int passes, int32_t nsets) {
   constexpr int R = 1 << BITS;
   __shared__ uint32_t s_w[R / 64];
+  const int p = blockIdx.y;
   for (int b = blockIdx.x; b < nsets; b += gridDim.x) {
-    for (int p = 0; p < passes; ++p) {
-      uint32_t *row = set_counts + ((int64_t)b * passes + p) * R;
-      const uint32_t v = row[threadIdx.x];
-      const uint32_t inc = wave_inclusive_scan(v);
-      if (lane_id() == 63) s_w[threadIdx.x / 64] = inc;
-      __syncthreads();
-      uint32_t off = 0;
-      for (int q = 0; q < (int)threadIdx.x / 64; ++q) off += s_w[q];
-      row[threadIdx.x] = (uint32_t)set_off[b] + off + inc - v;
-      __syncthreads();
-    }
+    uint32_t *row = set_counts + ((int64_t)b * passes + p) * R;
+    const uint32_t v = row[threadIdx.x];
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (lane_id() == 63) s_w[threadIdx.x / 64] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int q = 0; q < (int)threadIdx.x / 64; ++q) off += s_w[q];
+    row[threadIdx.x] = (uint32_t)set_off[b] + off + inc - v;
+    __syncthreads();
   }
 }
 
@@ -582,18 +583,21 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const f
 }
 
 hipError_t launch_hist_reduce(const Plan &p, const Work &w, hipStream_t s) {
-  if (p.seg) {  // each set's digit counts become its digit bases
-    const int64_t grid = p.nsets < 65535 ? p.nsets : 65535;
-    if (p.sort.bits == 8)
-      k_set_base<8><<<(unsigned)grid, 256, 0, s>>>(w.set_off, w.seg_base, p.key_passes, p.nsets);
-    else if (p.sort.bits == 9)
-      k_set_base<9><<<(unsigned)grid, 512, 0, s>>>(w.set_off, w.seg_base, p.key_passes, p.nsets);
-    else
-      return hipErrorInvalidValue;
-    return hipGetLastError();
+  // each set's digit counts become its digit bases (a single set: once, rather
+  // than in every tile of a pass)
+  uint32_t *counts = w.seg_base;
+  if (!p.seg) {
+    const int cols = p.key_passes * p.sort.radix();
+    k_hist_reduce<<<(cols + 15) / 16, 256, 0, s>>>(w.hist_part, keygen_blocks(p.n), cols, w.hist);
+    counts = w.hist;
   }
-  const int cols = p.key_passes * p.sort.radix();
-  k_hist_reduce<<<(cols + 15) / 16, 256, 0, s>>>(w.hist_part, keygen_blocks(p.n), cols, w.hist);
+  const dim3 grid((unsigned)(p.nsets < 65535 ? p.nsets : 65535), (unsigned)p.key_passes);
+  if (p.sort.bits == 8)
+    k_set_base<8><<<grid, 256, 0, s>>>(w.set_off, counts, p.key_passes, p.nsets);
+  else if (p.sort.bits == 9)
+    k_set_base<9><<<grid, 512, 0, s>>>(w.set_off, counts, p.key_passes, p.nsets);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -364,8 +364,8 @@ __device__ __forceinline__ void sweep_scatter(const typename S::Lds &L, uint32_t
 // One radix pass, one workgroup per tile.  kin/kout hold the key or packed
 // words; vin/vout the separate index of kFormKey64 (vin NULL: the index is the
 // position) and the output of kFormIdx.  shift: the digit's bit offset in the
-// input word; ib: idx_bits.  hist: single set, the pass's global digit counts
-// [radix]; batch, the pass's row of each set's digit bases (set b at b *
+// input word; ib: idx_bits.  hist: the pass's digit bases, where each digit's
+// run starts in the output [radix]; a batch has a row per set (set b at b *
 // base_stride).
 template <int BITS, int IPT, int THREADS, int FIN, int FOUT, bool COUNTED, bool SEG>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   }
   const uint32_t tile_n = (hi - lo) < (uint32_t)TILE ? (hi - lo) : (uint32_t)TILE;
   const uint32_t last = lo + tile_n - 1u;
-  // where each digit's run starts does not depend on the elements: issue its load first
+  // where each digit's run starts does not depend on the elements: load it first
   uint32_t g[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
@@ -426,23 +426,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   uint32_t tcnt[DPT], trun_d[DPT];
   sweep_rank<S, BITS, IPT, THREADS, !COUNTED>(L, k, v, wbase, last, shift, status, tile, first,
                                                tcnt, trun_d);
-  // where each digit's run starts in the output: a block scan of the global
-  // digit counts, or the set's own bases
-  uint32_t grun_d[DPT];
-  if constexpr (batch) {
-#pragma unroll
-    for (int t = 0; t < DPT; ++t) grun_d[t] = g[t];
-  } else {
-    uint32_t gsum = 0, dummy;
-#pragma unroll
-    for (int t = 0; t < DPT; ++t) gsum += g[t];
-    uint32_t grun = block_exclusive_sum<THREADS>(gsum, L.tmp, &dummy);
-#pragma unroll
-    for (int t = 0; t < DPT; ++t) {
-      grun_d[t] = grun;
-      grun += g[t];
-    }
-  }
+  // where each digit's run starts in the output: g, the pass's digit bases
   // the next pass's look-back words for this tile start cleared
   for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
 
@@ -461,7 +445,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
         atomic_store_agent(&status[(size_t)tile * R + d],
                            kFlagInclusive | (uint64_t)(excl + tcnt[t]));
       }
-      L.goff[d] = (int32_t)(grun_d[t] + excl - trun_d[t]);
+      L.goff[d] = (int32_t)(g[t] + excl - trun_d[t]);
     }
   }
   __syncthreads();
