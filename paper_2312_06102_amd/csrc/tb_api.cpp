@@ -102,6 +102,8 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   p->status1 = take(8 * (size_t)p->sort_tiles * R);
   p->counters = take(4 * 64);
   p->tile_off = take(4 * (size_t)p->sort_tiles * R);
+  // (rounded to whole 32-bit words: the count kernel reads words)
+  p->dig = take(p->counted ? ((size_t)n * (sc.bits > 8 ? 2 : 1) + 3) / 4 * 4 : 0);
   p->set_off = take(8 * B1);
   p->box = take(8 * 4 * (size_t)nsets);
   p->bbox_part = take(8 * 6 * (size_t)p->bbox_chunks);
@@ -148,6 +150,7 @@ Work carve(const Plan &p, void *base) {
   w.status1 = reinterpret_cast<uint64_t *>(b + p.status1);
   w.counters = reinterpret_cast<uint32_t *>(b + p.counters);
   w.tile_off = reinterpret_cast<uint32_t *>(b + p.tile_off);
+  w.dig = b + p.dig;
   w.set_off = reinterpret_cast<int64_t *>(b + p.set_off);
   w.box = reinterpret_cast<double *>(b + p.box);
   w.bbox_part = reinterpret_cast<double *>(b + p.bbox_part);

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "treebuild.h"
 
 namespace tb {
@@ -72,6 +74,9 @@ enum SortForm : uint8_t {
   kFormPack32 = 4,  // the same in 32 bits
 };
 constexpr int kMaxKeyPasses = 8;
+// One radix digit as the counted passes store it between passes.
+template <int BITS>
+using DigitType = typename std::conditional<(BITS > 8), uint16_t, uint8_t>::type;
 
 // Workspace plan: byte offsets of every scratch array inside the caller's
 // workspace, all 256-byte aligned.
@@ -101,6 +106,8 @@ struct Plan {
   size_t counters;      // u32 [64] dynamic tile counters
   size_t tile_off;      // u32 [radix][sort_tiles] digit counts of every tile, then their
                         // exclusive prefix over the tiles (counted passes)
+  size_t dig;           // u8 (u16 for 9-bit digits) [n] counted passes: the next pass's
+                        // digit of every element
   size_t set_off;       // i64 [B + 1] particle offsets of the sets
   size_t box;           // f64 [B][4] the root box of each set
   size_t bbox_part;     // f64 [bbox_chunks][6] per-chunk min/max
@@ -141,6 +148,7 @@ struct Work {
   uint64_t *status0, *status1;
   uint32_t *counters;
   uint32_t *tile_off;
+  void *dig;
   int64_t *set_off;
   double *box;
   double *bbox_part;

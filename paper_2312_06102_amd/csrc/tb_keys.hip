@@ -358,7 +358,8 @@ template <int BITS>
 __device__ __forceinline__ void key_one(float x, float y, float z, float m, bool valid,
                                         int64_t i, double lo0, double lo1, double lo2,
                                         double scale, bool hilbert, uint64_t *__restrict__ keys,
-                                        float4 *__restrict__ packed, uint32_t *h, bool &bad) {
+                                        float4 *__restrict__ packed, void *__restrict__ dig0,
+                                        uint32_t *h, bool &bad) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
   bad |= valid && !(isfinite(x) && isfinite(y) && isfinite(z));
@@ -367,6 +368,8 @@ __device__ __forceinline__ void key_one(float x, float y, float z, float m, bool
     keys[i] = key;
     // (x, y, z, m) in one 16-byte record: the reorder step gathers one line each
     packed[i] = make_float4(x, y, z, m);
+    // the first radix pass's digit, for its tile counts (counted passes)
+    if (dig0) static_cast<DigitType<BITS> *>(dig0)[i] = (DigitType<BITS>)(key & (R - 1));
   }
   const uint64_t active = __ballot(valid);
   if (valid) {
@@ -389,7 +392,8 @@ template <int BITS>
 __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
     const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
     const double *__restrict__ box, uint64_t *__restrict__ keys, float4 *__restrict__ packed,
-    uint32_t *__restrict__ hist_part, int passes, int hilbert, int32_t *__restrict__ status_word) {
+    void *__restrict__ dig0, uint32_t *__restrict__ hist_part, int passes, int hilbert,
+    int32_t *__restrict__ status_word) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
   __shared__ uint32_t h[MAXP * R];
@@ -416,7 +420,7 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen(
     for (int r = 0; r < kKeygenIpt; ++r) {
       const int64_t i = i0 + (int64_t)r * blockDim.x;
       key_one<BITS>(x[r], y[r], z[r], m[r], i < n, i, lo0, lo1, lo2, scale, hilbert != 0, keys,
-                    packed, h, bad);
+                    packed, dig0, h, bad);
     }
   }
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_NONFINITE);
@@ -477,7 +481,7 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen_sets(
       for (int r = 0; r < kKeygenIpt; ++r) {
         const int64_t i = base + r * kKeygenThreads + threadIdx.x;
         key_one<BITS>(x[r], y[r], z[r], m[r], i < s1, i, lo0, lo1, lo2, scale, hilbert != 0,
-                      keys, packed, h, bad);
+                      keys, packed, nullptr, h, bad);
       }
     }
     __syncthreads();
@@ -558,7 +562,8 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const f
     const int blocks = keygen_blocks(p.n);
 #define TB_KEYGEN(B)                                                                           \
   k_keygen<B><<<blocks, kKeygenThreads, 0, s>>>(pos, mass, p.n, w.box, w.keys0, w.packed,      \
-                                                w.hist_part, passes, hil, out.status)
+                                                (p.counted & 1u) ? w.dig : nullptr, w.hist_part, passes, \
+                                                hil, out.status)
     switch (p.sort.bits) {
       case 8: TB_KEYGEN(8); break;
       case 9: TB_KEYGEN(9); break;

@@ -88,30 +88,32 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
 }
 
 // Digit counts of one tile of a counted pass: tile t (the elements [t TILE,
-// (t + 1) TILE), as the scatter kernel tiles them) writes cnt[d][t].
-template <int BITS, int IPT, int THREADS, int FIN>
-__global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__ kin_v,
-                                                        uint32_t n, int shift,
+// (t + 1) TILE), as the scatter kernel tiles them) writes cnt[d][t].  The
+// digits come from dig, written for this pass by the key kernel (first pass) or
+// by the previous pass's scatter, so a count reads one byte an element (two for
+// 9-bit digits) instead of the element.
+template <int BITS, int IPT, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__ dig_v, uint32_t n,
                                                         uint32_t *__restrict__ cnt,
                                                         uint32_t n_tiles) {
-  using KI = typename FormType<FIN>::T;
+  using DT = DigitType<BITS>;
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
   constexpr uint32_t TILE = (uint32_t)THREADS * IPT;
   __shared__ uint32_t h[WAVES * R];  // one histogram per wave
   for (int i = threadIdx.x; i < WAVES * R; i += THREADS) h[i] = 0;
-  const KI *__restrict__ kin = static_cast<const KI *>(kin_v);
+  const DT *__restrict__ dig = static_cast<const DT *>(dig_v);
   const uint32_t tile = blockIdx.x;
   const uint32_t base = tile * TILE;
-  KI k[IPT];
+  uint32_t k[IPT];
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) k[j] = kin[min(base + j * THREADS + threadIdx.x, n - 1u)];
+  for (int j = 0; j < IPT; ++j) k[j] = dig[min(base + j * THREADS + threadIdx.x, n - 1u)];
   __syncthreads();
   uint32_t *hw = h + (threadIdx.x / 64) * R;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const bool valid = base + j * THREADS + threadIdx.x < n;
-    const uint32_t d = digit_of<BITS>(k[j], shift);
+    const uint32_t d = k[j];
     // clustered data gives few distinct digits per wave: groups of four or
     // more equal digits add once (all masks wave-uniform), the rest one by one
     uint64_t rem = __ballot(valid);
@@ -326,11 +328,14 @@ __device__ __forceinline__ void sweep_rank(typename S::Lds &L, const typename S:
 // Coalesced scatter of a tile sorted in LDS (L.goff set, behind a barrier):
 // consecutive lanes write consecutive slots of a digit run, inside [set_lo, hi).
 // A packed output word holds the key bits above this digit over the index.
+// dig_out (a counted next pass): the next pass's digit of each element, at its
+// output position.
 template <class S, int BITS, int THREADS, int FOUT>
 __device__ __forceinline__ void sweep_scatter(const typename S::Lds &L, uint32_t tile_n, int shift,
                                               int ib, uint32_t set_lo, uint32_t hi,
                                               typename S::KO *__restrict__ kout,
-                                              uint32_t *__restrict__ vout, bool &bad) {
+                                              uint32_t *__restrict__ vout,
+                                              DigitType<BITS> *__restrict__ dig_out, bool &bad) {
   using KI = typename S::KI;
   using KO = typename S::KO;
   const uint32_t idx_mask = ib >= 32 ? 0xffffffffu : (1u << ib) - 1u;
@@ -351,12 +356,16 @@ __device__ __forceinline__ void sweep_scatter(const typename S::Lds &L, uint32_t
     }
     if constexpr (FOUT == kFormIdx) {
       vout[gp] = idx;
-    } else if constexpr (FOUT == kFormKey64) {
-      kout[gp] = (KO)kk;
-      vout[gp] = idx;
     } else {
+      // the key bits above this digit: the next pass's digit at their bottom
       const uint64_t rest = (uint64_t)kk >> (shift + BITS);
-      kout[gp] = (KO)((rest << ib) | idx);
+      if constexpr (FOUT == kFormKey64) {
+        kout[gp] = (KO)kk;
+        vout[gp] = idx;
+      } else {
+        kout[gp] = (KO)((rest << ib) | idx);
+      }
+      if (dig_out) dig_out[gp] = (DigitType<BITS>)(rest & ((1u << BITS) - 1u));
     }
   }
 }
@@ -374,7 +383,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     int ib, const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
     uint64_t *__restrict__ status_next, uint32_t *__restrict__ tile_counter,
     const uint32_t *__restrict__ tile_off, int32_t *__restrict__ status_word, uint32_t n_tiles,
-    SegTiles seg) {
+    SegTiles seg, void *__restrict__ dig_out) {
   using S = Sweep<BITS, IPT, THREADS, FIN, FOUT>;
   using KI = typename S::KI;
   constexpr int R = S::R, WAVES = S::WAVES, TILE = S::TILE, DPT = S::DPT;
@@ -451,7 +460,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   __syncthreads();
 
   bool bad = false;
-  sweep_scatter<S, BITS, THREADS, FOUT>(L, tile_n, shift, ib, set_lo, hi, kout, vout, bad);
+  sweep_scatter<S, BITS, THREADS, FOUT>(L, tile_n, shift, ib, set_lo, hi, kout, vout,
+                                        static_cast<DigitType<BITS> *>(dig_out), bad);
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(status_word, TB_STATUS_INTERNAL);
 }
 
@@ -469,10 +479,12 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
   const int R = 1 << BITS;
   const int shift = FIN == kFormKey64 ? pass * BITS : p.idx_bits;
   if constexpr (COUNTED) {
-    k_tile_count<BITS, IPT, THREADS, FIN><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
-        K[pass % 2], (uint32_t)p.n, shift, w.tile_off, (uint32_t)p.sort_tiles);
+    k_tile_count<BITS, IPT, THREADS><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
+        w.dig, (uint32_t)p.n, w.tile_off, (uint32_t)p.sort_tiles);
     k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
   }
+  // a counted pass that follows needs this pass to leave its digits behind
+  void *dig_out = (pass + 1 < P && ((p.counted >> (pass + 1)) & 1u)) ? w.dig : nullptr;
   SegTiles seg{nullptr, nullptr, nullptr, 0, p.nsets};
   const uint32_t *hist = w.hist + (size_t)pass * R;
   if (p.seg) {
@@ -485,7 +497,7 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
   k<<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
       K[pass % 2], K[(pass + 1) % 2], vin, V[(pass + 1) % 2], (uint32_t)p.n, shift, p.idx_bits,
       hist, S[pass % 2], S[(pass + 1) % 2], w.counters + pass, w.tile_off, out.status,
-      (uint32_t)p.sort_tiles, seg);
+      (uint32_t)p.sort_tiles, seg, dig_out);
   return hipGetLastError();
 }
 

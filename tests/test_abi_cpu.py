@@ -63,8 +63,11 @@ def test_workspace_bytes_grows_with_n():
         tb.tb_workspace_bytes(10, 16, flags=7)
     with pytest.raises(tb.TreeBuildArgError):
         tb.tb_workspace_bytes(10, 16, flags=tb.TB_SORT_CONFIG(200))
-    # the look-back switch is a known flag (same workspace); neighbouring bits are not
-    assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_LOOKBACK) == tb.tb_workspace_bytes(10000, 16)
+    # the look-back switch is a known flag; neighbouring bits are not.  Counted
+    # passes (the default on small grids) keep one digit byte per element between
+    # passes, which look-back passes do not need
+    lb, dflt = tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_LOOKBACK), tb.tb_workspace_bytes(10000, 16)
+    assert abs((dflt - lb) - 10000) <= 256  # regions are 256-byte aligned
     # the subtree-rooted cell build is a known flag too
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SUBTREES) > 0
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED) > 0
