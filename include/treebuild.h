@@ -97,16 +97,15 @@ extern "C" {
 #define TB_SORT_CONFIG(k) (((uint32_t)(k)&0xffu) << 8)
 
 /* The radix passes of a single set normally take their tile offsets from a
- * separate count of every tile's digits (one more read of the pass's elements,
- * 8 or 4 bytes each) when the sort has at most 4096 tiles, and from the
- * decoupled look-back across tiles otherwise (and always in a batch).  This
- * flag keeps the look-back in every pass.  Results are bit-identical either
- * way; the flag exists for tuning and tests. */
+ * separate count of every tile's digits (one byte an element, which the
+ * previous pass leaves behind); a batch's passes use the decoupled look-back
+ * across tiles.  This flag uses the look-back in every pass.  Results are
+ * bit-identical either way; the flag exists for tuning and tests. */
 #define TB_SORT_LOOKBACK (1u << 17)
 
-/* Count the tiles' digits in every radix pass of a single set whatever the
- * number of tiles (batches keep the look-back).  Not with TB_SORT_LOOKBACK
- * (TB_ERR_ARG).  Results are bit-identical. */
+/* Count the tiles' digits in every radix pass, in a batch too (its offsets
+ * then start again at every set); for a single set this is the default.  Not
+ * with TB_SORT_LOOKBACK (TB_ERR_ARG).  Results are bit-identical. */
 #define TB_SORT_COUNTED (1u << 19)
 
 /* Build the cells subtree by subtree (Sec. 2.3.3, eq. 2): the sorted keys are

@@ -30,7 +30,6 @@ constexpr int kCellThreads = 256;
 constexpr int kCellIpt = 8;
 constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
 
-constexpr int64_t kCountedMaxTiles = 4096;  // largest sort grid with counted passes
 
 // The chip's eight XCDs each have their own L2, and workgroups of a launch are
 // dispatched to them in turn (workgroup b to XCD b mod 8).

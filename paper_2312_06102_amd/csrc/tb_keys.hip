@@ -437,8 +437,8 @@ template <int BITS>
 __global__ __launch_bounds__(kKeygenThreads) void k_keygen_sets(
     const float *__restrict__ pos, const float *__restrict__ mass, int64_t n,
     const int64_t *__restrict__ set_off, int32_t nsets, const double *__restrict__ box,
-    uint64_t *__restrict__ keys, float4 *__restrict__ packed, uint32_t *__restrict__ set_counts,
-    int passes, int hilbert, int32_t *__restrict__ status_word) {
+    uint64_t *__restrict__ keys, float4 *__restrict__ packed, void *__restrict__ dig0,
+    uint32_t *__restrict__ set_counts, int passes, int hilbert, int32_t *__restrict__ status_word) {
   constexpr int R = 1 << BITS;
   constexpr int MAXP = (63 + BITS - 1) / BITS;
   constexpr int64_t kStep = (int64_t)kKeygenThreads * kKeygenIpt;
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kKeygenThreads) void k_keygen_sets(
       for (int r = 0; r < kKeygenIpt; ++r) {
         const int64_t i = base + r * kKeygenThreads + threadIdx.x;
         key_one<BITS>(x[r], y[r], z[r], m[r], i < s1, i, lo0, lo1, lo2, scale, hilbert != 0,
-                      keys, packed, nullptr, h, bad);
+                      keys, packed, dig0, h, bad);
       }
     }
     __syncthreads();
@@ -575,8 +575,8 @@ hipError_t launch_keygen(const Plan &p, const Work &w, const float *pos, const f
     const int blocks = 2 * keygen_blocks(p.n);
 #define TB_KEYGEN_SETS(B)                                                                      \
   k_keygen_sets<B><<<(unsigned)blocks, kKeygenThreads, 0, s>>>(                                \
-      pos, mass, p.n, w.set_off, p.nsets, w.box, w.keys0, w.packed, w.seg_base, passes, hil,   \
-      out.status)
+      pos, mass, p.n, w.set_off, p.nsets, w.box, w.keys0, w.packed,                            \
+      (p.counted & 1u) ? w.dig : nullptr, w.seg_base, passes, hil, out.status)
     switch (p.sort.bits) {
       case 8: TB_KEYGEN_SETS(8); break;
       case 9: TB_KEYGEN_SETS(9); break;

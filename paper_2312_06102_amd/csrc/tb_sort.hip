@@ -16,12 +16,14 @@
 // The global digit counts come from the key-generation pass, so the keys are
 // read only once per pass.  The index payload of the last pass is `perm`.
 //
-// On small grids (see kCountedMaxTiles) the passes are "counted" instead
-// (reduce, then scan): a first kernel reads only the elements and writes every
-// tile's digit counts, a second turns them into exclusive prefixes over the
-// tiles, and the scatter kernel reads its tile's offsets instead of waiting on
-// its predecessors.  There, reading the elements again costs less than the
-// look-back chain across the chip; TB_SORT_LOOKBACK keeps the look-back.
+// By default the passes of a single set are "counted" instead (reduce, then
+// scan; a batch with TB_SORT_COUNTED too): a first
+// kernel reads each element's digit (one byte, left behind by the previous pass
+// or the key kernel) and writes every tile's digit counts, a second turns them
+// into exclusive prefixes over the tiles, and the scatter kernel reads its
+// tile's offsets instead of waiting on its predecessors.  Reading that byte
+// again costs less than the look-back chain across the chip; TB_SORT_LOOKBACK
+// keeps the look-back.
 //
 // A batch sorts every set in place: a set's tiles never straddle it, its tiles'
 // look-back chain starts at its own first tile, and its digit runs start at
@@ -87,15 +89,28 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift) {
   return (k >> shift) & ((1u << BITS) - 1u);
 }
 
-// Digit counts of one tile of a counted pass: tile t (the elements [t TILE,
-// (t + 1) TILE), as the scatter kernel tiles them) writes cnt[d][t].  The
-// digits come from dig, written for this pass by the key kernel (first pass) or
-// by the previous pass's scatter, so a count reads one byte an element (two for
-// 9-bit digits) instead of the element.
+// Tiles of a pass.  A single set: tile t holds keys [t TILE, (t+1) TILE) of the
+// array, and the digit runs start where the global digit counts put them.  A
+// batch: every set is sorted in place; a set's tiles never straddle it, tile t
+// of set b holds the set's keys [t TILE, (t+1) TILE) counted from the set's
+// first tile, and each digit's run of the set starts at the set's own base.
+struct SegTiles {
+  const int64_t *tile_start;  // [B + 1] first tile of each set, or NULL (single set)
+  const int32_t *tile_set;    // [tiles] set of each tile
+  const int64_t *set_off;     // [B + 1] first position of each set
+  size_t base_stride;         // words between two sets' rows of `hist`
+  int32_t nsets;
+};
+
+// Digit counts of one tile of a counted pass: tile t (its elements as the
+// scatter kernel tiles them, SegTiles) writes cnt[d][t].  The digits come from
+// dig, written for this pass by the key kernel (first pass) or by the previous
+// pass's scatter, so a count reads one byte an element (two for 9-bit digits)
+// instead of the element.
 template <int BITS, int IPT, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__ dig_v, uint32_t n,
                                                         uint32_t *__restrict__ cnt,
-                                                        uint32_t n_tiles) {
+                                                        uint32_t n_tiles, SegTiles seg) {
   using DT = DigitType<BITS>;
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
@@ -104,15 +119,22 @@ __global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__
   for (int i = threadIdx.x; i < WAVES * R; i += THREADS) h[i] = 0;
   const DT *__restrict__ dig = static_cast<const DT *>(dig_v);
   const uint32_t tile = blockIdx.x;
-  const uint32_t base = tile * TILE;
+  uint32_t base = tile * TILE, hi = n;
+  if (seg.tile_start) {
+    if (tile >= (uint32_t)seg.tile_start[seg.nsets]) return;  // the same for the whole workgroup
+    const int b = seg.tile_set[tile];
+    base = (uint32_t)seg.set_off[b] + (uint32_t)((int64_t)(tile - seg.tile_start[b]) * TILE);
+    hi = (uint32_t)seg.set_off[b + 1];
+  }
+  const uint32_t last = min(base + TILE, hi) - 1u;
   uint32_t k[IPT];
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) k[j] = dig[min(base + j * THREADS + threadIdx.x, n - 1u)];
+  for (int j = 0; j < IPT; ++j) k[j] = dig[min(base + j * THREADS + threadIdx.x, last)];
   __syncthreads();
   uint32_t *hw = h + (threadIdx.x / 64) * R;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
-    const bool valid = base + j * THREADS + threadIdx.x < n;
+    const bool valid = base + j * THREADS + threadIdx.x <= last;
     const uint32_t d = k[j];
     // clustered data gives few distinct digits per wave: groups of four or
     // more equal digits add once (all masks wave-uniform), the rest one by one
@@ -157,18 +179,6 @@ __global__ __launch_bounds__(THREADS) void k_tile_scan(uint32_t *__restrict__ cn
   }
 }
 
-// Tiles of a pass.  A single set: tile t holds keys [t TILE, (t+1) TILE) of the
-// array, and the digit runs start where the global digit counts put them.  A
-// batch: every set is sorted in place; a set's tiles never straddle it, tile t
-// of set b holds the set's keys [t TILE, (t+1) TILE) counted from the set's
-// first tile, and each digit's run of the set starts at the set's own base.
-struct SegTiles {
-  const int64_t *tile_start;  // [B + 1] first tile of each set, or NULL (single set)
-  const int32_t *tile_set;    // [tiles] set of each tile
-  const int64_t *set_off;     // [B + 1] first position of each set
-  size_t base_stride;         // words between two sets' rows of `hist`
-  int32_t nsets;
-};
 
 // All ones if bit b of d is set, else zero: one signed one-bit field extract
 // (the compiler would otherwise shift left and then arithmetically right).
@@ -393,7 +403,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   constexpr bool batch = SEG;
 
   // Look-back passes take tiles in the order they start, so that every earlier
-  // tile is already running; counted passes (single sets only) need no order.
+  // tile is already running; counted passes need no order.
   if (!COUNTED && threadIdx.x == 0) L.tile = atomicAdd(tile_counter, 1u);
   for (int i = threadIdx.x; i < WAVES * R; i += THREADS) L.wc[i] = 0;
   __syncthreads();
@@ -406,12 +416,13 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     return;
   }
   // the tile's elements [lo, lo + tile_n); its set's first tile starts the look-back
-  uint32_t lo = tile * (uint32_t)TILE, hi = n, set_lo = 0u;
+  uint32_t lo = tile * (uint32_t)TILE, hi = n, set_lo = 0u, set_tile0 = 0u;
   bool first = tile == 0;
   const uint32_t *digit_base = hist;
   if constexpr (batch) {
     const int b = seg.tile_set[tile];
     const int64_t t0 = seg.tile_start[b];
+    set_tile0 = (uint32_t)t0;
     set_lo = (uint32_t)seg.set_off[b];
     lo = set_lo + (uint32_t)((int64_t)(tile - t0) * TILE);
     hi = (uint32_t)seg.set_off[b + 1];
@@ -439,14 +450,16 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   // the next pass's look-back words for this tile start cleared
   for (int i = threadIdx.x; i < R; i += THREADS) status_next[(size_t)tile * R + i] = 0;
 
-  // decoupled look-back within the set (or the counted offsets), one thread per digit
+  // the counted offsets (or the decoupled look-back within the set), one thread per digit
 #pragma unroll
   for (int t = 0; t < DPT; ++t) {
     const int d = threadIdx.x * DPT + t;
     if (d < R) {
       uint32_t excl = 0;
       if (COUNTED) {
+        // the prefix over all earlier tiles, less the prefix before the set's first tile
         excl = tile_off[(size_t)d * n_tiles + tile];
+        if (batch) excl -= tile_off[(size_t)d * n_tiles + set_tile0];
       } else if (!first) {
         bool timed_out = false;
         excl = lookback<2>(status, R, tile, d, timed_out);
@@ -478,13 +491,6 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
   const uint32_t *vin = (pass == 0 || FIN != kFormKey64) ? nullptr : V[pass % 2];
   const int R = 1 << BITS;
   const int shift = FIN == kFormKey64 ? pass * BITS : p.idx_bits;
-  if constexpr (COUNTED) {
-    k_tile_count<BITS, IPT, THREADS><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
-        w.dig, (uint32_t)p.n, w.tile_off, (uint32_t)p.sort_tiles);
-    k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
-  }
-  // a counted pass that follows needs this pass to leave its digits behind
-  void *dig_out = (pass + 1 < P && ((p.counted >> (pass + 1)) & 1u)) ? w.dig : nullptr;
   SegTiles seg{nullptr, nullptr, nullptr, 0, p.nsets};
   const uint32_t *hist = w.hist + (size_t)pass * R;
   if (p.seg) {
@@ -492,6 +498,15 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
                    p.nsets};
     hist = w.seg_base + (size_t)pass * R;
   }
+  if constexpr (COUNTED) {
+    k_tile_count<BITS, IPT, THREADS><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
+        w.dig, (uint32_t)p.n, w.tile_off, (uint32_t)p.sort_tiles, seg);
+    // tiles past the batch's last one count nothing and come after every real
+    // tile, so the scan's prefixes for the real tiles are unaffected
+    k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
+  }
+  // a counted pass that follows needs this pass to leave its digits behind
+  void *dig_out = (pass + 1 < P && ((p.counted >> (pass + 1)) & 1u)) ? w.dig : nullptr;
   auto k = p.seg ? k_onesweep<BITS, IPT, THREADS, FIN, FOUT, COUNTED, true>
                  : k_onesweep<BITS, IPT, THREADS, FIN, FOUT, COUNTED, false>;
   k<<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(

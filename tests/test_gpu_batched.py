@@ -152,17 +152,21 @@ def test_one_set_batch_equals_single_build():
     assert np.array_equal(v["com"], s["com"]) and np.array_equal(v["quad"], s["quad"])
 
 
-@pytest.mark.parametrize("lookback", [False, True])
-@pytest.mark.parametrize("sort_config", [0, 2])
-def test_many_small_sets(sort_config, lookback):
+@pytest.mark.parametrize("mode", ["default", "lookback", "counted"])
+@pytest.mark.parametrize("sort_config", [0, 4])
+def test_many_small_sets(sort_config, mode):
     """600 sets of up to 300 particles, many sharing one radix tile's worth of
     positions with their neighbours but each sorted in place in tiles of its own;
-    8- and 9-bit digits (configs 0 and 2), with and without TB_SORT_LOOKBACK."""
+    8- and 9-bit digits (configs 0 and 4); the passes as the default chooses
+    them (look-back in a batch), with TB_SORT_LOOKBACK, and counted
+    (TB_SORT_COUNTED: each set's tile offsets start again at its first tile)."""
+    assert tb.tb_sort_configs()[4][0] == 9
     rng = _rng(33)
     sizes = rng.integers(0, 300, 600)
     sizes[::50] = 0
     pos, mass, offsets = plummer_batch(sizes, seed=33)
-    g = batch_build(pos, mass, offsets, 8, sort_config=sort_config, lookback=lookback)
+    g = batch_build(pos, mass, offsets, 8, sort_config=sort_config,
+                    lookback=mode == "lookback", counted=mode == "counted")
     check_offsets(g, offsets)
     check_against_oracle(pos, mass, offsets, 8, g, range(len(sizes)))
 

@@ -146,11 +146,10 @@ def test_full_size_clustered64m():
     sampled_moments(pos, mass, g, FP64_TOL)
 
 
-def test_counted_passes_at_largest_grid():
-    """N = 2^24 with a 4096-key sort tile gives exactly 4096 tiles, the largest
-    grid on which the passes count their tiles instead of looking back.  The
-    tree must be bit-identical to the look-back build, and the perm must sort
-    the keys stably."""
+def test_counted_passes_at_full_size():
+    """N = 2^24 with a 4096-key sort tile (exactly 4096 tiles): the counted
+    passes (the default) must give a tree bit-identical to the look-back build,
+    and the perm must sort the keys stably."""
     cfgs = tb.tb_sort_configs()
     k = next(i for i, (bits, ipt, thr) in enumerate(cfgs) if bits == 8 and ipt * thr == 4096)
     pos, mass = dg.plummer(1 << 24, seed=2)
