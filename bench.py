@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPYF", "COPYW"),
                     help="write profiles/pmc_<workload>.json and its .md from rocprofv3 --pmc "
                          "FETCH_SIZE / WRITE_SIZE CSVs of the build and of --copy-calibration")
+    ap.add_argument("--summarize-sq", metavar="CSV",
+                    help="write profiles/sort_<workload>_sq_counters.md from a rocprofv3 --pmc CSV "
+                         "of SQ counters (with --profile-command)")
     ap.add_argument("--gather-csv", default=None,
                     help="with --summarize-pmc: FETCH_SIZE CSV of --gather-calibration")
     ap.add_argument("--profile-command", default="", help="command line recorded in a summary")
@@ -176,6 +179,53 @@ def _read_csv(path):
     import csv
     with open(path) as f:
         return list(csv.DictReader(f))
+
+
+SQ_CLOCK_GHZ = 2.4  # MI355X engine clock; SQ_WAVE_CYCLES counts in units of 4 cycles
+
+
+def summarize_sq(args):
+    """Markdown table of SQ instruction counters per library kernel: the mean per
+    dispatch of every counter, and per wave the VALU and LDS instructions and the
+    wave's life (SQ_WAVE_CYCLES x 4 cycles over the waves, at 2.4 GHz)."""
+    rows = _read_csv(args.summarize_sq)
+    per = {}
+    for r in rows:
+        k = _short_kernel(r["Kernel_Name"])
+        if _stage(k) is None:
+            continue
+        d = per.setdefault(k, {"dispatches": set(), "waves": {}, "ctr": {}})
+        did = r["Dispatch_Id"]
+        d["dispatches"].add(did)
+        d["waves"][did] = int(r["Grid_Size"]) // 64
+        d["ctr"].setdefault(r["Counter_Name"], {})[did] = float(r["Counter_Value"])
+    names = sorted({c for d in per.values() for c in d["ctr"]})
+    out = [f"# SQ instruction counters: {args.workload}", "",
+           "Command (on the GPU host, repository root as `<repo>`):", "",
+           f"    {args.profile_command}", "",
+           "Mean per dispatch (values summed over the chip as rocprofv3 reports them); per "
+           "wave: the mean over dispatches of counter / waves of the dispatch; wave life = "
+           f"SQ_WAVE_CYCLES x 4 cycles / waves at {SQ_CLOCK_GHZ} GHz.", "",
+           "| kernel | dispatches | " + " | ".join(n.replace("SQ_", "") for n in names)
+           + " | VALU / wave | LDS / wave | wave life us |",
+           "|---|---|" + "---|" * len(names) + "---|---|---|"]
+    order = sorted(per.items(), key=lambda kv: -sum(kv[1]["ctr"].get("SQ_WAVE_CYCLES", {}).values()))
+    for k, d in order:
+        disp = sorted(d["dispatches"])
+        means = [sum(d["ctr"].get(n, {}).values()) / len(disp) for n in names]
+
+        def per_wave(name):
+            v = d["ctr"].get(name, {})
+            xs = [v[i] / d["waves"][i] for i in disp if i in v and d["waves"][i]]
+            return sum(xs) / len(xs) if xs else float("nan")
+        life = per_wave("SQ_WAVE_CYCLES") * 4 / (SQ_CLOCK_GHZ * 1e3)
+        out.append(f"| {k} | {len(disp)} | " + " | ".join(f"{m:.3g}" for m in means)
+                   + f" | {per_wave('SQ_INSTS_VALU'):.0f} | {per_wave('SQ_INSTS_LDS'):.0f} | "
+                   f"{life:.2f} |")
+    path = os.path.join(PROFILES, f"sort_{args.workload}_sq_counters.md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print(path)
 
 
 def summarize_trace(args):
@@ -447,7 +497,7 @@ def kernels_table(trace, steps, alg):
 SORT_PASS_BYTES = 24  # the method's bytes per key and radix pass: (key 8 + index 4) in and out
 
 
-def roofline(trace, alg, key_passes, workload, n):
+def roofline(trace, alg, key_passes, workload, n, counters_apply=True):
     """Roofline entry of the dominant kernel (the sort's key passes).  achieved =
     the method's algorithmic bytes of one pass (24 per key) / the mean pass
     time; design_* = what this design's element formats move (less, as the
@@ -464,7 +514,7 @@ def roofline(trace, alg, key_passes, workload, n):
          "alg_bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 5),
          "design_bytes_per_launch": design,
          "design_GBps": round(design / (avg_ms * 1e-3) / 1e9, 1)}
-    prof = counter_traffic(workload)
+    prof = counter_traffic(workload) if counters_apply else None
     if prof is not None:
         k = prof["kernels"].get("sort_pass")
         if k:
@@ -473,8 +523,8 @@ def roofline(trace, alg, key_passes, workload, n):
     return r
 
 
-def counter_summary(workload, ms_per_step):
-    prof = counter_traffic(workload)
+def counter_summary(workload, ms_per_step, counters_apply=True):
+    prof = counter_traffic(workload) if counters_apply else None
     if prof is None:
         return None
     tot = sum(k["bytes_per_launch"] * k["launches_per_build"] for k in prof["kernels"].values())
@@ -539,6 +589,12 @@ def run_single(args, tb, dg, torch, np):
     print(f"[bench] generated {args.workload} N={n} in {time.time() - t_gen:.1f}s", file=sys.stderr,
           flush=True)
     precision = args.precision or ("mixed" if args.workload == "mixed16m" else "fp64")
+    # the committed counter profiles were taken with the defaults: their sort
+    # figures apply while the sort runs as profiled, the whole-build figure only
+    # while every kernel does
+    sort_as_profiled = not (args.sort_config or args.sort_counted or args.sort_lookback)
+    build_as_profiled = (not args.subtrees and args.curve == "morton"
+                         and precision == ("mixed" if args.workload == "mixed16m" else "fp64"))
     k = args.sort_config or 0
     dev = torch.device("cuda:0")
     pos = torch.from_numpy(pos_np).to(dev)
@@ -569,11 +625,12 @@ def run_single(args, tb, dg, torch, np):
                    "cell_build": "subtree-rooted blocks" if args.subtrees else "tiles + parents",
                    "sort_counted_all_passes": bool(args.sort_counted),
                    "sort_lookback_all_passes": bool(args.sort_lookback), "keys": args.curve},
-        "roofline": roofline(trace, alg, key_passes, args.workload, n),
+        "roofline": roofline(trace, alg, key_passes, args.workload, n, sort_as_profiled),
         "build_method_bytes": total_method,
         "build_alg_GBps": round(total_method / sec / 1e9, 1),
         "build_alg_frac": round(total_method / sec / 1e9 / HBM_PEAK_GBPS, 4),
-        "build_counter_traffic": counter_summary(args.workload, sec * 1e3),
+        "build_counter_traffic": counter_summary(args.workload, sec * 1e3,
+                                                 sort_as_profiled and build_as_profiled),
         "traced_ms_per_build": round(sum(v[1] for v in trace.values()) / args.steps, 4),
         "kernels": kernels_table(trace, args.steps, alg),
     }
@@ -821,6 +878,9 @@ def main():
         return
     if args.summarize_pmc:
         summarize_pmc(args)
+        return
+    if args.summarize_sq:
+        summarize_sq(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
