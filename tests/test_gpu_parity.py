@@ -268,6 +268,25 @@ def test_mixed_nonunit_box_and_duplicates():
 # determinism and options
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("lookback", [False, True])
+def test_perm_at_every_index_width(lookback):
+    """The radix passes pack key and index into one word once they fit, so the
+    element formats change with the index width bits(N - 1).  N = 2^k and
+    2^k + 1 for k = 0..20 runs every width up to 21 bits: perm must be the stable
+    order of the oracle's keys, bit for bit, counted and with look-back."""
+    rng = np.random.default_rng(61)
+    for k in range(0, 21):
+        for n in sorted({1 << k, (1 << k) + 1}):
+            pos = rng.random((n, 3), dtype=np.float32)
+            pos[: n // 3] = pos[0]  # a third of the particles on one point: equal keys
+            mass = np.full(n, 1.0 / n, np.float32)
+            g = gpu_build(pos, mass, 16, lookback=lookback)
+            _, keys = oracle.keys(pos)
+            want = np.argsort(keys, kind="stable").astype(np.int32)
+            assert np.array_equal(g["perm"], want), (n, lookback)
+            assert np.array_equal(g["key_sorted"], keys[want]), (n, lookback)
+
+
 def test_every_sort_config_identical():
     """Every sort shape, with its default passes (counted on small grids), with
     the look-back kept in every pass and with counting forced, gives the same
