@@ -13,17 +13,18 @@
 //   * keys and payloads are first sorted by digit inside the tile in LDS, then
 //     written so that consecutive lanes store consecutive addresses of a digit
 //     run.
-// The global digit counts come from the key-generation pass, so the keys are
-// read only once per pass.  The index payload of the last pass is `perm`.
+// The global digit counts come from the key-generation pass (and become each
+// digit's base once per build), so the keys are read only once per pass.  The
+// index payload of the last pass is `perm`.
 //
 // By default the passes of a single set are "counted" instead (reduce, then
-// scan; a batch with TB_SORT_COUNTED too): a first
-// kernel reads each element's digit (one byte, left behind by the previous pass
-// or the key kernel) and writes every tile's digit counts, a second turns them
-// into exclusive prefixes over the tiles, and the scatter kernel reads its
-// tile's offsets instead of waiting on its predecessors.  Reading that byte
-// again costs less than the look-back chain across the chip; TB_SORT_LOOKBACK
-// keeps the look-back.
+// scan; a batch with TB_SORT_COUNTED too): a first kernel reads each element's
+// digit (one byte, left behind by the previous pass or the key kernel) and
+// writes every tile's digit counts, a second turns them into exclusive
+// prefixes over the tiles, and the scatter kernel reads its tile's offsets
+// instead of waiting on its predecessors.  Reading that byte again costs less
+// than the look-back chain across the chip; TB_SORT_LOOKBACK keeps the
+// look-back.
 //
 // A batch sorts every set in place: a set's tiles never straddle it, its tiles'
 // look-back chain starts at its own first tile, and its digit runs start at
