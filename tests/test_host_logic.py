@@ -135,6 +135,14 @@ def test_counter_profile_is_ignored_once_sources_change(tmp_path, monkeypatch):
     assert bench.counter_traffic("missing") is None
 
 
+def test_source_hash_ignores_comments_only():
+    src = 'int a = 1; // note\n/* block\n comment */ char s[] = "//x /*y*/";\n\n  int b;  \n'
+    assert bench.code_text(src) == 'int a = 1;\n  char s[] = "//x /*y*/";\n  int b;'
+    same = src.replace("// note", "// another note").replace("block", "other")
+    assert bench.code_text(same) == bench.code_text(src)
+    assert bench.code_text(src.replace("int b;", "int c;")) != bench.code_text(src)
+
+
 def test_committed_counter_profiles_are_well_formed():
     pdir = os.path.join(ROOT, "profiles")
     for f in os.listdir(pdir):
