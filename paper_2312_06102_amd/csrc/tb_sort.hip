@@ -103,12 +103,14 @@ struct SegTiles {
   int32_t nsets;
 };
 
-// Digit counts of one tile of a counted pass: tile t (its elements as the
-// scatter kernel tiles them, SegTiles) writes cnt[d][t].  The digits come from
+// Digit counts of the tiles of a counted pass: tile t (its elements as the
+// scatter kernel tiles them, SegTiles) gets cnt[d][t].  The digits come from
 // dig, written for this pass by the key kernel (first pass) or by the previous
 // pass's scatter, so a count reads one byte an element (two for 9-bit digits)
-// instead of the element.
-template <int BITS, int IPT, int THREADS>
+// instead of the element.  A workgroup counts TPW consecutive tiles at once
+// (every thread's loads of all of them in flight together, one set of per-wave
+// histograms per tile), which halves the waves for about the same wave life.
+template <int BITS, int IPT, int THREADS, int TPW>
 __global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__ dig_v, uint32_t n,
                                                         uint32_t *__restrict__ cnt,
                                                         uint32_t n_tiles, SegTiles seg) {
@@ -116,47 +118,65 @@ __global__ __launch_bounds__(THREADS) void k_tile_count(const void *__restrict__
   constexpr int R = 1 << BITS;
   constexpr int WAVES = THREADS / 64;
   constexpr uint32_t TILE = (uint32_t)THREADS * IPT;
-  __shared__ uint32_t h[WAVES * R];  // one histogram per wave
-  for (int i = threadIdx.x; i < WAVES * R; i += THREADS) h[i] = 0;
+  __shared__ uint32_t h[TPW * WAVES * R];  // per tile, one histogram per wave
+  for (int i = threadIdx.x; i < TPW * WAVES * R; i += THREADS) h[i] = 0;
   const DT *__restrict__ dig = static_cast<const DT *>(dig_v);
-  const uint32_t tile = blockIdx.x;
-  uint32_t base = tile * TILE, hi = n;
-  if (seg.tile_start) {
-    if (tile >= (uint32_t)seg.tile_start[seg.nsets]) return;  // the same for the whole workgroup
-    const int b = seg.tile_set[tile];
-    base = (uint32_t)seg.set_off[b] + (uint32_t)((int64_t)(tile - seg.tile_start[b]) * TILE);
-    hi = (uint32_t)seg.set_off[b + 1];
-  }
-  const uint32_t last = min(base + TILE, hi) - 1u;
-  uint32_t k[IPT];
+  const uint32_t t0 = blockIdx.x * TPW;
+  const uint32_t tiles_here = seg.tile_start ? (uint32_t)seg.tile_start[seg.nsets] : n_tiles;
+  uint32_t base[TPW], last[TPW];
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) k[j] = dig[min(base + j * THREADS + threadIdx.x, last)];
-  __syncthreads();
-  uint32_t *hw = h + (threadIdx.x / 64) * R;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const bool valid = base + j * THREADS + threadIdx.x <= last;
-    const uint32_t d = k[j];
-    // clustered data gives few distinct digits per wave: groups of four or
-    // more equal digits add once (all masks wave-uniform), the rest one by one
-    uint64_t rem = __ballot(valid);
-    while (rem != 0) {
-      const int l = __builtin_ctzll(rem);
-      const uint32_t d0 = __builtin_amdgcn_readlane(d, l);
-      const uint64_t m = __ballot(d == d0) & rem;
-      const uint32_t c = (uint32_t)__popcll(m);
-      if (c < 4) break;
-      if (lane_id() == l) atomicAdd(&hw[d0], c);
-      rem &= ~m;
+  for (int q = 0; q < TPW; ++q) {
+    const uint32_t tile = t0 + q;
+    base[q] = tile * TILE;
+    uint32_t hi = n;
+    if (tile >= tiles_here) {  // past the last tile: counts nothing
+      base[q] = 1u;
+      hi = 1u;
+    } else if (seg.tile_start) {
+      const int b = seg.tile_set[tile];
+      base[q] = (uint32_t)seg.set_off[b] + (uint32_t)((int64_t)(tile - seg.tile_start[b]) * TILE);
+      hi = (uint32_t)seg.set_off[b + 1];
     }
-    if ((rem >> lane_id()) & 1u) atomicAdd(&hw[d], 1u);
+    last[q] = min(base[q] + TILE, hi) - 1u;  // base[q] - 1 when the tile is empty
+  }
+  uint32_t k[TPW][IPT];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q)
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      k[q][j] = dig[min(min(base[q] + j * THREADS + threadIdx.x, last[q]), n - 1u)];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    uint32_t *hw = h + (q * WAVES + threadIdx.x / 64) * R;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const bool valid = base[q] + j * THREADS + threadIdx.x <= last[q] &&
+                         base[q] <= last[q];
+      const uint32_t d = k[q][j];
+      // clustered data gives few distinct digits per wave: groups of four or
+      // more equal digits add once (all masks wave-uniform), the rest one by one
+      uint64_t rem = __ballot(valid);
+      while (rem != 0) {
+        const int l = __builtin_ctzll(rem);
+        const uint32_t d0 = __builtin_amdgcn_readlane(d, l);
+        const uint64_t m = __ballot(d == d0) & rem;
+        const uint32_t c = (uint32_t)__popcll(m);
+        if (c < 4) break;
+        if (lane_id() == l) atomicAdd(&hw[d0], c);
+        rem &= ~m;
+      }
+      if ((rem >> lane_id()) & 1u) atomicAdd(&hw[d], 1u);
+    }
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < R; d += THREADS) {
+  for (int i = threadIdx.x; i < TPW * R; i += THREADS) {
+    const int q = i / R, d = i % R;
+    if (t0 + q >= tiles_here) continue;
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) c += h[w * R + d];
-    cnt[(size_t)d * n_tiles + tile] = c;
+    for (int w = 0; w < WAVES; ++w) c += h[(q * WAVES + w) * R + d];
+    cnt[(size_t)d * n_tiles + t0 + q] = c;
   }
 }
 
@@ -500,8 +520,10 @@ static hipError_t launch_pass_k(const Plan &p, const Work &w, int pass, const tb
     hist = w.seg_base + (size_t)pass * R;
   }
   if constexpr (COUNTED) {
-    k_tile_count<BITS, IPT, THREADS><<<(unsigned)p.sort_tiles, THREADS, 0, s>>>(
-        w.dig, (uint32_t)p.n, w.tile_off, (uint32_t)p.sort_tiles, seg);
+    constexpr int TPW = 2;
+    k_tile_count<BITS, IPT, THREADS, TPW>
+        <<<(unsigned)((p.sort_tiles + TPW - 1) / TPW), THREADS, 0, s>>>(
+            w.dig, (uint32_t)p.n, w.tile_off, (uint32_t)p.sort_tiles, seg);
     // tiles past the batch's last one count nothing and come after every real
     // tile, so the scan's prefixes for the real tiles are unaffected
     k_tile_scan<1024><<<R, 1024, 0, s>>>(w.tile_off, (uint32_t)p.sort_tiles);
