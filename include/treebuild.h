@@ -96,16 +96,17 @@ extern "C" {
  * results; only speed and workspace size differ. */
 #define TB_SORT_CONFIG(k) (((uint32_t)(k)&0xffu) << 8)
 
-/* The radix passes of a single set normally take their tile offsets from a
+/* The radix passes of a single set of at least 512 sort tiles (about 2.9e6
+ * particles with the default shape) normally take their tile offsets from a
  * separate count of every tile's digits (one byte an element, which the
- * previous pass leaves behind); a batch's passes use the decoupled look-back
- * across tiles.  This flag uses the look-back in every pass.  Results are
- * bit-identical either way; the flag exists for tuning and tests. */
+ * previous pass leaves behind); smaller sets and batches use the decoupled
+ * look-back across tiles.  This flag uses the look-back in every pass.  Results
+ * are bit-identical either way; the flag exists for tuning and tests. */
 #define TB_SORT_LOOKBACK (1u << 17)
 
-/* Count the tiles' digits in every radix pass, in a batch too (its offsets
- * then start again at every set); for a single set this is the default.  Not
- * with TB_SORT_LOOKBACK (TB_ERR_ARG).  Results are bit-identical. */
+/* Count the tiles' digits in every radix pass of any build, small sets and
+ * batches too (a batch's offsets then start again at every set).  Not with
+ * TB_SORT_LOOKBACK (TB_ERR_ARG).  Results are bit-identical. */
 #define TB_SORT_COUNTED (1u << 19)
 
 /* Build the cells subtree by subtree (Sec. 2.3.3, eq. 2): the sorted keys are

@@ -66,16 +66,20 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
     else
       p->form[k + 1] = kFormKey64;
   }
-  // The passes of a single set count their tiles' digits first (reduce, then
-  // scan) instead of chaining the tiles through the look-back.  The count reads
-  // one digit byte an element, which the previous pass (or the key kernel) leaves
-  // behind: at N = 2^24 the sort takes 779 us counted against 865 us with
-  // look-back, at 2^26 2.99 ms against 3.25 ms.  A batch looks back (its 31,180
-  // set-aligned tiles: 7.0 ms against 8.7 ms counted) unless TB_SORT_COUNTED asks
-  // for counting; there a tile's offsets start again at its set's first tile.
-  // TB_SORT_LOOKBACK looks back everywhere.
+  // The passes of a single set with at least kCountedMinTiles tiles count their
+  // tiles' digits first (reduce, then scan) instead of chaining the tiles
+  // through the look-back.  The count reads one digit byte an element, which the
+  // previous pass (or the key kernel) leaves behind: at N = 2^24 the sort takes
+  // 779 us counted against 865 us with look-back, at 2^26 2.99 ms against
+  // 3.25 ms; a whole build at 2^22 (745 tiles) 0.636 against 0.649 ms.  Smaller
+  // grids look back: a counted pass is three launches where a look-back pass is
+  // one (2^21, 373 tiles: 0.443 against 0.419 ms).  A batch looks back too (its
+  // 31,180 set-aligned tiles: 7.0 ms against 8.7 ms counted).  TB_SORT_COUNTED
+  // counts every pass of any build, a batch's too (there a tile's offsets start
+  // again at its set's first tile); TB_SORT_LOOKBACK looks back everywhere.
   p->counted = 0;
-  if (!(flags & TB_SORT_LOOKBACK) && (!p->seg || (flags & TB_SORT_COUNTED)))
+  if (!(flags & TB_SORT_LOOKBACK) &&
+      ((flags & TB_SORT_COUNTED) || (!p->seg && p->sort_tiles >= kCountedMinTiles)))
     p->counted = (1u << p->key_passes) - 1u;
   // tiles never straddle two sets: at most one partial tile per set
   p->cell_tiles = (n + kCellTile - 1) / kCellTile + nsets;

@@ -33,6 +33,8 @@ constexpr int kCellTile = kCellThreads * kCellIpt;  // 2048 particles
 
 // The chip's eight XCDs each have their own L2, and workgroups of a launch are
 // dispatched to them in turn (workgroup b to XCD b mod 8).
+// Smallest radix grid whose passes count their tiles rather than look back.
+constexpr int64_t kCountedMinTiles = 512;
 constexpr uint32_t kXcds = 8;
 
 // Parent kernel: children staged per workgroup step.

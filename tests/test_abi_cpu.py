@@ -64,10 +64,12 @@ def test_workspace_bytes_grows_with_n():
     with pytest.raises(tb.TreeBuildArgError):
         tb.tb_workspace_bytes(10, 16, flags=tb.TB_SORT_CONFIG(200))
     # the look-back switch is a known flag; neighbouring bits are not.  Counted
-    # passes (the default on small grids) keep one digit byte per element between
-    # passes, which look-back passes do not need
+    # passes keep one digit byte per element between passes, which look-back
+    # passes (the default on a grid this small) do not need
     lb, dflt = tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_LOOKBACK), tb.tb_workspace_bytes(10000, 16)
-    assert abs((dflt - lb) - 10000) <= 256  # regions are 256-byte aligned
+    cnt = tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED)
+    assert dflt == lb
+    assert abs((cnt - lb) - 10000) <= 256  # regions are 256-byte aligned
     # the subtree-rooted cell build is a known flag too
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SUBTREES) > 0
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED) > 0

@@ -268,23 +268,25 @@ def test_mixed_nonunit_box_and_duplicates():
 # determinism and options
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("lookback", [False, True])
-def test_perm_at_every_index_width(lookback):
+@pytest.mark.parametrize("mode", ["default", "lookback", "counted"])
+def test_perm_at_every_index_width(mode):
     """The radix passes pack key and index into one word once they fit, so the
     element formats change with the index width bits(N - 1).  N = 2^k and
     2^k + 1 for k = 0..20 runs every width up to 21 bits: perm must be the stable
-    order of the oracle's keys, bit for bit, counted and with look-back."""
+    order of the oracle's keys, bit for bit, with the passes as the default
+    picks them, with look-back and counted (TB_SORT_COUNTED)."""
+    lookback, counted = mode == "lookback", mode == "counted"
     rng = np.random.default_rng(61)
     for k in range(0, 21):
         for n in sorted({1 << k, (1 << k) + 1}):
             pos = rng.random((n, 3), dtype=np.float32)
             pos[: n // 3] = pos[0]  # a third of the particles on one point: equal keys
             mass = np.full(n, 1.0 / n, np.float32)
-            g = gpu_build(pos, mass, 16, lookback=lookback)
+            g = gpu_build(pos, mass, 16, lookback=lookback, counted=counted)
             _, keys = oracle.keys(pos)
             want = np.argsort(keys, kind="stable").astype(np.int32)
-            assert np.array_equal(g["perm"], want), (n, lookback)
-            assert np.array_equal(g["key_sorted"], keys[want]), (n, lookback)
+            assert np.array_equal(g["perm"], want), (n, mode)
+            assert np.array_equal(g["key_sorted"], keys[want]), (n, mode)
 
 
 def test_every_sort_config_identical():
