@@ -422,7 +422,8 @@ def counter_traffic(workload: str) -> dict | None:
     return prof
 
 
-def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: str) -> dict:
+def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: str,
+                 index_bits: int = 0) -> dict:
     """Bytes each traced stage must read + write for what it computes (its
     compulsory traffic), per build.
 
@@ -450,7 +451,7 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: st
     mom = 80 if precision == "fp64" else 44
     inner = cells - leaves
     bits = -(-63 // key_passes)  # digit width of these passes
-    forms = sort_forms(n, bits)
+    forms = sort_forms(n, bits, index_bits)
     size = {"key64": 12, "pack64": 8, "pack32": 4, "idx": 4}
     sort = 0
     for p in range(key_passes):
@@ -466,12 +467,15 @@ def kernel_bytes(n: int, cells: int, leaves: int, key_passes: int, precision: st
     }
 
 
-def sort_forms(n: int, bits: int) -> list:
+def sort_forms(n: int, bits: int, index_bits: int = 0) -> list:
     """Element format read by each radix pass, then the last pass's output, as
-    the library plans them: the index needs ib = bits(n - 1) bits; once the key
-    bits not yet consumed (with its leading 1) fit beside it in 64 or 32 bits,
-    key and index travel as one packed word."""
+    the library plans them: the index needs ib = bits(n - 1) bits (or a batch's
+    set-size bound, index_bits, when smaller); once the key bits not yet
+    consumed (with its leading 1) fit beside it in 64 or 32 bits, key and index
+    travel as one packed word."""
     ib = max(1, (n - 1).bit_length())
+    if 0 < index_bits < ib:
+        ib = index_bits
     passes = -(-63 // bits)
     forms = ["key64"]
     for k in range(passes):
@@ -709,15 +713,17 @@ def run_batched(args, tb, dg, torch, np):
     mass = torch.from_numpy(mass_np).to(dev)
     off = torch.from_numpy(offsets_np).to(dev)
     boxes = torch.tensor([[0.0, 0.0, 0.0, 1.0]] * B, dtype=torch.float64, device=dev)
+    # the largest set bounds the sort's index within a set (TB_SET_INDEX_BITS)
+    set_bits = max(1, (int(np.max(sizes)) - 1).bit_length())
     # sort shape: the autotuner's choice on this batch (timed outside the steps)
     t_tune = time.time()
     if args.sort_config is None:
         k = autotune.tune(pos, mass, n_leaf, precision, set_offsets=off, boxes=boxes,
-                          use_cache=False, verbose=True)
+                          use_cache=False, verbose=True, set_index_bits=set_bits)
     else:
         k = args.sort_config
     tune_s = time.time() - t_tune
-    bb = tb.BatchBuilder(n, B, n_leaf, precision, k, dev)
+    bb = tb.BatchBuilder(n, B, n_leaf, precision, k, dev, set_index_bits=set_bits)
     bb.capture(pos, mass, off, boxes)
     sec = time_steps(bb.replay, args.steps, args.warmup)
     print(f"[bench] {args.steps} graph replays, {sec * 1e3:.3f} ms/batch", file=sys.stderr,
@@ -730,7 +736,7 @@ def run_batched(args, tb, dg, torch, np):
     trace = traced_kernels(eager, args.steps, tb)
     bits = tb.tb_sort_configs()[k][0]
     key_passes = (63 + bits - 1) // bits
-    alg = kernel_bytes(n, cells, leaves, key_passes, precision)
+    alg = kernel_bytes(n, cells, leaves, key_passes, precision, set_bits)
     total_method = method_bytes(n, cells, key_passes, precision)
     line = {
         "metric": METRIC, "value": n / sec, "unit": "particles/s", "n_gpus": 1,
@@ -740,6 +746,7 @@ def run_batched(args, tb, dg, torch, np):
         "data": "synthetic",
         "config": {"workload": "batched4096", "description": WORKLOADS["batched4096"], "N": n,
                    "sets": B, "set_size_min": int(sizes.min()), "set_size_max": int(sizes.max()),
+                   "set_index_bits": set_bits,
                    "n_leaf": n_leaf, "precision": precision, "box": "unit cube per set",
                    "sort_config": list(tb.tb_sort_configs()[k]), "autotune_s": round(tune_s, 2),
                    "cells": cells, "leaves": leaves, "launch": "one HIP graph per batch"},

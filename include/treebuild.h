@@ -84,7 +84,8 @@ extern "C" {
 #define TB_STATUS_NONFINITE 1
 #define TB_STATUS_MASS 2
 #define TB_STATUS_INTERNAL 4 /* an index computed on the device fell out of range */
-#define TB_STATUS_SETS 8     /* batch set offsets not 0 .. n_total and non-decreasing */
+#define TB_STATUS_SETS 8     /* batch set offsets not 0 .. n_total and non-decreasing,
+                                or a set larger than TB_SET_INDEX_BITS allows */
 #define TB_STATUS_BOX 16     /* a batch box (device memory) failed the tb_box rules     */
 
 /* Precision flags (bits 0..7). */
@@ -132,6 +133,16 @@ extern "C" {
  * and a child's octant is no longer its key's last digit.  Pass the same bit
  * to tb_gravity for a tree built with it. */
 #define TB_HILBERT (1u << 20)
+
+/* A batch whose every set holds at most 2^k particles (k = 1 .. 31): the radix
+ * sort carries each particle's index within its set (a batch sorts every set in
+ * place) in k bits rather than its position in the batch, so that key and index
+ * pack into one word earlier.  tb_build_batched only; a single build ignores
+ * it.  A set larger than 2^k is reported as TB_STATUS_SETS (TB_ERR_ARG from the
+ * _sync forms); the batch's outputs are then undefined (every set comes out as
+ * a tree of coincident points), but every kernel stays inside its arrays.
+ * Results are bit-identical with and without it. */
+#define TB_SET_INDEX_BITS(k) ((((uint32_t)(k)) & 0x1fu) << 24)
 
 #define TB_MAX_DEPTH 21
 #define TB_MAX_NLEAF 1024 /* largest supported n_leaf */

@@ -64,14 +64,16 @@ def lookup(n: int, nsets: int, n_leaf: int, precision: str = "fp64", device=None
 
 
 def time_config(k: int, pos, mass, n_leaf: int, precision: str, set_offsets=None, boxes=None,
-                box=((0.0, 0.0, 0.0), 1.0), reps: int = 3) -> float:
-    """Milliseconds per build with sort shape k (median of `reps` after one warm-up)."""
+                box=((0.0, 0.0, 0.0), 1.0), reps: int = 3, set_index_bits: int = 0) -> float:
+    """Milliseconds per build with sort shape k (median of `reps` after one warm-up);
+    set_index_bits: the batch's set-size bound, as the builds will use it."""
     n = pos.shape[0]
     if set_offsets is None:
         b = tb.Builder(n, n_leaf, precision, k, pos.device)
         run = lambda: b.launch(pos, mass, box)
     else:
-        b = tb.BatchBuilder(n, set_offsets.shape[0] - 1, n_leaf, precision, k, pos.device)
+        b = tb.BatchBuilder(n, set_offsets.shape[0] - 1, n_leaf, precision, k, pos.device,
+                            set_index_bits=set_index_bits)
         run = lambda: b.launch(pos, mass, set_offsets, boxes)
     run()
     torch.cuda.synchronize()
@@ -90,8 +92,9 @@ def time_config(k: int, pos, mass, n_leaf: int, precision: str, set_offsets=None
 
 def tune(pos, mass, n_leaf: int, precision: str = "fp64", set_offsets=None, boxes=None,
          box=((0.0, 0.0, 0.0), 1.0), reps: int = 3, use_cache: bool = True,
-         path: Optional[str] = None, verbose: bool = False) -> int:
-    """Fastest sort shape for builds like this one; the result is cached."""
+         path: Optional[str] = None, verbose: bool = False, set_index_bits: int = 0) -> int:
+    """Fastest sort shape for builds like this one; the result is cached.
+    set_index_bits: a batch's set-size bound (TB_SET_INDEX_BITS), timed with it."""
     n = pos.shape[0]
     nsets = 1 if set_offsets is None else set_offsets.shape[0] - 1
     path = path or cache_path()
@@ -102,7 +105,8 @@ def tune(pos, mass, n_leaf: int, precision: str = "fp64", set_offsets=None, boxe
             return int(hit["sort_config"])
     results = {}
     for k in range(len(tb.tb_sort_configs())):
-        results[k] = time_config(k, pos, mass, n_leaf, precision, set_offsets, boxes, box, reps)
+        results[k] = time_config(k, pos, mass, n_leaf, precision, set_offsets, boxes, box, reps,
+                                 set_index_bits)
         if verbose:
             print(f"[autotune] {key} config {k} {tb.tb_sort_configs()[k]}: {results[k]:.3f} ms",
                   file=sys.stderr, flush=True)

@@ -52,6 +52,10 @@ int make_plan(int64_t n, int32_t nsets, int32_t n_leaf, uint32_t flags, const So
   // bits + 24 index bits in 8 bytes, and the seventh 8 + 24 bits in 4.
   p->idx_bits = 1;
   while (p->idx_bits < 32 && (int64_t{1} << p->idx_bits) < n) ++p->idx_bits;
+  // a batch sorts its sets in place, so an index within the set suffices: the
+  // caller may bound the set size (TB_SET_INDEX_BITS), which k_setup checks
+  p->set_index_bits = p->seg ? (int)((flags >> 24) & 0x1fu) : 0;
+  if (p->set_index_bits > 0 && p->set_index_bits < p->idx_bits) p->idx_bits = p->set_index_bits;
   // The leading 1 at bit 63 stays in the word (the key kernel's counts of the
   // last 8-bit digit include it), so key >> consumed bits keeps 64 - consumed bits.
   p->form[0] = kFormKey64;
@@ -245,7 +249,8 @@ static int check_sizes(int64_t n, int32_t n_leaf) {
 static int config_from_flags(uint32_t flags, SortConfig *sc) {
   const uint32_t prec = flags & 0xffu;
   if (prec != TB_FP64 && prec != TB_MIXED) return TB_ERR_ARG;
-  if (flags & ~(0xffffu | TB_SORT_LOOKBACK | TB_SUBTREES | TB_SORT_COUNTED | TB_HILBERT))
+  if (flags & ~(0xffffu | TB_SORT_LOOKBACK | TB_SUBTREES | TB_SORT_COUNTED | TB_HILBERT |
+                TB_SET_INDEX_BITS(31)))
     return TB_ERR_ARG;
   if ((flags & TB_SORT_LOOKBACK) && (flags & TB_SORT_COUNTED)) return TB_ERR_ARG;
   const int k = (int)((flags >> 8) & 0xffu);

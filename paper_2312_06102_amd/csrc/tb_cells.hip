@@ -193,9 +193,11 @@ __global__ __launch_bounds__(kCellThreads) void k_reorder(
     int64_t cell_tiles, float4 *__restrict__ sorted, uint64_t *__restrict__ keys,
     uint64_t *__restrict__ key_out, float *__restrict__ pos_sorted,
     float *__restrict__ mass_sorted, uint16_t *__restrict__ ad, uint32_t *__restrict__ tile_cnt,
-    int hilbert, int32_t *__restrict__ status_word) {
+    int hilbert, const uint32_t *__restrict__ oversize, int32_t *__restrict__ status_word) {
   extern __shared__ __align__(16) unsigned char lds[];
   const WindowLds s = carve_window(lds, nl);
+  // a batch set over the caller's index bound: every particle gets the root key
+  const bool flat = oversize && *oversize != 0u;
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= tile_start[nsets]) return;
   const TileRange tr = tile_range(tile, tile_start, tile_set, set_off);
@@ -234,8 +236,10 @@ __global__ __launch_bounds__(kCellThreads) void k_reorder(
       const int64_t g = ws + i;
       const bool in = i < wn && g >= tr.S && g < tr.E;
       const uint64_t key =
-          in ? particle_key(rec[r].x, rec[r].y, rec[r].z, lo0, lo1, lo2, scale, hilbert != 0)
-             : 0ull;
+          !in ? 0ull
+          : flat
+              ? 1ull << 63
+              : particle_key(rec[r].x, rec[r].y, rec[r].z, lo0, lo1, lo2, scale, hilbert != 0);
       if (i < wn) s.keys[i] = key;
       if (g >= t0 && g < t1 && i < wn) {
         sorted[g] = rec[r];
@@ -763,7 +767,8 @@ hipError_t launch_reorder(const Plan &p, const Work &w, const tb_tree &out, hipS
   k_reorder<<<(unsigned)p.cell_tiles, kCellThreads, window_lds_bytes(p.n_leaf), s>>>(
       out.perm, w.packed, p.n, p.n_leaf, w.tile_start, w.tile_set, w.set_off, p.nsets, w.box,
       p.cell_tiles, w.sorted, sorted_keys(p, w), out.key_sorted, out.pos_sorted, out.mass_sorted,
-      w.ad, w.cell_cnt, (p.flags & TB_HILBERT) ? 1 : 0, out.status);
+      w.ad, w.cell_cnt, (p.flags & TB_HILBERT) ? 1 : 0,
+      p.set_index_bits ? w.counters + kOversizeCounter : nullptr, out.status);
   return hipGetLastError();
 }
 

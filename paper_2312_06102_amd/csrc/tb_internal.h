@@ -47,6 +47,10 @@ constexpr int kBboxChunk = 65536;
 // Largest number of sets in one batch.
 constexpr int kMaxSetsLds = TB_MAX_SETS;
 
+// counters[kOversizeCounter]: nonzero when a batch set is larger than the
+// bound TB_SET_INDEX_BITS gives (set by the setup, read by the reorder)
+constexpr int kOversizeCounter = 16;
+
 // counters[kUpperCounter + d]: number of cells above the blocks at depth d
 constexpr int kUpperCounter = 32;
 
@@ -89,7 +93,9 @@ struct Plan {
   SortConfig sort;
   int key_passes;   // radix passes over the 63 key bits
   uint32_t counted; // bit k: key pass k takes its tile offsets from a count and a scan
-  int idx_bits;     // bits of the largest index, n - 1 (at least 1)
+  int idx_bits;     // bits of the largest index, n - 1 (at least 1); in a batch the index
+                    // is the position within the set
+  int set_index_bits;  // batch: TB_SET_INDEX_BITS (0: none), checked against every set
   uint8_t form[kMaxKeyPasses + 1];  // form[k]: what pass k reads; form[k + 1]: what it writes
   bool seg;         // batch of several sets: every radix pass sorts each set in place
                     // (tiles never straddle a set; each set has its own digit bases)

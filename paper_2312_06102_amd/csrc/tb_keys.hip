@@ -119,8 +119,8 @@ __device__ __forceinline__ bool box_valid(const double *b) {
 __global__ __launch_bounds__(kSetupThreads) void k_setup(
     int64_t *__restrict__ set_off, int32_t nsets, int64_t n, int64_t *__restrict__ tile_start,
     int64_t *__restrict__ chunk_start, int64_t *__restrict__ sort_tile_start, int sort_tile_keys,
-    int with_chunks, double *__restrict__ box, int check_boxes,
-    int32_t *__restrict__ status_word) {
+    int with_chunks, double *__restrict__ box, int check_boxes, int max_set_bits,
+    uint32_t *__restrict__ oversize, int32_t *__restrict__ status_word) {
   __shared__ uint32_t s_w[3][kSetupThreads / 64];
   __shared__ uint64_t s_carry[3];
   __shared__ int s_bad;
@@ -134,6 +134,22 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup(
   if (s_bad) {
     for (int b = threadIdx.x; b <= nsets; b += kSetupThreads) set_off[b] = b == nsets ? n : 0;
     if (threadIdx.x == 0) atomicOr(status_word, TB_STATUS_SETS);
+  }
+  if (max_set_bits > 0) {
+    // A set larger than the caller's bound (checked on the offsets as they now
+    // stand): its indices do not fit in the sort's index bits, so its order and
+    // the keys the cell stages would read from it are not consistent.  It is
+    // reported, and the flag makes the reorder give every particle the same key,
+    // which turns each set into coincident points: a tree every kernel handles
+    // and C_max bounds.
+    __syncthreads();
+    bool big = false;
+    for (int b = threadIdx.x; b < nsets; b += kSetupThreads)
+      big |= set_off[b + 1] - set_off[b] > (int64_t{1} << max_set_bits);
+    if (big) {
+      atomicOr(status_word, TB_STATUS_SETS);
+      *oversize = 1u;
+    }
   }
   // a caller-given box that is not usable is reported and replaced by the unit
   // cube, so that the key arithmetic stays finite
@@ -235,7 +251,8 @@ hipError_t launch_setup(const Plan &p, const Work &w, const BatchIn &in, int32_t
   const bool with_chunks = in.auto_box;
   k_setup<<<1, kSetupThreads, 0, s>>>(w.set_off, p.nsets, p.n, w.tile_start, w.chunk_start,
                                       p.seg ? w.seg_tile_start : nullptr, p.sort.tile(),
-                                      with_chunks ? 1 : 0, w.box, in.dev_boxes ? 1 : 0, status);
+                                      with_chunks ? 1 : 0, w.box, in.dev_boxes ? 1 : 0,
+                                      p.set_index_bits, w.counters + kOversizeCounter, status);
   const int64_t n_counts = p.seg ? (int64_t)p.nsets * p.key_passes * p.sort.radix() : 0;
   const int64_t entries = p.cell_tiles + (with_chunks ? p.bbox_chunks : 0) +
                           (p.seg ? p.sort_tiles : 0) + n_counts;

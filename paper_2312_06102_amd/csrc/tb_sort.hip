@@ -238,12 +238,14 @@ struct Sweep {
 // Wave-striped load of a tile: item j of lane l is element wbase + j*64, with
 // wbase = lo + wave*64*IPT + l.  Loads are branch-free (indices past the tile
 // are clamped and the items masked later) so that all of them are in flight
-// together.  v: the separate index of kFormKey64 (the position when vin is NULL).
+// together.  v: the separate index of kFormKey64; when vin is NULL, the position
+// less vbase (the set's first position in a batch, whose sort carries indices
+// within the set).
 template <class S, int IPT>
 __device__ __forceinline__ void sweep_load(const typename S::KI *__restrict__ kin,
                                            const uint32_t *__restrict__ vin, uint32_t wbase,
-                                           uint32_t last, typename S::KI (&k)[IPT],
-                                           uint32_t (&v)[IPT]) {
+                                           uint32_t last, uint32_t vbase,
+                                           typename S::KI (&k)[IPT], uint32_t (&v)[IPT]) {
 #pragma unroll
   for (int j = 0; j < IPT; ++j) k[j] = kin[min(wbase + j * 64, last)];
   if constexpr (!S::PIN) {
@@ -252,7 +254,7 @@ __device__ __forceinline__ void sweep_load(const typename S::KI *__restrict__ ki
       for (int j = 0; j < IPT; ++j) v[j] = vin[min(wbase + j * 64, last)];
     } else {
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64;
+      for (int j = 0; j < IPT; ++j) v[j] = wbase + j * 64 - vbase;
     }
   }
 }
@@ -358,7 +360,8 @@ __device__ __forceinline__ void sweep_rank(typename S::Lds &L, const typename S:
 
 // Coalesced scatter of a tile sorted in LDS (L.goff set, behind a barrier):
 // consecutive lanes write consecutive slots of a digit run, inside [set_lo, hi).
-// A packed output word holds the key bits above this digit over the index.
+// A packed output word holds the key bits above this digit over the index; the
+// last pass writes the index plus set_lo (a batch's indices are within the set).
 // dig_out (a counted next pass): the next pass's digit of each element, at its
 // output position.
 template <class S, int BITS, int THREADS, int FOUT>
@@ -386,7 +389,7 @@ __device__ __forceinline__ void sweep_scatter(const typename S::Lds &L, uint32_t
       continue;
     }
     if constexpr (FOUT == kFormIdx) {
-      vout[gp] = idx;
+      vout[gp] = idx + set_lo;
     } else {
       // the key bits above this digit: the next pass's digit at their bottom
       const uint64_t rest = (uint64_t)kk >> (shift + BITS);
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
   const uint32_t wbase = lo + (uint32_t)(threadIdx.x / 64) * 64u * IPT + (uint32_t)lane_id();
   KI k[IPT];
   uint32_t v[IPT];
-  sweep_load<S, IPT>(kin, vin, wbase, last, k, v);
+  sweep_load<S, IPT>(kin, vin, wbase, last, set_lo, k, v);
 
   uint32_t tcnt[DPT], trun_d[DPT];
   sweep_rank<S, BITS, IPT, THREADS, !COUNTED>(L, k, v, wbase, last, shift, status, tile, first,

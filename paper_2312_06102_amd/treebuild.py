@@ -47,6 +47,12 @@ TB_SORT_LOOKBACK = 1 << 17  # keep the decoupled look-back in every radix pass
 TB_SUBTREES = 1 << 18  # build the cells subtree by subtree (Sec. 2.3.3, eq. 2)
 TB_SORT_COUNTED = 1 << 19  # count the tiles' digits in every radix pass
 TB_HILBERT = 1 << 20  # Peano-Hilbert keys (footnote of Sec. 2.2)
+
+
+def TB_SET_INDEX_BITS(k: int) -> int:
+    """Batches: every set holds at most 2^k particles (the sort carries indices
+    within the set in k bits)."""
+    return (int(k) & 0x1F) << 24
 CURVES = ("morton", "hilbert")
 
 
@@ -562,13 +568,19 @@ class BatchBuilder(_Graphable):
     def __init__(self, n_total: int, nsets: int, n_leaf: int = 16, precision: str = "fp64",
                  sort_config: int = 0, device="cuda", sorted_particles: bool = False,
                  sorted_keys: bool = False, lookback: bool = False, subtrees: bool = False,
-                 counted: bool = False, curve: str = "morton"):
+                 counted: bool = False, curve: str = "morton", set_index_bits: int = 0):
+        """set_index_bits: k > 0 promises that every set holds at most 2^k
+        particles (TB_SET_INDEX_BITS); a larger set is reported as
+        TB_STATUS_SETS."""
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
+        if not 0 <= int(set_index_bits) <= 31:
+            raise ValueError("set_index_bits must be 0 (no bound) or 1 .. 31")
         self.n, self.nsets, self.n_leaf, self.precision = int(n_total), int(nsets), int(n_leaf), precision
         self.flags = ((TB_FP64 if precision == "fp64" else TB_MIXED) | TB_SORT_CONFIG(sort_config)
                       | (TB_SORT_LOOKBACK if lookback else 0) | (TB_SUBTREES if subtrees else 0)
-                      | (TB_SORT_COUNTED if counted else 0) | _curve_flag(curve))
+                      | (TB_SORT_COUNTED if counted else 0) | _curve_flag(curve)
+                      | TB_SET_INDEX_BITS(set_index_bits))
         self.ws_bytes = tb_workspace_bytes_batched(self.n, self.nsets, self.n_leaf, self.flags)
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = TreeBuffers.allocate(self.n, self.n_leaf, precision, device, sorted_particles,
@@ -625,10 +637,11 @@ def build_batched(pos: torch.Tensor, mass: torch.Tensor, set_offsets: torch.Tens
                   n_leaf: int = 16, boxes: Optional[torch.Tensor] = None,
                   precision: str = "fp64", sort_config: int = 0, sorted_particles: bool = False,
                   sorted_keys: bool = False, lookback: bool = False,
-                  subtrees: bool = False, counted: bool = False, curve: str = "morton") -> dict:
+                  subtrees: bool = False, counted: bool = False, curve: str = "morton",
+                  set_index_bits: int = 0) -> dict:
     """One-shot batched build; returns device tensors trimmed to n_cells."""
     b = BatchBuilder(pos.shape[0], set_offsets.shape[0] - 1, n_leaf, precision, sort_config,
                      pos.device, sorted_particles, sorted_keys, lookback, subtrees, counted,
-                     curve)
+                     curve, set_index_bits)
     b.launch(pos, mass, set_offsets, boxes)
     return b.result()

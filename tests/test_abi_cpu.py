@@ -76,6 +76,11 @@ def test_workspace_bytes_grows_with_n():
     with pytest.raises(tb.TreeBuildArgError):
         tb.tb_workspace_bytes(10000, 16, tb.TB_SORT_COUNTED | tb.TB_SORT_LOOKBACK)
     assert tb.tb_workspace_bytes(10000, 16, tb.TB_HILBERT) > 0
+    # the set-size bound of a batch is a known flag (bits 24..28)
+    assert tb.tb_workspace_bytes_batched(10000, 8, 16, tb.TB_SET_INDEX_BITS(12)) > 0
+    m = re.search(r"#define TB_SET_INDEX_BITS\(k\) \(\(\(\(uint32_t\)\(k\)\) & 0x1fu\) << 24\)",
+                  open(HEADER).read())
+    assert m and tb.TB_SET_INDEX_BITS(12) == 12 << 24
     for bit in (16, 21, 31):
         with pytest.raises(tb.TreeBuildArgError):
             tb.tb_workspace_bytes(10, 16, flags=1 << bit)

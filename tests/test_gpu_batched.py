@@ -237,13 +237,13 @@ def test_duplicate_heavy_sets():
 # errors found on the device
 # --------------------------------------------------------------------------
 
-def _raw_batched_sync(pos, mass, offsets, boxes, n_leaf=16):
+def _raw_batched_sync(pos, mass, offsets, boxes, n_leaf=16, **kw):
     p = torch.from_numpy(pos).cuda()
     m = torch.from_numpy(mass).cuda()
     off = torch.tensor(offsets, dtype=torch.int64, device="cuda")
     B = len(offsets) - 1
     bx = None if boxes is None else torch.tensor(boxes, dtype=torch.float64, device="cuda")
-    bb = tb.BatchBuilder(pos.shape[0], B, n_leaf)
+    bb = tb.BatchBuilder(pos.shape[0], B, n_leaf, **kw)
     rc = tb.tb_build_batched_sync(p.data_ptr(), m.data_ptr(), pos.shape[0], B, off.data_ptr(),
                                   n_leaf, None if bx is None else bx.data_ptr(), bb.flags,
                                   bb.workspace.data_ptr(), bb.ws_bytes, bb._struct,
@@ -265,6 +265,49 @@ def test_bad_offsets_reported():
         assert int(bb.cell_offsets[-1].item()) == int(bb.out.n_cells.item()) > 0
     rc, _ = _raw_batched_sync(pos, mass, [0, 2000, 2000, 5000], None)
     assert rc == tb.TB_OK
+
+
+@pytest.mark.parametrize("mode", ["default", "counted"])
+def test_set_index_bits(mode):
+    """TB_SET_INDEX_BITS: with every set's size bounded (here exactly, 2^17 for
+    the largest set of 100,003), the sort carries indices within the set in 17
+    bits and packs earlier; the batch must be bit-identical to the unbounded
+    build and agree with the oracle.  A bound one bit too small (the set of
+    100,003 over 2^16, the set of 65,536 exactly at it) is reported, every set
+    comes out as coincident points, and the next build on the same workspace,
+    with every set inside the bound, is exact again."""
+    sizes = uneven_sizes()
+    pos, mass, offsets = plummer_batch(sizes, seed=41)
+    bits = int(sizes.max() - 1).bit_length()
+    counted = mode == "counted"
+    g = batch_build(pos, mass, offsets, 16, set_index_bits=bits, counted=counted)
+    r = batch_build(pos, mass, offsets, 16, counted=counted)
+    compare_structure(g, r)
+    assert np.array_equal(g["com"], r["com"]) and np.array_equal(g["quad"], r["quad"])
+    check_against_oracle(pos, mass, offsets, 16, g, range(len(sizes)))
+    rc, _ = _raw_batched_sync(pos, mass, offsets, None, set_index_bits=bits)
+    assert rc == tb.TB_OK
+
+    print(f"[set bits] {bits - 1} for a set of {int(sizes.max())}", flush=True)
+    bb = tb.BatchBuilder(pos.shape[0], len(sizes), 16, set_index_bits=bits - 1, counted=counted)
+    p, m = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+    bb.launch(p, m, torch.from_numpy(np.asarray(offsets, np.int64)).cuda())
+    with pytest.raises(tb.TreeBuildError) as err:
+        bb.result()
+    assert err.value.code == tb.TB_ERR_ARG
+    per_set = np.diff(bb.cell_offsets.cpu().numpy())
+    assert np.array_equal(per_set, np.where(sizes == 0, 0, np.where(sizes <= 16, 1, 22)))
+    big = int(np.argmax(sizes))
+    sizes2 = sizes.copy()
+    sizes2[big], sizes2[big + 1] = 50000, sizes[big] + sizes[big + 1] - 50000
+    assert sizes2.max() <= 1 << (bits - 1)
+    off2 = np.concatenate([[0], np.cumsum(sizes2)]).astype(np.int64)
+    print(f"[set bits] {bits - 1} then sets of at most {int(sizes2.max())}", flush=True)
+    bb.launch(p, m, torch.from_numpy(off2).cuda())
+    g2 = _to_np(bb.result())
+    r2 = batch_build(pos, mass, off2, 16, counted=counted)
+    compare_structure(g2, r2)
+    assert np.array_equal(g2["com"], r2["com"]) and np.array_equal(g2["quad"], r2["quad"])
 
 
 def test_bad_device_box_reported():

@@ -53,6 +53,17 @@ def test_sort_bytes_follow_element_formats():
     assert bench.sort_forms(1 << 24, 9) == ["key64"] * 3 + ["pack64"] * 4 + ["idx"]
 
 
+def test_batch_set_index_bits_pack_earlier():
+    # 1.6e8 particles need 28 index bits; sets of at most 2^18 need 18
+    n = 159_638_865
+    assert bench.sort_forms(n, 8) == ["key64"] * 4 + ["pack64"] * 4 + ["idx"]
+    assert bench.sort_forms(n, 8, 18) == ["key64"] * 3 + ["pack64"] * 4 + ["pack32", "idx"]
+    assert bench.sort_forms(n, 8, 30) == bench.sort_forms(n, 8)  # a looser bound changes nothing
+    full = bench.kernel_bytes(n, 0, 0, 8, "fp64")["sort_pass"] / n
+    tight = bench.kernel_bytes(n, 0, 0, 8, "fp64", 18)["sort_pass"] / n
+    assert (full, tight) == (148, 132)
+
+
 SUPPORTED_PAIRS = {("key64", "key64"), ("key64", "pack64"), ("pack64", "pack64"),
                    ("pack64", "pack32"), ("pack64", "idx"), ("pack32", "pack32"),
                    ("pack32", "idx")}
