@@ -310,6 +310,24 @@ def test_set_index_bits(mode):
     assert np.array_equal(g2["com"], r2["com"]) and np.array_equal(g2["quad"], r2["quad"])
 
 
+@pytest.mark.parametrize("variant", ["subtrees", "hilbert", "mixed", "nleaf1"])
+def test_set_index_bits_other_paths(variant):
+    """The set bound changes only the sort's element formats: with the subtree
+    blocks, Hilbert keys, the mixed-precision moments or n_leaf = 1 the bounded
+    batch is bit-identical to the unbounded one, sorted keys included."""
+    sizes = uneven_sizes()
+    pos, mass, offsets = plummer_batch(sizes, seed=42)
+    bits = int(sizes.max() - 1).bit_length()
+    kw = {"subtrees": dict(subtrees=True), "hilbert": dict(curve="hilbert"),
+          "mixed": dict(precision="mixed"), "nleaf1": {}}[variant]
+    nl = 1 if variant == "nleaf1" else 16
+    g = batch_build(pos, mass, offsets, nl, set_index_bits=bits, **kw)
+    r = batch_build(pos, mass, offsets, nl, **kw)
+    compare_structure(g, r)
+    assert np.array_equal(g["com"], r["com"]) and np.array_equal(g["quad"], r["quad"])
+    assert np.array_equal(g["key_sorted"], r["key_sorted"])
+
+
 def test_bad_device_box_reported():
     rng = _rng(39)
     pos = rng.random((3000, 3), dtype=np.float32)
