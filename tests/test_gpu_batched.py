@@ -328,6 +328,27 @@ def test_set_index_bits_other_paths(variant):
     assert np.array_equal(g["key_sorted"], r["key_sorted"])
 
 
+@pytest.mark.parametrize("case", ["k1", "k31"])
+def test_set_index_bits_extremes(case):
+    """The ends of the bound's range: k = 1 on 3000 sets of 0 to 2 particles
+    (a 1-bit index packs beside the key from the first pass), and k = 31 on the
+    uneven sizes (later packing than the batch's own 28 bits)."""
+    if case == "k1":
+        sizes = _rng(43).integers(0, 3, 3000).astype(np.int64)
+        bits = 1
+    else:
+        sizes = uneven_sizes()
+        bits = 31
+    pos, mass, offsets = plummer_batch(sizes, seed=44)
+    g = batch_build(pos, mass, offsets, 1, set_index_bits=bits)
+    r = batch_build(pos, mass, offsets, 1)
+    compare_structure(g, r)
+    assert np.array_equal(g["com"], r["com"]) and np.array_equal(g["quad"], r["quad"])
+    assert np.array_equal(g["key_sorted"], r["key_sorted"])
+    if case == "k1":
+        check_against_oracle(pos, mass, offsets, 1, g, range(0, len(sizes), 7))
+
+
 def test_bad_device_box_reported():
     rng = _rng(39)
     pos = rng.random((3000, 3), dtype=np.float32)
