@@ -13,6 +13,7 @@ import torch
 
 import oracle
 import treecheck as tc
+from paper_2312_06102_amd import autotune
 from paper_2312_06102_amd import datagen as dg
 from paper_2312_06102_amd import treebuild as tb
 from test_gpu_batched import check_against_oracle, set_view
@@ -106,12 +107,26 @@ def test_full_size_batched4096_graph():
     m = torch.from_numpy(mass).cuda()
     off = torch.from_numpy(offsets).cuda()
     boxes = torch.tensor([[0.0, 0.0, 0.0, 1.0]] * B, dtype=torch.float64, device="cuda")
-    bb = tb.BatchBuilder(N, B, 16, sorted_keys=True)
+    # the configuration the benchmark times: the autotuner's sort shape and the
+    # set-size bound of the largest set
+    set_bits = max(1, (int(sizes.max()) - 1).bit_length())
+    k = autotune.tune(p, m, 16, "fp64", set_offsets=off, boxes=boxes, use_cache=False,
+                      set_index_bits=set_bits)
+    print(f"[full batch] sort config {k}, set index bits {set_bits}", flush=True)
+    bb = tb.BatchBuilder(N, B, 16, "fp64", k, sorted_keys=True, set_index_bits=set_bits)
     bb.capture(p, m, off, boxes)
     bb.replay()
     bb.replay()
-    g = _np(bb.result())
-    print(f"[full batch] built, {g['n_cells']} cells", flush=True)
+    res = bb.result()
+    # bit-identical to the default shape without the bound
+    ref = tb.build_batched(p, m, off, 16, boxes, sorted_keys=True)
+    for name in ("perm", "cell_key", "cell_level", "cell_first", "cell_count", "child_ptr",
+                 "com", "quad", "level_offset", "cell_offsets", "key_sorted"):
+        assert torch.equal(res[name], ref[name]), name
+    assert res["n_cells"] == ref["n_cells"]
+    del ref
+    g = _np(res)
+    print(f"[full batch] built, {g['n_cells']} cells, equal to the unbounded default", flush=True)
     co = g["cell_offsets"]
     assert co[0] == 0 and co[-1] == g["n_cells"] and np.all(np.diff(co) > 0)
     assert np.array_equal(g["level_offset"][:, 0], co[:-1])
