@@ -314,7 +314,8 @@ def test_set_index_bits(mode):
 def test_set_index_bits_other_paths(variant):
     """The set bound changes only the sort's element formats: with the subtree
     blocks, Hilbert keys, the mixed-precision moments or n_leaf = 1 the bounded
-    batch is bit-identical to the unbounded one, sorted keys included."""
+    batch is bit-identical to the unbounded one, sorted keys included; a bound
+    one bit too small is reported and gives coincident points on each path."""
     sizes = uneven_sizes()
     pos, mass, offsets = plummer_batch(sizes, seed=42)
     bits = int(sizes.max() - 1).bit_length()
@@ -326,6 +327,16 @@ def test_set_index_bits_other_paths(variant):
     compare_structure(g, r)
     assert np.array_equal(g["com"], r["com"]) and np.array_equal(g["quad"], r["quad"])
     assert np.array_equal(g["key_sorted"], r["key_sorted"])
+    # a bound one bit too small on this path too: reported, coincident points
+    print(f"[set bits] {variant}: {bits - 1} for a set of {int(sizes.max())}", flush=True)
+    bb = tb.BatchBuilder(pos.shape[0], len(sizes), nl, set_index_bits=bits - 1, **kw)
+    bb.launch(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda(),
+              torch.from_numpy(np.asarray(offsets, np.int64)).cuda())
+    with pytest.raises(tb.TreeBuildError) as err:
+        bb.result()
+    assert err.value.code == tb.TB_ERR_ARG
+    per_set = np.diff(bb.cell_offsets.cpu().numpy())
+    assert np.array_equal(per_set, np.where(sizes == 0, 0, np.where(sizes <= nl, 1, 22)))
 
 
 @pytest.mark.parametrize("case", ["k1", "k31"])
