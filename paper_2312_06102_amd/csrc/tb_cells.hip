@@ -71,21 +71,27 @@ struct EmitLds {
   uint32_t *lvl;       // [kLevels]       per-depth base of this tile
   uint16_t *off;       // [kLevels][kCellThreads] next cell slot per depth per thread
   float4 *rec;         // [T + NL]        sorted (x, y, z, m) of [t0, t1 + NL); stored once
-                       //                 the cells are placed, over the dead `off`
+                       //                 the cells are placed, over the dead `off` and `leaf`
   uint32_t *leaf;      // [T]             leaf starting in the tile: local first particle |
-                       //                 depth << 11 | slot within its depth << 16
+                       //                 depth << 11 | slot within its depth << 16; beside
+                       //                 `off`, and read into registers before `rec` is stored
   uint8_t *heads;      // [T / 8]         bit li: particle t0 + li starts a leaf
   uint32_t *nleaf;     // [1]
 };
 
+__host__ __device__ inline size_t emit_off_bytes() {
+  return round16((size_t)kLevels * kCellThreads * 2);
+}
+
 __host__ __device__ inline size_t emit_union_bytes(int nl) {
-  const size_t off = (size_t)kLevels * kCellThreads * 2, rec = (size_t)(kCellTile + nl) * 16;
-  return round16(off > rec ? off : rec);
+  const size_t cells = emit_off_bytes() + (size_t)kCellTile * 4;  // off, then leaf
+  const size_t rec = (size_t)(kCellTile + nl) * 16;
+  return round16(cells > rec ? cells : rec);
 }
 
 __host__ __device__ inline size_t emit_lds_bytes(int nl) {
   return round16(kCellTile + nl) + round16(kCellTile) + round16((size_t)kWaves * kLevelWords * 4) +
-         round16(kLevels * 4) + emit_union_bytes(nl) + (size_t)kCellTile * 4 + kCellTile / 8 + 16;
+         round16(kLevels * 4) + emit_union_bytes(nl) + kCellTile / 8 + 16;
 }
 
 __device__ inline EmitLds carve_emit(unsigned char *base, int nl) {
@@ -98,13 +104,13 @@ __device__ inline EmitLds carve_emit(unsigned char *base, int nl) {
   base += round16((size_t)kWaves * kLevelWords * 4);
   s.lvl = reinterpret_cast<uint32_t *>(base);
   base += round16(kLevels * 4);
-  // the per-depth cursors are dead once the cells are placed; the particle
-  // records take their place for the moment phase
+  // the per-depth cursors and the leaf list are dead once the cells are placed
+  // (each thread keeps its leaf entries in registers); the particle records
+  // take their place for the moment phase
   s.off = reinterpret_cast<uint16_t *>(base);
+  s.leaf = reinterpret_cast<uint32_t *>(base + emit_off_bytes());
   s.rec = reinterpret_cast<float4 *>(base);
   base += emit_union_bytes(nl);
-  s.leaf = reinterpret_cast<uint32_t *>(base);
-  base += (size_t)kCellTile * 4;
   s.heads = base;
   base += kCellTile / 8;
   s.nleaf = reinterpret_cast<uint32_t *>(base);
@@ -646,9 +652,19 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     }
   }
   __syncthreads();
+  // the leaf list shares its space with the records: each thread keeps its
+  // entries (at most kCellIpt: a tile starts at most one leaf a particle)
+  const uint32_t nlv = *s.nleaf;
+  uint32_t my_leaf[kCellIpt];
+#pragma unroll
+  for (int k = 0; k < kCellIpt; ++k) {
+    const uint32_t x = threadIdx.x + (uint32_t)k * kCellThreads;
+    my_leaf[k] = x < nlv ? s.leaf[x] : 0u;
+  }
+  __syncthreads();
 
-  // the cursors are dead: the particle records (tile and halo) take their
-  // place, in batched loads
+  // the cursors and the leaf list are dead: the particle records (tile and
+  // halo) take their place, in batched loads
   for (int x0 = 0; x0 < span; x0 += kRecBatch * kCellThreads) {
     float4 r[kRecBatch];
 #pragma unroll
@@ -663,13 +679,17 @@ __global__ __launch_bounds__(kCellThreads) void k_cell_emit(
     }
   }
   __syncthreads();
-  const uint32_t nlv = *s.nleaf;
 
   // leaf moments: one lane per leaf, particles read from LDS
   const double lo[3] = {box[4 * tr.b + 0], box[4 * tr.b + 1], box[4 * tr.b + 2]};
   const double side = box[4 * tr.b + 3];
-  for (uint32_t x = threadIdx.x; x < nlv; x += kCellThreads) {
-    const uint32_t le = s.leaf[x];
+#pragma unroll 1
+  for (int k = 0; k < kCellIpt; ++k) {
+    if (threadIdx.x + (uint32_t)k * kCellThreads >= nlv) break;
+    // this thread's next entry; the rest move down (constant register indices)
+    const uint32_t le = my_leaf[0];
+#pragma unroll
+    for (int j = 0; j + 1 < kCellIpt; ++j) my_leaf[j] = my_leaf[j + 1];
     const int li = le & 0x7ff;
     const int dl = (le >> 11) & 31;
     if (dl > kMaxDepth || li >= T) {  // cannot happen: entries come from the loop above
