@@ -409,9 +409,12 @@ __device__ __forceinline__ void sweep_scatter(const typename S::Lds &L, uint32_t
 // position) and the output of kFormIdx.  shift: the digit's bit offset in the
 // input word; ib: idx_bits.  hist: the pass's digit bases, where each digit's
 // run starts in the output [radix]; a batch has a row per set (set b at b *
-// base_stride).
+// base_stride).  A pass over 32-bit packed words with 8-bit digits needs little
+// LDS, so its registers are held to six waves a SIMD (80 VGPRs, a 12-byte spill
+// a lane): three 512-thread workgroups a CU instead of two, 47.6 -> 43.8 us at
+// 2^24 (the wider formats' tiles take more LDS, which caps them first).
 template <int BITS, int IPT, int THREADS, int FIN, int FOUT, bool COUNTED, bool SEG>
-__global__ __launch_bounds__(THREADS) void k_onesweep(
+__global__ __launch_bounds__(THREADS, (FIN == kFormPack32 && BITS == 8) ? 6 : 1) void k_onesweep(
     const void *__restrict__ kin_v, void *__restrict__ kout_v,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
     int ib, const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
