@@ -409,12 +409,26 @@ __device__ __forceinline__ void sweep_scatter(const typename S::Lds &L, uint32_t
 // position) and the output of kFormIdx.  shift: the digit's bit offset in the
 // input word; ib: idx_bits.  hist: the pass's digit bases, where each digit's
 // run starts in the output [radix]; a batch has a row per set (set b at b *
-// base_stride).  A pass over 32-bit packed words with 8-bit digits needs little
-// LDS, so its registers are held to six waves a SIMD (80 VGPRs, a 12-byte spill
-// a lane): three 512-thread workgroups a CU instead of two, 47.6 -> 43.8 us at
-// 2^24 (the wider formats' tiles take more LDS, which caps them first).
+// base_stride).
+//
+// Waves a SIMD a pass's registers must allow (the second launch bound; 1: no
+// limit).  With 8-bit digits a pass over 32-bit packed words needs little LDS,
+// so held to six waves (80 VGPRs, a 12-byte spill a lane) it runs three
+// 512-thread workgroups a CU instead of two: 47.6 -> 43.8 us at 2^24.  So does
+// a batch's look-back pass over 64-bit packed words with 5120-key tiles (a
+// 28-byte spill; the 4096-set batch's sort 6.45 -> 6.34 ms), while the counted
+// single-set pass loses more to its spill than it gains (sort 0.79 -> 0.87 ms)
+// and larger tiles leave no LDS for a third workgroup.
+template <int BITS, int IPT, int THREADS, int FIN, bool COUNTED, bool SEG>
+constexpr int sweep_waves() {
+  if (BITS != 8) return 1;
+  if (FIN == kFormPack32) return 6;
+  if (FIN == kFormPack64 && SEG && !COUNTED && THREADS == 512 && THREADS * IPT <= 5120) return 6;
+  return 1;
+}
+
 template <int BITS, int IPT, int THREADS, int FIN, int FOUT, bool COUNTED, bool SEG>
-__global__ __launch_bounds__(THREADS, (FIN == kFormPack32 && BITS == 8) ? 6 : 1) void k_onesweep(
+__global__ __launch_bounds__(THREADS, (sweep_waves<BITS, IPT, THREADS, FIN, COUNTED, SEG>())) void k_onesweep(
     const void *__restrict__ kin_v, void *__restrict__ kout_v,
     const uint32_t *__restrict__ vin, uint32_t *__restrict__ vout, uint32_t n, int shift,
     int ib, const uint32_t *__restrict__ hist, uint64_t *__restrict__ status,
