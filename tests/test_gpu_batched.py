@@ -153,11 +153,12 @@ def test_one_set_batch_equals_single_build():
 
 
 @pytest.mark.parametrize("mode", ["default", "lookback", "counted"])
-@pytest.mark.parametrize("sort_config", [0, 4])
+@pytest.mark.parametrize("sort_config", [0, 2, 4])
 def test_many_small_sets(sort_config, mode):
     """600 sets of up to 300 particles, many sharing one radix tile's worth of
     positions with their neighbours but each sorted in place in tiles of its own;
-    8- and 9-bit digits (configs 0 and 4); the passes as the default chooses
+    8- and 9-bit digits (configs 0 and 4; config 2's look-back passes over packed
+    words run with a register bound and a spill); the passes as the default chooses
     them (look-back in a batch), with TB_SORT_LOOKBACK, and counted
     (TB_SORT_COUNTED: each set's tile offsets start again at its first tile)."""
     assert tb.tb_sort_configs()[4][0] == 9
@@ -267,8 +268,9 @@ def test_bad_offsets_reported():
     assert rc == tb.TB_OK
 
 
+@pytest.mark.parametrize("sort_config", [0, 2])
 @pytest.mark.parametrize("mode", ["default", "counted"])
-def test_set_index_bits(mode):
+def test_set_index_bits(mode, sort_config):
     """TB_SET_INDEX_BITS: with every set's size bounded (here exactly, 2^17 for
     the largest set of 100,003), the sort carries indices within the set in 17
     bits and packs earlier; the batch must be bit-identical to the unbounded
@@ -280,7 +282,8 @@ def test_set_index_bits(mode):
     pos, mass, offsets = plummer_batch(sizes, seed=41)
     bits = int(sizes.max() - 1).bit_length()
     counted = mode == "counted"
-    g = batch_build(pos, mass, offsets, 16, set_index_bits=bits, counted=counted)
+    g = batch_build(pos, mass, offsets, 16, set_index_bits=bits, counted=counted,
+                    sort_config=sort_config)
     r = batch_build(pos, mass, offsets, 16, counted=counted)
     compare_structure(g, r)
     assert np.array_equal(g["com"], r["com"]) and np.array_equal(g["quad"], r["quad"])
@@ -289,7 +292,8 @@ def test_set_index_bits(mode):
     assert rc == tb.TB_OK
 
     print(f"[set bits] {bits - 1} for a set of {int(sizes.max())}", flush=True)
-    bb = tb.BatchBuilder(pos.shape[0], len(sizes), 16, set_index_bits=bits - 1, counted=counted)
+    bb = tb.BatchBuilder(pos.shape[0], len(sizes), 16, "fp64", sort_config,
+                         set_index_bits=bits - 1, counted=counted)
     p, m = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
     bb.launch(p, m, torch.from_numpy(np.asarray(offsets, np.int64)).cuda())
     with pytest.raises(tb.TreeBuildError) as err:
