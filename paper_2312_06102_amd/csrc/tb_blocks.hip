@@ -276,20 +276,23 @@ __global__ __launch_bounds__(kCellThreads) void k_block_build(
     const int32_t *__restrict__ tile_set, const int64_t *__restrict__ set_off, int32_t nsets,
     const int64_t *__restrict__ lvl_off, const double *__restrict__ box,
     const float4 *__restrict__ sorted, BlockOut o, int32_t *__restrict__ status_word) {
-  // blk of [t0, t0 + W) before the batches, the leaf queue (first particles)
-  // during them
-  __shared__ __align__(16) unsigned char s_u[kSerial * sizeof(uint32_t)];
+  // blk of [t0, t0 + W) before the batches (W is at most two tiles), the leaf
+  // queue (batch offsets of first particles, below kSerial) during them
+  __shared__ __align__(16) unsigned char s_u[2 * kSerial];
   uint8_t *s_bw = s_u;
-  uint32_t *s_leaf = reinterpret_cast<uint32_t *>(s_u);
+  uint16_t *s_leaf = reinterpret_cast<uint16_t *>(s_u);
   __shared__ uint16_t s_st[kSerial];      // block starts in the tile (offsets from t0)
   __shared__ uint8_t s_sd[kSerial];       // their root depths
   __shared__ uint64_t s_key[kSerial + 1]; // keys of [bs - 1, be)
   __shared__ uint8_t s_dr[kSerial];       // root depth of each batch particle's block
   __shared__ uint8_t s_a[kSerial];        // A_x: the shallowest depth particle x starts
   __shared__ uint8_t s_d[kSerial];        // D_x: its leaf depth (eq. 2)
-  __shared__ uint8_t s_m[kSerial + TB_MAX_NLEAF];  // w_j (offset nl), then windowed maxima
   __shared__ __align__(8) uint8_t s_mask[kLevels + 1][kCellThreads];  // bit x: A_x <= d
   __shared__ uint16_t s_off[kLevels][kCellThreads];  // cells per depth of the earlier threads
+  // w_j (offset nl), then the windowed maxima: in s_off's space, since they are
+  // dead once every thread holds its particles' depths, before s_off is written
+  uint8_t *s_m = reinterpret_cast<uint8_t *>(&s_off[0][0]);
+  static_assert(sizeof(s_off) >= kSerial + TB_MAX_NLEAF, "the window maxima fit in s_off");
   __shared__ uint32_t s_tot[kLevels];      // cells per depth of the batch
   __shared__ uint32_t s_base[2][kLevels];  // first slot per depth: tile t (running), tile t+1
   __shared__ uint32_t s_cnt1[kLevels];     // cells per depth the batch starts in tile t
@@ -524,6 +527,7 @@ __global__ __launch_bounds__(kCellThreads) void k_block_build(
         A[j] = a;
         D[j] = dd;
       }
+      __syncthreads();  // s_m is dead: s_off, which holds it, is written next
       // depth masks: bit x of s_mask[d] set when particle x starts a cell at depth <= d
 #pragma unroll
       for (int d = 0; d <= kLevels; ++d) {
@@ -593,7 +597,7 @@ __global__ __launch_bounds__(kCellThreads) void k_block_build(
           continue;
         }
         if (d < dr && !put_upper(o, slot, d)) bad = true;
-        if (d == dl) s_leaf[atomicAdd(&s_nleaf, 1u)] = (uint32_t)x;
+        if (d == dl) s_leaf[atomicAdd(&s_nleaf, 1u)] = (uint16_t)x;
       }
     }
     __syncthreads();
