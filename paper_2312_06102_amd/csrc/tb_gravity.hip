@@ -28,7 +28,7 @@ constexpr int kWalkThreads = 256;
 constexpr int kWalkPpt = 4;                               // group particles per thread per pass
 constexpr int kWalkPass = kWalkThreads * kWalkPpt;        // group particles per pass
 constexpr int kStackCap = 4096;                           // cells waiting in LDS
-constexpr int kPartBatch = 512;                           // source particles staged at once
+constexpr int kPartBatch = 256;                           // source particles staged at once
 
 struct GravArgs {
   const uint64_t *key;
