@@ -29,6 +29,7 @@ constexpr int kWalkPpt = 4;                               // group particles per
 constexpr int kWalkPass = kWalkThreads * kWalkPpt;        // group particles per pass
 constexpr int kStackCap = 4096;                           // cells waiting in LDS
 constexpr int kPartBatch = 256;                           // source particles staged at once
+constexpr int kCellBatch = kWalkThreads / 2;              // accepted cells staged at once
 
 struct GravArgs {
   const uint64_t *key;
@@ -94,7 +95,10 @@ __device__ inline int block_excl(int v, int *s_w, int *total) {
   return off + (int)inc - v;
 }
 
-__global__ __launch_bounds__(kWalkThreads) void k_walk(
+// Four workgroups a CU: 38.9 KB of LDS each (the cells and particles of a
+// round are staged in halves), and registers held to four waves a SIMD
+// (128 VGPRs, no spill).
+__global__ __launch_bounds__(kWalkThreads, 4) void k_walk(
     GravArgs g, const int32_t *__restrict__ groups, const uint32_t *__restrict__ n_groups,
     double *__restrict__ acc, unsigned long long *__restrict__ stats,
     int32_t *__restrict__ status_word) {
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(
   __shared__ int32_t s_cells[kWalkThreads];   // accepted cells of the round
   __shared__ int32_t s_leaves[kWalkThreads];  // opened leaves of the round
   __shared__ int32_t s_lstart[kWalkThreads + 1];
-  __shared__ double s_cdat[kWalkThreads][10];  // com (abs) x y z, M, Q[6]
+  __shared__ double s_cdat[kCellBatch][10];   // com (abs) x y z, M, Q[6]
   __shared__ double s_part[kPartBatch][4];     // x y z m of staged source particles
   __shared__ int32_t s_pidx[kPartBatch];
   __shared__ int s_w[kWalkThreads / 64];
@@ -188,17 +192,6 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(
         if (threadIdx.x == 0) s_top = base + tot_p;
         __syncthreads();
         if (s_over) break;
-        // stage the accepted cells: absolute centre of mass, mass, quadrupole
-        if ((int)threadIdx.x < tot_c) {
-          const int64_t cc = s_cells[threadIdx.x];
-          double cen[3], l;
-          cell_centre(g, cc, cen, l);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) s_cdat[threadIdx.x][a] = cen[a] + g.com[4 * cc + a];
-          s_cdat[threadIdx.x][3] = g.com[4 * cc + 3];
-#pragma unroll
-          for (int q = 0; q < 6; ++q) s_cdat[threadIdx.x][4 + q] = g.quad[6 * cc + q];
-        }
         // particle ranges of the opened leaves
         int lc = 0;
         if ((int)threadIdx.x < tot_l) lc = g.count[s_leaves[threadIdx.x]];
@@ -211,36 +204,52 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(
           my_cells += (unsigned long long)tot_c;
           my_pairs += (unsigned long long)tot_pairs;
         }
-        // cell terms
+        // cell terms, the accepted cells staged kCellBatch at a time (absolute
+        // centre of mass, mass, quadrupole); each particle sums them in order
+        for (int c0 = 0; c0 < tot_c; c0 += kCellBatch) {
+          const int nc = min(kCellBatch, tot_c - c0);
+          __syncthreads();  // the previous batch is consumed
+          if ((int)threadIdx.x < nc) {
+            const int64_t cc = s_cells[c0 + threadIdx.x];
+            double cen[3], l;
+            cell_centre(g, cc, cen, l);
 #pragma unroll
-        for (int u = 0; u < kWalkPpt; ++u) {
-          if (si[u] < 0) continue;
-          for (int k = 0; k < tot_c; ++k) {
-            const double r0 = xi[u][0] - s_cdat[k][0];
-            const double r1 = xi[u][1] - s_cdat[k][1];
-            const double r2v = xi[u][2] - s_cdat[k][2];
-            const double M = s_cdat[k][3];
-            const double rr = r0 * r0 + r1 * r1 + r2v * r2v;
-            const double rinv = 1.0 / sqrt(rr);
-            const double rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
-            double t0 = -M * r0 * rinv3, t1 = -M * r1 * rinv3, t2 = -M * r2v * rinv3;
-            double phi = -M * rinv;
-            if (g.quad_on) {
-              const double *Q = &s_cdat[k][4];
-              const double q0 = Q[0] * r0 + Q[1] * r1 + Q[2] * r2v;
-              const double q1 = Q[1] * r0 + Q[3] * r1 + Q[4] * r2v;
-              const double q2 = Q[2] * r0 + Q[4] * r1 + Q[5] * r2v;
-              const double rqr = r0 * q0 + r1 * q1 + r2v * q2;
-              const double rinv5 = rinv3 * rinv2, rinv7 = rinv5 * rinv2;
-              t0 += q0 * rinv5 - 2.5 * rqr * r0 * rinv7;
-              t1 += q1 * rinv5 - 2.5 * rqr * r1 * rinv7;
-              t2 += q2 * rinv5 - 2.5 * rqr * r2v * rinv7;
-              phi -= 0.5 * rqr * rinv5;
+            for (int a = 0; a < 3; ++a) s_cdat[threadIdx.x][a] = cen[a] + g.com[4 * cc + a];
+            s_cdat[threadIdx.x][3] = g.com[4 * cc + 3];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s_cdat[threadIdx.x][4 + q] = g.quad[6 * cc + q];
+          }
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < kWalkPpt; ++u) {
+            if (si[u] < 0) continue;
+            for (int k = 0; k < nc; ++k) {
+              const double r0 = xi[u][0] - s_cdat[k][0];
+              const double r1 = xi[u][1] - s_cdat[k][1];
+              const double r2v = xi[u][2] - s_cdat[k][2];
+              const double M = s_cdat[k][3];
+              const double rr = r0 * r0 + r1 * r1 + r2v * r2v;
+              const double rinv = 1.0 / sqrt(rr);
+              const double rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+              double t0 = -M * r0 * rinv3, t1 = -M * r1 * rinv3, t2 = -M * r2v * rinv3;
+              double phi = -M * rinv;
+              if (g.quad_on) {
+                const double *Q = &s_cdat[k][4];
+                const double q0 = Q[0] * r0 + Q[1] * r1 + Q[2] * r2v;
+                const double q1 = Q[1] * r0 + Q[3] * r1 + Q[4] * r2v;
+                const double q2 = Q[2] * r0 + Q[4] * r1 + Q[5] * r2v;
+                const double rqr = r0 * q0 + r1 * q1 + r2v * q2;
+                const double rinv5 = rinv3 * rinv2, rinv7 = rinv5 * rinv2;
+                t0 += q0 * rinv5 - 2.5 * rqr * r0 * rinv7;
+                t1 += q1 * rinv5 - 2.5 * rqr * r1 * rinv7;
+                t2 += q2 * rinv5 - 2.5 * rqr * r2v * rinv7;
+                phi -= 0.5 * rqr * rinv5;
+              }
+              ai[u][0] += t0;
+              ai[u][1] += t1;
+              ai[u][2] += t2;
+              ai[u][3] += phi;
             }
-            ai[u][0] += t0;
-            ai[u][1] += t1;
-            ai[u][2] += t2;
-            ai[u][3] += phi;
           }
         }
         // particle terms, staged kPartBatch at a time
